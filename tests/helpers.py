@@ -1,0 +1,30 @@
+"""Test helpers shared by oracle pins and GPU parity tests (no method arithmetic)."""
+
+import numpy as np
+
+from workloads import splitmix64_stream
+
+
+def digest_weights(n: int) -> np.ndarray:
+    """Random odd 64-bit weights for the per-sample label digest."""
+    return splitmix64_stream(0xD16E57, 0, n) | np.uint64(1)
+
+
+def label_digests(labels_chunk: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """sum_v (label[v] + 1) * w[v] mod 2^64 for every column of a [n][c] chunk."""
+    x = (labels_chunk.astype(np.int64) + 1).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        return (x * w[:, None]).sum(axis=0, dtype=np.uint64)
+
+
+def min_id_labels(n: int, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Connected components of (range(n), {u_i, v_i}) via scipy, relabelled to min id."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    a = sp.coo_matrix((np.ones(len(u)), (np.asarray(u, np.int64), np.asarray(v, np.int64))),
+                      shape=(n, n))
+    _, comp = connected_components(a, directed=False)
+    mins = np.full(comp.max() + 1 if n else 0, n, dtype=np.int64)
+    np.minimum.at(mins, comp, np.arange(n))
+    return mins[comp].astype(np.int32)
