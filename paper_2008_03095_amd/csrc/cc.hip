@@ -1,0 +1,388 @@
+// Fused multi-simulation connected components and the component-size memo
+// (Section III-B, Algorithms 5-6; Section III-C).
+//
+// The paper labels R sampled subgraphs by min-label propagation, 8
+// simulations per AVX2 op, re-testing each edge's hash-liveness as it is
+// read.  Here a wavefront owns one vertex row of the vertex-major memo and
+// its 64 lanes x 4 columns are 256 simulations of that vertex (coalesced
+// 16-byte accesses).  Instead of iterating propagation sweeps to a fixed
+// point, components are built as a union-find forest whose roots are the
+// component minima:
+//
+//   k_hook     one streaming pass over the memo: M[v][q] = smallest live
+//              neighbour u < v of v in column q (a parent pointer), or -1
+//              when v has none (a root).  This is the first propagation step
+//              of Algorithm 5 restricted to smaller neighbours; it reads no
+//              label, so the pass is a pure write of n*Rs words.
+//   k_link     the remaining live edges (u < v, u not the hook of v) are
+//              merged by lock-free union: the larger root is linked under the
+//              smaller with compare-and-swap, so every root stays the minimum
+//              of its tree in any interleaving.
+//   k_compress every non-root entry is replaced by its root, and each root's
+//              -1 is decremented once per member: afterwards roots hold
+//              -|component| (the size memo) and members hold the label.
+//   k_gain0    mg_v = sum over columns of |C_q(v)| (Algorithm 5, int64).
+//
+// Work skipping.  Columns are sorted by X, so a 256-column tile spans a
+// narrow X interval; edge e can be live in the tile only if h_e >> k lies in
+// [X_lo >> k, X_hi >> k] where k = bitlen(T - 1).  The wavefront tests all
+// (up to 64) adjacent edges with one compare and one ballot per tile and runs
+// the per-column test only for the candidates.  k_hook records, per
+// (vertex, tile), whether any candidate exists (tmask: the tile may hold a
+// non-singleton column) and whether some column has two or more live smaller
+// neighbours (lmask: the tile needs k_link); the later kernels visit only
+// those tiles.
+#include "common.h"
+
+namespace infuse {
+
+struct TileCtx {
+  uint32_t q0;      // first column of this lane
+  uint32_t x[4];    // X of the lane's 4 columns
+  uint32_t klo, khi;
+  bool valid[4];
+};
+
+__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ inline void tile_setup(const MemoView& m, uint32_t t, uint32_t lane, uint32_t kshift,
+                                  TileCtx& tc, bool per_edge) {
+  tc.q0 = t * kTile + lane * kPerLane;
+  const uint4 x4 = *reinterpret_cast<const uint4*>(m.xs + tc.q0);
+  tc.x[0] = x4.x;
+  tc.x[1] = x4.y;
+  tc.x[2] = x4.z;
+  tc.x[3] = x4.w;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) tc.valid[i] = tc.q0 + i < m.R;
+  const uint32_t qlast = min(t * kTile + kTile - 1, m.R - 1);
+  const uint32_t xlo = uni(m.xs[t * kTile]);
+  const uint32_t xhi = uni(m.xs[qlast]);
+  if (!per_edge) {
+    tc.klo = (uint32_t)((uint64_t)xlo >> kshift);
+    tc.khi = (uint32_t)((uint64_t)xhi >> kshift);
+  } else {
+    tc.klo = xlo;  // shifted per edge
+    tc.khi = xhi;
+  }
+}
+
+// Can an edge with hash h and bit length k be live in the tile?
+__device__ inline bool cand_uniform(uint32_t h, uint32_t kshift, const TileCtx& tc) {
+  const uint32_t hk = (uint32_t)((uint64_t)h >> kshift);
+  return hk - tc.klo <= tc.khi - tc.klo;
+}
+__device__ inline bool cand_per_edge(uint32_t h, uint32_t k, const TileCtx& tc) {
+  const uint32_t hk = (uint32_t)((uint64_t)h >> k);
+  const uint32_t lo = (uint32_t)((uint64_t)tc.klo >> k), hi = (uint32_t)((uint64_t)tc.khi >> k);
+  return hk - lo <= hi - lo;
+}
+
+// Visits the candidate edges of v in the tile, calling f(u, h, tm1, small)
+// for each in slot order.  Returns whether any candidate exists.
+template <bool PER_EDGE, bool SMALL_ONLY, typename F>
+__device__ inline bool for_candidates(const GraphView& g, const MemoView& m, uint32_t v,
+                                      uint32_t beg, uint32_t end, uint32_t split, uint32_t lane,
+                                      bool inreg, uint32_t rcol, uint32_t rh, uint32_t rtm1,
+                                      const TileCtx& tc, F&& f) {
+  bool any = false;
+  const uint32_t last = SMALL_ONLY ? split : end;
+  if (m.never_live) return false;
+  if (inreg) {
+    const uint32_t j = beg + lane;
+    bool c = j < last;
+    if (PER_EDGE) c = c && cand_per_edge(rh, bitlen32(rtm1), tc);
+    else c = c && cand_uniform(rh, m.kshift, tc);
+    uint64_t mask = __ballot(c);
+    any = mask != 0;
+    while (mask) {
+      const int b = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const uint32_t u = __builtin_amdgcn_readlane(rcol, b);
+      const uint32_t h = __builtin_amdgcn_readlane(rh, b);
+      const uint32_t tt = PER_EDGE ? __builtin_amdgcn_readlane(rtm1, b) : m.tm1;
+      f(u, h, tt, beg + (uint32_t)b < split);
+    }
+  } else {
+    for (uint32_t base = beg; base < last; base += kWave) {
+      const uint32_t j = base + lane;
+      uint32_t col = kInvalid, h = 0, tm1 = 0;
+      bool c = false;
+      if (j < last) {
+        const uint2 e = m.edges[j];
+        col = e.x;
+        h = e.y;
+        if (PER_EDGE) {
+          tm1 = g.tm1[j];
+          c = cand_per_edge(h, bitlen32(tm1), tc);
+        } else {
+          c = cand_uniform(h, m.kshift, tc);
+        }
+      }
+      uint64_t mask = __ballot(c);
+      any = any || mask != 0;
+      while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint32_t u = __builtin_amdgcn_readlane(col, b);
+        const uint32_t hh = __builtin_amdgcn_readlane(h, b);
+        const uint32_t tt = PER_EDGE ? __builtin_amdgcn_readlane(tm1, b) : m.tm1;
+        f(u, hh, tt, base + (uint32_t)b < split);
+      }
+    }
+  }
+  return any;
+}
+
+struct WaveJob {
+  uint32_t v, t0, t1;
+  bool ok;
+};
+
+__device__ inline WaveJob wave_job(uint32_t n, uint32_t ntiles, uint32_t chunk, uint32_t wpv) {
+  WaveJob w;
+  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  w.v = uni((uint32_t)(wid / wpv));
+  const uint32_t c = uni((uint32_t)(wid % wpv));
+  w.ok = w.v < n;
+  w.t0 = c * chunk;
+  w.t1 = min(w.t0 + chunk, ntiles);
+  return w;
+}
+
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_hook(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
+  const WaveJob job = wave_job(g.n, m.ntiles, chunk, wpv);
+  if (!job.ok) return;
+  const uint32_t lane = threadIdx.x & 63, v = job.v;
+  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
+  const bool inreg = end - beg <= (uint32_t)kWave;
+  uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
+  if (inreg && beg + lane < end) {
+    const uint2 e = m.edges[beg + lane];
+    rcol = e.x;
+    rh = e.y;
+    if (PER_EDGE) rtm1 = g.tm1[beg + lane];
+  }
+  int32_t* row = m.M + (uint64_t)v * m.Rs;
+  uint32_t tbits = 0, lbits = 0;
+  for (uint32_t t = job.t0; t < job.t1; ++t) {
+    TileCtx tc;
+    tile_setup(m, t, lane, m.kshift, tc, PER_EDGE);
+    int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    uint32_t cnt[4] = {0, 0, 0, 0};
+    // candidates among all neighbours mark the tile; smaller ones hook
+    const bool any = for_candidates<PER_EDGE, false>(
+        g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
+        [&](uint32_t u, uint32_t h, uint32_t tt, bool small) {
+          if (!small) return;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
+            cnt[i] += live ? 1u : 0u;
+            mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
+          }
+        });
+    int4 out;
+    out.x = cnt[0] ? mn[0] : -1;
+    out.y = cnt[1] ? mn[1] : -1;
+    out.z = cnt[2] ? mn[2] : -1;
+    out.w = cnt[3] ? mn[3] : -1;
+    *reinterpret_cast<int4*>(row + tc.q0) = out;
+    const bool need = cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1;
+    const uint64_t nb = __ballot(need);
+    tbits |= (any ? 1u : 0u) << (t - job.t0);
+    lbits |= (nb ? 1u : 0u) << (t - job.t0);
+  }
+  if (lane == 0) {
+    const uint32_t word = job.t0 >> 5, sh = job.t0 & 31;
+    if (tbits) atomicOr(&m.tmask[(uint64_t)v * m.mwords + word], tbits << sh);
+    if (lbits) atomicOr(&m.lmask[(uint64_t)v * m.mwords + word], lbits << sh);
+  }
+}
+
+__device__ inline uint32_t find_root(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
+  while (true) {
+    const int32_t p = __hip_atomic_load(&M[(uint64_t)x * Rs + q], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    if (p < 0) return x;
+    x = (uint32_t)p;
+  }
+}
+
+// Union of a and b in column q.  Roots hold -1 during linking; linking the
+// larger root under the smaller keeps every root its tree's minimum.
+__device__ inline void unite(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
+  while (true) {
+    a = find_root(M, Rs, a, q);
+    b = find_root(M, Rs, b, q);
+    if (a == b) return;
+    if (a < b) {
+      const uint32_t t = a;
+      a = b;
+      b = t;
+    }
+    int32_t expected = -1;
+    if (__hip_atomic_compare_exchange_strong(&M[(uint64_t)a * Rs + q], &expected, (int32_t)b,
+                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return;
+  }
+}
+
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
+  const WaveJob job = wave_job(g.n, m.ntiles, chunk, wpv);
+  if (!job.ok) return;
+  const uint32_t lane = threadIdx.x & 63, v = job.v;
+  const uint32_t word = uni(m.lmask[(uint64_t)v * m.mwords + (job.t0 >> 5)]);
+  const uint32_t mybits = (word >> (job.t0 & 31)) & (job.t1 - job.t0 >= 32 ? ~0u : ((1u << (job.t1 - job.t0)) - 1));
+  if (!mybits) return;
+  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
+  const bool inreg = end - beg <= (uint32_t)kWave;
+  uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
+  if (inreg && beg + lane < end) {
+    const uint2 e = m.edges[beg + lane];
+    rcol = e.x;
+    rh = e.y;
+    if (PER_EDGE) rtm1 = g.tm1[beg + lane];
+  }
+  for (uint32_t t = job.t0; t < job.t1; ++t) {
+    if (!((mybits >> (t - job.t0)) & 1u)) continue;
+    TileCtx tc;
+    tile_setup(m, t, lane, m.kshift, tc, PER_EDGE);
+    int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
+                                   [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
+#pragma unroll
+                                     for (int i = 0; i < 4; ++i) {
+                                       const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
+                                       mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
+                                     }
+                                   });
+    for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
+                                   [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
+#pragma unroll
+                                     for (int i = 0; i < 4; ++i) {
+                                       const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
+                                       if (live && (int32_t)u != mn[i])
+                                         unite(m.M, m.Rs, v, u, tc.q0 + i);
+                                     }
+                                   });
+  }
+}
+
+__global__ void __launch_bounds__(256) k_compress(MemoView m, uint32_t chunk, uint32_t wpv) {
+  const WaveJob job = wave_job(m.n, m.ntiles, chunk, wpv);
+  if (!job.ok) return;
+  const uint32_t lane = threadIdx.x & 63, v = job.v;
+  const uint32_t word = uni(m.tmask[(uint64_t)v * m.mwords + (job.t0 >> 5)]);
+  const uint32_t mybits = (word >> (job.t0 & 31)) & (job.t1 - job.t0 >= 32 ? ~0u : ((1u << (job.t1 - job.t0)) - 1));
+  if (!mybits) return;
+  int32_t* row = m.M + (uint64_t)v * m.Rs;
+  for (uint32_t t = job.t0; t < job.t1; ++t) {
+    if (!((mybits >> (t - job.t0)) & 1u)) continue;
+    const uint32_t q0 = t * kTile + lane * kPerLane;
+    const int4 cur = *reinterpret_cast<const int4*>(row + q0);
+    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t q = q0 + i;
+      const int32_t val = vals[i];
+      if (q >= m.R || val < 0) continue;
+      uint32_t c = (uint32_t)val;
+      while (true) {
+        const int32_t p = m.M[(uint64_t)c * m.Rs + q];
+        if (p < 0) break;
+        c = (uint32_t)p;
+      }
+      if (c != (uint32_t)val) row[q] = (int32_t)c;
+      atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+    }
+  }
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// One wavefront per vertex: mg_v = sum_q |C_q(v)|.
+__global__ void __launch_bounds__(256) k_gain0(MemoView m) {
+  const uint32_t v = uni((uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  if (v >= m.n) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const int32_t* row = m.M + (uint64_t)v * m.Rs;
+  uint64_t sum = 0;
+  for (uint32_t t = 0; t < m.ntiles; ++t) {
+    const uint32_t q0 = t * kTile + lane * kPerLane;
+    const uint32_t bit = (uni(m.tmask[(uint64_t)v * m.mwords + (t >> 5)]) >> (t & 31)) & 1u;
+    if (!bit) {
+      sum += (uint64_t)min(max((int32_t)m.R - (int32_t)q0, 0), 4);
+      continue;
+    }
+    const int4 cur = *reinterpret_cast<const int4*>(row + q0);
+    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t q = q0 + i;
+      if (q >= m.R) continue;
+      const int32_t val = vals[i];
+      sum += (uint64_t)(val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q]);
+    }
+  }
+  sum = wave_sum_u64(sum);
+  if (lane == 0) m.g0[v] = (int64_t)sum;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---- launchers -----------------------------------------------------------
+
+static uint32_t waves_per_vertex(const MemoView& m, uint32_t chunk) {
+  return (m.ntiles + chunk - 1) / chunk;
+}
+
+static dim3 grid_for(uint32_t n, uint32_t wpv) {
+  const uint64_t waves = (uint64_t)n * wpv;
+  return dim3((uint32_t)((waves + 3) / 4));
+}
+
+void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st) {
+  if (!count) return;
+  uint64_t blocks = (count + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, st, p, count, value);
+}
+
+void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
+  const uint32_t wpv = waves_per_vertex(m, chunk);
+  if (g.tm1)
+    hipLaunchKernelGGL(k_hook<true>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+  else
+    hipLaunchKernelGGL(k_hook<false>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+}
+
+void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
+  const uint32_t wpv = waves_per_vertex(m, chunk);
+  if (g.tm1)
+    hipLaunchKernelGGL(k_link<true>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+  else
+    hipLaunchKernelGGL(k_link<false>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+}
+
+void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {
+  const uint32_t wpv = waves_per_vertex(m, chunk);
+  hipLaunchKernelGGL(k_compress, grid_for(m.n, wpv), dim3(256), 0, st, m, chunk, wpv);
+}
+
+void launch_gain0(const MemoView& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_gain0, dim3((m.n + 3) / 4), dim3(256), 0, st, m);
+}
+
+}  // namespace infuse

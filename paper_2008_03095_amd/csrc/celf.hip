@@ -1,0 +1,332 @@
+// CELF on the memo (Algorithm 7), on the device.
+//
+// Queue state: key[v] = gain << B | (2^B - 1 - v) (B = bitlen(n), so larger
+// key = larger gain, then smaller id; 0 marks a selected vertex) and iter[v]
+// (|S| when key[v] was computed).  Covered components: one bit per
+// (label, column), set for every column's component of every seed.
+//
+// One CELF step commits exactly one seed, in three launches:
+//   k_celf_topw  top-(W+1) keys of unselected vertices (per-wave, per-block,
+//                then a last-block merge);
+//   k_celf_eval  gains of the W candidates for the current S (blocks over
+//                (candidate, 1024-column chunk)); the last block sets
+//                key/iter of the candidates and commits the best if its key
+//                beats the (W+1)-th key; otherwise it asks for
+//   k_celf_bulk  re-evaluation of every stale vertex whose key exceeds the
+//                best fresh key k*; the last block commits the best key.
+// Why this is lazy greedy: gains only fall as S grows (coverage is
+// submodular), so a stale key bounds its vertex's gain.  A committed key is
+// fresh and larger than every stale key, hence it is the lowest-id maximiser
+// of the exact gains, the same vertex plain greedy and the sequential CELF
+// queue pick.
+#include "common.h"
+
+namespace infuse {
+
+__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ inline uint64_t wave_max_u64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t y = __shfl_xor(x, off);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+__device__ inline uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__device__ inline uint32_t key_id(const CelfView& c, uint64_t k) {
+  return (uint32_t)((1ull << c.B) - 1 - (k & ((1ull << c.B) - 1)));
+}
+__device__ inline uint64_t key_gain(const CelfView& c, uint64_t k) { return k >> c.B; }
+__device__ inline uint64_t make_key(const CelfView& c, uint64_t gain, uint32_t v) {
+  return (gain << c.B) | ((1ull << c.B) - 1 - v);
+}
+
+// Per-lane partial gain of vertex u over tile t: sum over the lane's columns
+// of |C_q(u)| when the component is not covered.
+__device__ inline uint64_t eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane) {
+  const MemoView& m = c.m;
+  const uint32_t q0 = t * kTile + lane * kPerLane;
+  const uint32_t bit = (uni(m.tmask[(uint64_t)u * m.mwords + (t >> 5)]) >> (t & 31)) & 1u;
+  if (!bit) return (uint64_t)min(max((int32_t)m.R - (int32_t)q0, 0), 4);
+  const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)u * m.Rs + q0);
+  const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t q = q0 + i;
+    if (q >= m.R) continue;
+    const int32_t val = vals[i];
+    if (val == -1) {  // u alone: u is unselected, so its component is uncovered
+      sum += 1;
+      continue;
+    }
+    const uint32_t root = val < 0 ? u : (uint32_t)val;
+    const int32_t size = val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q];
+    const uint32_t w = c.cov[(uint64_t)root * c.cwords + (q >> 5)];
+    sum += ((w >> (q & 31)) & 1u) ? 0 : (uint64_t)size;
+  }
+  return sum;
+}
+
+// Commit the vertex of key k as seed number st->s (whole block).
+__device__ void commit_block(const CelfView& c, uint64_t k) {
+  const MemoView& m = c.m;
+  const uint32_t id = key_id(c, k);
+  for (uint32_t q = threadIdx.x; q < m.R; q += blockDim.x) {
+    const int32_t val = m.M[(uint64_t)id * m.Rs + q];
+    const uint32_t root = val < 0 ? id : (uint32_t)val;
+    atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t s = __hip_atomic_load(&c.st->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.seeds[s] = id;
+    c.marginal[s] = (int64_t)key_gain(c, k);
+    c.key[id] = 0;
+    __threadfence();
+    c.st->s = s + 1;
+  }
+}
+
+constexpr int kTopPerLane = 16;  // keys per lane in k_celf_topw
+
+// Largest key below `last` among this lane's keys, then over the wave.
+__device__ inline uint64_t next_below(const uint64_t* kk, int cnt, uint64_t last) {
+  uint64_t best = 0;
+  for (int i = 0; i < cnt; ++i) {
+    const uint64_t k = kk[i];
+    best = (k < last && k > best) ? k : best;
+  }
+  return wave_max_u64(best);
+}
+
+__global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
+  if (c.st->s >= c.K) return;
+  __shared__ uint64_t wl[4][65];
+  __shared__ uint64_t red[4];
+  __shared__ uint32_t last_block;
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t W1 = c.W + 1;
+  const uint64_t base = ((uint64_t)blockIdx.x * 4 + wv) * (64 * kTopPerLane);
+  uint64_t kk[kTopPerLane];
+#pragma unroll
+  for (int i = 0; i < kTopPerLane; ++i) {
+    const uint64_t v = base + (uint64_t)i * 64 + lane;
+    kk[i] = v < c.m.n ? c.key[v] : 0;
+  }
+  uint64_t last = ~0ull;
+  for (uint32_t it = 0; it < W1; ++it) {
+    last = next_below(kk, kTopPerLane, last);
+    if (lane == 0) wl[wv][it] = last;
+  }
+  __syncthreads();
+  if (wv == 0) {  // merge the 4 wave lists
+    uint64_t mk[5];
+    int cnt = 0;
+    for (uint32_t i = lane; i < 4 * W1; i += 64) mk[cnt++] = wl[i / W1][i % W1];
+    uint64_t l2 = ~0ull;
+    for (uint32_t it = 0; it < W1; ++it) {
+      l2 = next_below(mk, cnt, l2);
+      if (lane == 0) c.lists[(uint64_t)blockIdx.x * W1 + it] = l2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last_block = atomicAdd(&c.st->ticket1, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last_block) return;
+  __threadfence();
+  // final merge over gridDim.x * W1 keys: W1 rounds of "largest key below
+  // the previous one" with a block reduction
+  const uint64_t total = (uint64_t)gridDim.x * W1;
+  uint64_t prev = ~0ull;
+  for (uint32_t it = 0; it < W1; ++it) {
+    uint64_t best = 0;
+    for (uint64_t i = threadIdx.x; i < total; i += blockDim.x) {
+      const uint64_t k = __hip_atomic_load(&c.lists[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      best = (k < prev && k > best) ? k : best;
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) red[wv] = best;
+    __syncthreads();
+    uint64_t b = red[0];
+    for (int i = 1; i < 4; ++i) b = red[i] > b ? red[i] : b;
+    __syncthreads();
+    prev = b;
+    if (threadIdx.x == 0) {
+      if (it < c.W) {
+        c.cand[it] = b ? key_id(c, b) : kInvalid;
+        c.candgain[it] = 0;
+      } else {
+        c.st->next_key = b;
+      }
+    }
+    if (b == 0 && threadIdx.x == 0) {
+      // fewer than W+1 unselected vertices: pad
+      for (uint32_t j = it; j < c.W; ++j) {
+        c.cand[j] = kInvalid;
+        c.candgain[j] = 0;
+      }
+      c.st->next_key = 0;
+    }
+    if (b == 0) break;
+  }
+  if (threadIdx.x == 0) {
+    uint32_t nc = 0;
+    for (uint32_t j = 0; j < c.W; ++j) nc += c.cand[j] != kInvalid ? 1u : 0u;
+    c.st->ncand = nc;
+    c.st->ticket1 = 0;
+    __threadfence();
+  }
+}
+
+constexpr uint32_t kEvalCols = 1024;  // columns per evaluation block (4 waves x 1 tile)
+
+__global__ void __launch_bounds__(256) k_celf_eval(CelfView c, uint32_t nchunks) {
+  if (c.st->s >= c.K) return;
+  __shared__ uint64_t red[4];
+  __shared__ uint32_t last_block;
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t w = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
+  const uint32_t s = c.st->s;
+  if (w < c.W) {
+    const uint32_t u = c.cand[w];
+    if (u != kInvalid && c.iter[u] != s) {
+      const uint32_t t = ch * (kEvalCols / kTile) + wv;
+      uint64_t part = t < c.m.ntiles ? eval_tile(c, u, t, lane) : 0;
+      part = wave_sum_u64(part);
+      if (lane == 0) red[wv] = part;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint64_t tot = red[0] + red[1] + red[2] + red[3];
+        if (tot) atomicAdd((unsigned long long*)&c.candgain[w], (unsigned long long)tot);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last_block = atomicAdd(&c.st->ticket2, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last_block) return;
+  __threadfence();
+  __shared__ uint64_t best_sh;
+  __shared__ uint32_t bulk_sh;
+  if (threadIdx.x == 0) {
+    uint64_t best = 0;
+    uint64_t ev = 0;
+    for (uint32_t j = 0; j < c.W; ++j) {
+      const uint32_t u = c.cand[j];
+      if (u == kInvalid) continue;
+      if (c.iter[u] != s) {
+        const uint64_t g = __hip_atomic_load(&c.candgain[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c.key[u] = make_key(c, g, u);
+        c.iter[u] = s;
+        ++ev;
+      }
+      const uint64_t k = c.key[u];
+      best = k > best ? k : best;
+    }
+    c.st->evals += ev;
+    c.st->ticket2 = 0;
+    // decisions travel through LDS: the block's L1 may hold the state line
+    bulk_sh = best > c.st->next_key ? 0u : 1u;
+    c.st->need_bulk = bulk_sh;
+    if (bulk_sh) {
+      c.st->kstar = best;
+      c.st->bulk_best = best;
+    }
+    best_sh = best;
+    __threadfence();
+  }
+  __syncthreads();
+  if (!bulk_sh) commit_block(c, best_sh);
+}
+
+__global__ void __launch_bounds__(256) k_celf_bulk(CelfView c) {
+  if (c.st->s >= c.K || !c.st->need_bulk) return;
+  __shared__ uint32_t last_block;
+  __shared__ uint64_t evs[4];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t s = c.st->s;
+  const uint64_t kstar = c.st->kstar;
+  const uint32_t nw = gridDim.x * 4;
+  uint64_t ev = 0, best = 0;
+  for (uint32_t v = blockIdx.x * 4 + wv; v < c.m.n; v += nw) {
+    const uint64_t k = c.key[v];
+    if (k <= kstar) continue;
+    uint64_t nk = k;
+    if (c.iter[v] != s) {
+      uint64_t sum = 0;
+      for (uint32_t t = 0; t < c.m.ntiles; ++t) sum += eval_tile(c, v, t, lane);
+      sum = wave_sum_u64(sum);
+      nk = make_key(c, sum, v);
+      if (lane == 0) {
+        c.key[v] = nk;
+        c.iter[v] = s;
+      }
+      ++ev;
+    }
+    best = nk > best ? nk : best;
+  }
+  if (lane == 0) {
+    if (best) atomicMax((unsigned long long*)&c.st->bulk_best, (unsigned long long)best);
+    evs[wv] = ev;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t e = evs[0] + evs[1] + evs[2] + evs[3];
+    if (e) atomicAdd((unsigned long long*)&c.st->evals, (unsigned long long)e);
+    __threadfence();
+    last_block = atomicAdd(&c.st->ticket3, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last_block) return;
+  __threadfence();
+  __shared__ uint64_t k_sh;
+  if (threadIdx.x == 0) {
+    k_sh = __hip_atomic_load(&c.st->bulk_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.st->ticket3 = 0;
+    c.st->need_bulk = 0;
+  }
+  __syncthreads();
+  commit_block(c, k_sh);
+}
+
+__global__ void k_celf_init(CelfView c) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < c.m.n) {
+    c.key[i] = make_key(c, (uint64_t)c.m.g0[i], (uint32_t)i);
+    c.iter[i] = 0;
+  }
+  if (i == 0) {
+    CelfState z = {};
+    *c.st = z;
+  }
+}
+
+// ---- launchers -------------------------------------------------------------
+
+uint32_t celf_topw_blocks(uint32_t n) { return (n + 4 * 64 * kTopPerLane - 1) / (4 * 64 * kTopPerLane); }
+
+void launch_celf_init(const CelfView& c, hipStream_t st) {
+  hipLaunchKernelGGL(k_celf_init, dim3((c.m.n + 255) / 256), dim3(256), 0, st, c);
+}
+
+void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_celf_topw, dim3(celf_topw_blocks(c.m.n)), dim3(256), 0, st, c);
+  const uint32_t nchunks = (c.m.Rs + kEvalCols - 1) / kEvalCols;
+  hipLaunchKernelGGL(k_celf_eval, dim3(c.W * nchunks), dim3(256), 0, st, c, nchunks);
+  hipLaunchKernelGGL(k_celf_bulk, dim3(bulk_blocks), dim3(256), 0, st, c);
+}
+
+
+}  // namespace infuse

@@ -1,0 +1,114 @@
+// Internal definitions shared by the gfx950 kernels and the host runtime.
+//
+// Memo layout (vertex-major, Section III-C).  One int32 word per (vertex,
+// simulation) pair, rows of Rs = roundup(R, 256) words:
+//   M[v][q] <  0 : v is the smallest vertex of its component in simulation
+//                  column q, and -M[v][q] is the component size;
+//   M[v][q] >= 0 : M[v][q] is the smallest vertex of v's component.
+// So the label array and the size array of the paper (both n x R, sizes
+// indexed by label, rows of non-labels unused) share one allocation: the
+// size array's used rows are exactly the label array's redundant entries.
+//
+// Column order.  Column q holds simulation inv[q]; columns are sorted by
+// ascending X_r.  Since (h ^ X) < T <= 2^k forces X >> k == h >> k, an edge
+// can only be live in the few columns whose X shares its top 32-k bits:
+// a 256-column tile is skipped for an edge with one range test.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace infuse {
+
+constexpr int kWave = 64;
+constexpr int kTile = 256;        // columns per tile: 64 lanes x 4 columns
+constexpr int kPerLane = 4;
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+
+// MurmurHash3 32-bit finaliser (Appleby, public domain).
+__host__ __device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Key of the unordered pair {u, v} (Eq. 1 hashes min || max): min * n + max
+// in 64 bits, folded to 32 bits as lo ^ fmix32(hi) (identity below 2^32).
+__host__ __device__ inline uint32_t edge_key32(uint32_t u, uint32_t v, uint32_t n) {
+  uint64_t lo = u < v ? u : v, hi = u < v ? v : u;
+  uint64_t key = lo * (uint64_t)n + hi;
+  return (uint32_t)key ^ fmix32((uint32_t)(key >> 32));
+}
+
+// Bit length of t (0 for t = 0): the smallest k with t < 2^k.  With
+// tm1 = T - 1 a live edge needs (h ^ X) <= tm1, hence (h ^ X) >> k == 0.
+__host__ __device__ inline uint32_t bitlen32(uint32_t t) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return t ? 32u - (uint32_t)__clz((int)t) : 0u;
+#else
+  return t ? 32u - (uint32_t)__builtin_clz(t) : 0u;
+#endif
+}
+
+// Per-graph device view.  Offsets are 32-bit (nnz < 2^32).
+struct GraphView {
+  uint32_t n;
+  uint32_t nnz;
+  const uint32_t* row_ptr;  // [n+1]
+  const uint32_t* col;      // [nnz] ascending per row
+  const uint32_t* split;    // [n]  first slot of row v whose neighbour is > v
+  const uint32_t* tm1;      // [nnz] per-slot T-1, or nullptr (uniform p)
+};
+
+// Per-memo device view.
+struct MemoView {
+  uint32_t n;
+  uint32_t R;
+  uint32_t Rs;          // row stride, multiple of kTile
+  uint32_t ntiles;      // Rs / kTile
+  uint32_t mwords;      // 32-bit mask words per vertex: ceil(ntiles / 32)
+  uint32_t tm1;         // uniform mode: T - 1
+  uint32_t kshift;      // uniform mode: bitlen(tm1)
+  uint32_t never_live;  // uniform mode with T = 0
+  const uint2* edges;   // [nnz] {neighbour, h_e}
+  const uint32_t* xs;   // [Rs] X of column q (ascending for q < R)
+  int32_t* M;           // [n][Rs]
+  uint32_t* tmask;      // [n][mwords]  tile may hold a non-singleton column
+  uint32_t* lmask;      // [n][mwords]  tile needs the link pass
+  int64_t* g0;          // [n]
+};
+
+struct CelfState {
+  uint32_t s;          // |S|
+  uint32_t need_bulk;
+  uint32_t ticket1, ticket2, ticket3;
+  uint32_t ncand;
+  uint64_t next_key;   // (W+1)-th largest key when the candidates were chosen
+  uint64_t kstar;
+  uint64_t bulk_best;
+  uint64_t evals;
+};
+
+struct CelfView {
+  MemoView m;
+  uint32_t K;
+  uint32_t W;          // candidates per round (<= 64)
+  uint32_t B;          // id bits of the key
+  uint32_t cwords;     // Rs / 32
+  uint64_t* key;       // [n]
+  uint32_t* iter;      // [n]
+  uint32_t* cov;       // [n][cwords]
+  uint64_t* lists;     // [topw blocks][W+1]
+  uint32_t* cand;      // [W]
+  uint64_t* candgain;  // [W]
+  uint32_t* seeds;     // [K]
+  int64_t* marginal;   // [K]
+  CelfState* st;
+};
+
+inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace infuse

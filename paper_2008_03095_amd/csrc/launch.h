@@ -1,0 +1,35 @@
+// Host-side launchers of the gfx950 kernels (one definition per .hip file).
+#pragma once
+
+#include "common.h"
+
+namespace infuse {
+
+// sampler.hip
+void launch_edge_hash(const GraphView& g, uint32_t seed, uint2* edges, hipStream_t st);
+uint32_t x_sort_scratch_elems(uint32_t R);
+void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, uint32_t* xs,
+                   uint32_t* inv, uint32_t* pos, hipStream_t st);
+
+// cc.hip
+void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st);
+void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_compress(const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_gain0(const MemoView& m, hipStream_t st);
+
+// celf.hip
+uint32_t celf_topw_blocks(uint32_t n);
+void launch_celf_init(const CelfView& c, hipStream_t st);
+void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
+
+// query.hip
+uint32_t sigma_pair_max();
+void launch_sigma_pair(const MemoView& m, const uint32_t* S, uint32_t len, unsigned long long* out,
+                       hipStream_t st);
+void launch_sigma_bitmap(const MemoView& m, const uint32_t* S, uint32_t len, uint32_t* bm,
+                         uint32_t cwords, unsigned long long* out, hipStream_t st);
+void launch_export(const MemoView& m, const uint32_t* pos, uint32_t r0, uint32_t cnt, uint32_t v0,
+                   uint32_t nv, int mode, int32_t* out, hipStream_t st);
+
+}  // namespace infuse

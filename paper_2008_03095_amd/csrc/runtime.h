@@ -1,0 +1,128 @@
+// Host-side objects behind the opaque handles of include/infuse.h.
+#pragma once
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "../../include/infuse.h"
+#include "common.h"
+
+struct im_graph;
+
+namespace infuse {
+
+struct PendingEvent {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+// One memo: sampler state and the n x Rs label/size words for (p, R, s).
+struct Memo {
+  uint64_t tkey = 0;  // threshold floor(p * 2^32) (0 for per-slot p graphs)
+  uint32_t R = 0, seed = 0;
+  uint32_t Rs = 0, ntiles = 0, mwords = 0;
+  uint32_t tm1 = 0, kshift = 0, never_live = 0;
+  void* base = nullptr;  // one allocation holding every array below
+  size_t bytes = 0;
+  uint2* edges = nullptr;
+  uint32_t* xs = nullptr;
+  uint32_t* inv = nullptr;
+  uint32_t* pos = nullptr;
+  uint64_t* scratch = nullptr;
+  int32_t* M = nullptr;
+  uint32_t* tmask = nullptr;
+  uint32_t* lmask = nullptr;
+  int64_t* g0 = nullptr;
+  uint64_t last_use = 0;
+  int pins = 0;
+  hipEvent_t ready_ev = nullptr;  // recorded after construction
+  MemoView view(const im_graph* g) const;
+};
+
+struct CelfBuffers {
+  void* base = nullptr;
+  size_t bytes = 0;
+  CelfView v;
+};
+
+im_status fail(im_status s, const char* fmt, ...);
+im_status ctx_alloc(im_ctx* c, size_t bytes, void** out);
+void ctx_free(im_ctx* c, void* p);
+void memo_destroy(im_graph* g, Memo* m);
+uint64_t memo_bytes(const im_graph* g, uint32_t R);
+Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed);
+im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out);
+im_status memo_acquire(im_graph* g, Memo** out);
+void memo_release(im_graph* g, Memo* m);
+im_status check_params(const im_graph* g, double p, uint32_t R);
+uint32_t key_bits(uint32_t n);
+im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuffers* cb);
+void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st);
+im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
+                       int64_t* marginal, int64_t* cover, uint64_t* evals);
+im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out);
+im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
+                        void** scratch, unsigned long long** dev_out);
+
+// Records HIP events around a launch on `st` when profiling is on.
+class KTimer {
+ public:
+  KTimer(im_ctx* c, const char* name, hipStream_t st);
+  ~KTimer();
+
+ private:
+  im_ctx* c_;
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+}  // namespace infuse
+
+struct im_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  im_allocator alloc = {nullptr, nullptr, nullptr};
+  bool has_alloc = false;
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  uint64_t use_clock = 0;
+  uint64_t evictions = 0;
+  im_tuning tune = {};
+  bool profiling = false;
+  std::vector<infuse::PendingEvent> pending;
+  std::map<std::string, std::pair<uint64_t, double>> kstats;
+  std::vector<im_graph*> graphs;
+  std::unordered_map<void*, size_t> sizes;
+  std::recursive_mutex mu;
+};
+
+struct im_graph {
+  im_ctx* ctx = nullptr;
+  uint32_t n = 0;
+  uint64_t nnz_in = 0;  // slots given by the caller
+  uint32_t nnz = 0;     // slots on the device (per-slot p: T = 0 slots dropped)
+  bool per_edge = false;
+  void* gbuf = nullptr;
+  uint32_t* row_ptr = nullptr;
+  uint32_t* col = nullptr;
+  uint32_t* split = nullptr;
+  uint32_t* tm1 = nullptr;
+  double p = 0.0;
+  uint32_t R = 0, seed = 0;
+  bool params_set = false;
+  std::vector<infuse::Memo*> memos;
+  // events: [0] build start, [1] sampler ready, [2] components done,
+  // [3] gains done, [4] CELF start, [5] CELF end
+  hipEvent_t ev[6] = {};
+  bool timed_build = false;
+  double phase_ms[4] = {0, 0, 0, 0};
+  uint64_t last_evals = 0;
+  infuse::GraphView view() const;
+};

@@ -1,0 +1,857 @@
+// Host runtime behind the C ABI of include/infuse.h: contexts, graph upload
+// and validation, memo construction and caching, CELF selection, sigma
+// queries, label export and per-kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/infuse.h"
+#include "launch.h"
+#include "runtime.h"
+
+using namespace infuse;
+
+infuse::GraphView im_graph::view() const {
+  infuse::GraphView v;
+  v.n = n;
+  v.nnz = nnz;
+  v.row_ptr = row_ptr;
+  v.col = col;
+  v.split = split;
+  v.tm1 = per_edge ? tm1 : nullptr;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+namespace infuse {
+im_status fail(im_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+}  // namespace infuse
+
+extern "C" const char* im_last_error(void) { return g_err.c_str(); }
+extern "C" const char* im_version(void) { return "infuse-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// allocation (budgeted, with LRU eviction of unpinned memos)
+// ---------------------------------------------------------------------------
+
+namespace infuse {
+
+static void raw_free(im_ctx* c, void* p) {
+  if (!p) return;
+  if (c->has_alloc) c->alloc.free(c->alloc.user, p, (void*)c->stream);
+  else (void)hipFree(p);
+}
+
+static void* raw_alloc(im_ctx* c, size_t bytes) {
+  void* p = nullptr;
+  if (c->has_alloc) {
+    p = c->alloc.alloc(c->alloc.user, bytes, (void*)c->stream);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  return p;
+}
+
+static bool evict_one(im_ctx* c) {
+  Memo* victim = nullptr;
+  im_graph* owner = nullptr;
+  for (im_graph* g : c->graphs)
+    for (Memo* m : g->memos)
+      if (m->pins == 0 && (!victim || m->last_use < victim->last_use)) {
+        victim = m;
+        owner = g;
+      }
+  if (!victim) return false;
+  memo_destroy(owner, victim);
+  c->evictions++;
+  return true;
+}
+
+im_status ctx_alloc(im_ctx* c, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~(size_t)255;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (c->budget && bytes > c->budget)
+    return fail(IM_ERR_BUDGET, "request of %zu bytes exceeds the context budget of %llu bytes", bytes,
+                (unsigned long long)c->budget);
+  while (c->budget && c->in_use + bytes > c->budget)
+    if (!evict_one(c))
+      return fail(IM_ERR_BUDGET, "budget exhausted: %llu in use, %zu requested, budget %llu",
+                  (unsigned long long)c->in_use, bytes, (unsigned long long)c->budget);
+  void* p = raw_alloc(c, bytes);
+  while (!p && evict_one(c)) p = raw_alloc(c, bytes);
+  if (!p) return fail(IM_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
+  c->in_use += bytes;
+  c->sizes[p] = bytes;
+  *out = p;
+  return IM_OK;
+}
+
+void ctx_free(im_ctx* c, void* p) {
+  if (!p) return;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->sizes.find(p);
+  if (it != c->sizes.end()) {
+    c->in_use -= it->second;
+    c->sizes.erase(it);
+  }
+  raw_free(c, p);
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+
+KTimer::KTimer(im_ctx* c, const char* name, hipStream_t st) : c_(c), name_(name), st_(st) {
+  if (!c_->profiling) return;
+  (void)hipEventCreate(&a_);
+  (void)hipEventCreate(&b_);
+  (void)hipEventRecord(a_, st_);
+}
+
+KTimer::~KTimer() {
+  if (!c_->profiling) return;
+  (void)hipEventRecord(b_, st_);
+  std::lock_guard<std::recursive_mutex> lk(c_->mu);
+  c_->pending.push_back({name_, a_, b_});
+}
+
+static void resolve_pending(im_ctx* c) {
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  for (auto& p : c->pending) {
+    (void)hipEventSynchronize(p.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& s = c->kstats[p.name];
+      s.first += 1;
+      s.second += ms;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// memo
+// ---------------------------------------------------------------------------
+
+static uint64_t thr_of(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return 1ull << 32;
+  return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+MemoView Memo::view(const im_graph* g) const {
+  MemoView v;
+  v.n = g->n;
+  v.R = R;
+  v.Rs = Rs;
+  v.ntiles = ntiles;
+  v.mwords = mwords;
+  v.tm1 = tm1;
+  v.kshift = kshift;
+  v.never_live = never_live;
+  v.edges = edges;
+  v.xs = xs;
+  v.M = M;
+  v.tmask = tmask;
+  v.lmask = lmask;
+  v.g0 = g0;
+  return v;
+}
+
+void memo_destroy(im_graph* g, Memo* m) {
+  auto& v = g->memos;
+  v.erase(std::remove(v.begin(), v.end(), m), v.end());
+  if (m->ready_ev) (void)hipEventDestroy(m->ready_ev);
+  ctx_free(g->ctx, m->base);
+  delete m;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+uint64_t memo_bytes(const im_graph* g, uint32_t R) {
+  const uint32_t Rs = round_up(R, kTile);
+  const uint32_t ntiles = Rs / kTile;
+  const uint32_t mwords = (ntiles + 31) / 32;
+  size_t b = 0;
+  b += align256((size_t)g->nnz * sizeof(uint2));
+  b += align256((size_t)Rs * 4) * 2 + align256((size_t)R * 4);
+  b += align256((size_t)x_sort_scratch_elems(R) * 8);
+  b += align256((size_t)g->n * Rs * 4);
+  b += align256((size_t)g->n * mwords * 4) * 2;
+  b += align256((size_t)g->n * 8);
+  return b;
+}
+
+Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
+  const uint64_t pb = g->per_edge ? 0 : thr_of(p);
+  for (Memo* m : g->memos)
+    if (m->tkey == pb && m->R == R && m->seed == seed) return m;
+  return nullptr;
+}
+
+// Allocates the memo and enqueues its construction on `st`.
+im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out) {
+  im_ctx* c = g->ctx;
+  Memo* m = new Memo();
+  m->tkey = g->per_edge ? 0 : thr_of(p);
+  m->R = R;
+  m->seed = seed;
+  m->Rs = round_up(R, kTile);
+  m->ntiles = m->Rs / kTile;
+  m->mwords = (m->ntiles + 31) / 32;
+  const uint64_t T = thr_of(p);
+  m->never_live = (!g->per_edge && T == 0) ? 1u : 0u;
+  m->tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
+  m->kshift = bitlen32(m->tm1);
+  m->bytes = memo_bytes(g, R);
+  void* base = nullptr;
+  im_status s = ctx_alloc(c, m->bytes, &base);
+  if (s != IM_OK) {
+    delete m;
+    return s;
+  }
+  m->base = base;
+  char* p8 = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* r = p8;
+    p8 += align256(bytes);
+    return r;
+  };
+  m->edges = reinterpret_cast<uint2*>(take((size_t)g->nnz * sizeof(uint2)));
+  m->xs = reinterpret_cast<uint32_t*>(take((size_t)m->Rs * 4));
+  m->inv = reinterpret_cast<uint32_t*>(take((size_t)m->Rs * 4));
+  m->pos = reinterpret_cast<uint32_t*>(take((size_t)R * 4));
+  m->scratch = reinterpret_cast<uint64_t*>(take((size_t)x_sort_scratch_elems(R) * 8));
+  m->M = reinterpret_cast<int32_t*>(take((size_t)g->n * m->Rs * 4));
+  m->tmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
+  m->lmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
+  m->g0 = reinterpret_cast<int64_t*>(take((size_t)g->n * 8));
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    g->memos.push_back(m);
+    m->last_use = ++c->use_clock;
+  }
+
+  const MemoView mv = m->view(g);
+  const uint32_t chunk_tiles = std::max(1u, std::min(32u, c->tune.cc_chunk / kTile));
+  const bool timed = g->ev[0] != nullptr && st == c->stream;
+  if (timed) (void)hipEventRecord(g->ev[0], st);
+  {
+    KTimer t(c, "edge_hash", st);
+    launch_edge_hash(g->view(), seed, m->edges, st);
+  }
+  {
+    KTimer t(c, "x_sort", st);
+    launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
+  }
+  launch_fill_u32(m->tmask, (uint64_t)g->n * m->mwords, 0u, st);
+  launch_fill_u32(m->lmask, (uint64_t)g->n * m->mwords, 0u, st);
+  if (timed) (void)hipEventRecord(g->ev[1], st);
+  {
+    KTimer t(c, "hook", st);
+    launch_hook(g->view(), mv, chunk_tiles, st);
+  }
+  {
+    KTimer t(c, "link", st);
+    launch_link(g->view(), mv, chunk_tiles, st);
+  }
+  {
+    KTimer t(c, "compress", st);
+    launch_compress(mv, chunk_tiles, st);
+  }
+  if (timed) (void)hipEventRecord(g->ev[2], st);
+  {
+    KTimer t(c, "gain0", st);
+    launch_gain0(mv, st);
+  }
+  if (timed) (void)hipEventRecord(g->ev[3], st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    memo_destroy(g, m);
+    return fail(IM_ERR_DEVICE, "memo kernels failed to launch: %s", hipGetErrorString(e));
+  }
+  if (hipEventCreateWithFlags(&m->ready_ev, hipEventDisableTiming) == hipSuccess)
+    (void)hipEventRecord(m->ready_ev, st);
+  g->timed_build = timed;
+  *out = m;
+  return IM_OK;
+}
+
+// Finds or builds the memo of the graph's current parameters and pins it.
+im_status memo_acquire(im_graph* g, Memo** out) {
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  im_ctx* c = g->ctx;
+  Memo* m = memo_find(g, g->p, g->R, g->seed);
+  if (!m) {
+    im_status s = memo_build(g, g->p, g->R, g->seed, c->stream, &m);
+    if (s != IM_OK) return s;
+  } else {
+    g->timed_build = false;
+    if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+  }
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  m->pins++;
+  m->last_use = ++c->use_clock;
+  *out = m;
+  return IM_OK;
+}
+
+void memo_release(im_graph* g, Memo* m) {
+  std::lock_guard<std::recursive_mutex> lk(g->ctx->mu);
+  m->pins--;
+}
+
+
+// ---------------------------------------------------------------------------
+// CELF selection on a memo
+// ---------------------------------------------------------------------------
+
+uint32_t key_bits(uint32_t n) { return bitlen32(n); }
+
+im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuffers* cb) {
+  im_ctx* c = g->ctx;
+  const uint32_t n = g->n;
+  const uint32_t cwords = m->Rs / 32;
+  const uint32_t tb = celf_topw_blocks(n);
+  size_t b = 0;
+  b += align256((size_t)n * 8);
+  b += align256((size_t)n * 4);
+  b += align256((size_t)n * cwords * 4);
+  b += align256((size_t)tb * (W + 1) * 8);
+  b += align256((size_t)W * 4) + align256((size_t)W * 8);
+  b += align256((size_t)std::max(K, 1u) * 4) + align256((size_t)std::max(K, 1u) * 8);
+  b += align256(sizeof(CelfState));
+  void* base = nullptr;
+  im_status s = ctx_alloc(c, b, &base);
+  if (s != IM_OK) return s;
+  cb->base = base;
+  cb->bytes = b;
+  char* p8 = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* r = p8;
+    p8 += align256(bytes);
+    return r;
+  };
+  CelfView& v = cb->v;
+  v.m = m->view(g);
+  v.K = K;
+  v.W = W;
+  v.B = key_bits(n);
+  v.cwords = cwords;
+  v.key = reinterpret_cast<uint64_t*>(take((size_t)n * 8));
+  v.iter = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
+  v.cov = reinterpret_cast<uint32_t*>(take((size_t)n * cwords * 4));
+  v.lists = reinterpret_cast<uint64_t*>(take((size_t)tb * (W + 1) * 8));
+  v.cand = reinterpret_cast<uint32_t*>(take((size_t)W * 4));
+  v.candgain = reinterpret_cast<uint64_t*>(take((size_t)W * 8));
+  v.seeds = reinterpret_cast<uint32_t*>(take((size_t)std::max(K, 1u) * 4));
+  v.marginal = reinterpret_cast<int64_t*>(take((size_t)std::max(K, 1u) * 8));
+  v.st = reinterpret_cast<CelfState*>(take(sizeof(CelfState)));
+  return IM_OK;
+}
+
+void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+  const CelfView& v = cb->v;
+  launch_fill_u32(v.cov, (uint64_t)v.m.n * v.cwords, 0u, st);
+  launch_celf_init(v, st);
+  const uint32_t bulk_blocks = std::max(1u, std::min(2048u, (v.m.n + 3) / 4));
+  for (uint32_t k = 0; k < v.K; ++k) {
+    KTimer t(c, "celf_step", st);
+    launch_celf_step(v, bulk_blocks, st);
+  }
+}
+
+im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
+                       int64_t* marginal, int64_t* cover, uint64_t* evals) {
+  const CelfView& v = cb->v;
+  CelfState hs;
+  if (hipMemcpyAsync(seeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(marginal, v.marginal, (size_t)v.K * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&hs, v.st, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    return fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
+  }
+  if (hs.s != v.K) return fail(IM_ERR_DEVICE, "CELF committed %u of %u seeds", hs.s, v.K);
+  int64_t tot = 0;
+  for (uint32_t i = 0; i < v.K; ++i) tot += marginal[i];
+  if (cover) *cover = tot;
+  if (evals) *evals = hs.evals;
+  (void)c;
+  return IM_OK;
+}
+
+}  // namespace infuse
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator* alloc,
+                                   uint64_t hbm_budget, im_ctx** out) {
+  if (!out) return fail(IM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return fail(IM_ERR_DEVICE, "device %d not available (%d devices)", device, count);
+  if (hipSetDevice(device) != hipSuccess) return fail(IM_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(IM_ERR_INVALID_ARG, "allocator needs both alloc and free");
+  im_ctx* c = new im_ctx();
+  c->device = device;
+  c->budget = hbm_budget;
+  if (alloc) {
+    c->alloc = *alloc;
+    c->has_alloc = true;
+  }
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(IM_ERR_DEVICE, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  c->tune.cc_chunk = 2048;
+  c->tune.celf_width = 16;
+  c->tune.use_graphs = 0;
+  *out = c;
+  return IM_OK;
+}
+
+extern "C" void im_ctx_destroy(im_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  resolve_pending(c);
+  while (!c->graphs.empty()) im_graph_free(c->graphs.back());
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" uint64_t im_ctx_bytes_in_use(const im_ctx* c) { return c ? c->in_use : 0; }
+
+extern "C" im_status im_set_tuning(im_ctx* c, const im_tuning* t) {
+  if (!c || !t) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  if (t->cc_chunk) {
+    const uint32_t tiles = t->cc_chunk / kTile;
+    if (t->cc_chunk % kTile || tiles == 0 || tiles > 32 || (tiles & (tiles - 1)))
+      return fail(IM_ERR_INVALID_ARG, "cc_chunk must be 256 * 2^k with 2^k <= 32");
+    c->tune.cc_chunk = t->cc_chunk;
+  }
+  if (t->celf_width) {
+    if (t->celf_width > 64) return fail(IM_ERR_INVALID_ARG, "celf_width must be <= 64");
+    c->tune.celf_width = t->celf_width;
+  }
+  if (t->use_graphs) c->tune.use_graphs = t->use_graphs == 1 ? 1 : 0;
+  return IM_OK;
+}
+
+extern "C" im_status im_get_tuning(const im_ctx* c, im_tuning* t) {
+  if (!c || !t) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  *t = c->tune;
+  return IM_OK;
+}
+
+extern "C" im_status im_set_profiling(im_ctx* c, int enabled) {
+  if (!c) return fail(IM_ERR_INVALID_ARG, "NULL context");
+  c->profiling = enabled != 0;
+  return IM_OK;
+}
+
+extern "C" im_status im_reset_kernel_stats(im_ctx* c) {
+  if (!c) return fail(IM_ERR_INVALID_ARG, "NULL context");
+  resolve_pending(c);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  c->kstats.clear();
+  return IM_OK;
+}
+
+extern "C" im_status im_kernel_stats(im_ctx* c, const char* kernel, uint64_t* launches,
+                                     double* total_ms) {
+  if (!c || !kernel) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  resolve_pending(c);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = c->kstats.find(kernel);
+  if (launches) *launches = it == c->kstats.end() ? 0 : it->second.first;
+  if (total_ms) *total_ms = it == c->kstats.end() ? 0.0 : it->second.second;
+  return IM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph
+// ---------------------------------------------------------------------------
+
+static im_status validate_csr(uint32_t n, uint64_t nnz, const uint64_t* rp, const uint32_t* col,
+                              const double* p_slot) {
+  if (n == 0) return fail(IM_ERR_INVALID_GRAPH, "n must be >= 1");
+  if (n >= (1u << 31)) return fail(IM_ERR_INVALID_GRAPH, "n must be < 2^31");
+  if (nnz >= (1ull << 32)) return fail(IM_ERR_INVALID_GRAPH, "nnz must be < 2^32");
+  if (!rp || (nnz && !col)) return fail(IM_ERR_INVALID_GRAPH, "NULL CSR array");
+  if (rp[0] != 0 || rp[n] != nnz) return fail(IM_ERR_INVALID_GRAPH, "row_ptr must start at 0 and end at nnz");
+  for (uint32_t u = 0; u < n; ++u) {
+    if (rp[u + 1] < rp[u]) return fail(IM_ERR_INVALID_GRAPH, "row_ptr decreases at row %u", u);
+    for (uint64_t j = rp[u]; j < rp[u + 1]; ++j) {
+      const uint32_t v = col[j];
+      if (v >= n) return fail(IM_ERR_INVALID_GRAPH, "neighbour id %u >= n in row %u", v, u);
+      if (v == u) return fail(IM_ERR_INVALID_GRAPH, "self-loop at vertex %u", u);
+      if (j > rp[u] && col[j - 1] >= v)
+        return fail(IM_ERR_INVALID_GRAPH, "row %u is not strictly increasing", u);
+      if (p_slot && (!(p_slot[j] >= 0.0) || !(p_slot[j] <= 1.0)))
+        return fail(IM_ERR_INVALID_GRAPH, "p_slot[%llu] outside [0,1]", (unsigned long long)j);
+      // symmetric: (v, u) must exist with the same probability
+      const uint32_t* b = col + rp[v];
+      const uint32_t* e = col + rp[v + 1];
+      const uint32_t* f = std::lower_bound(b, e, u);
+      if (f == e || *f != u) return fail(IM_ERR_INVALID_GRAPH, "edge (%u,%u) has no reverse", u, v);
+      if (p_slot && p_slot[rp[v] + (f - b)] != p_slot[j])
+        return fail(IM_ERR_INVALID_GRAPH, "p_slot differs between (%u,%u) and its reverse", u, v);
+    }
+  }
+  return IM_OK;
+}
+
+extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                       const uint32_t* col_idx, const double* p_slot, im_graph** out) {
+  if (!c || !out) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  im_status s = validate_csr(n, nnz, row_ptr, col_idx, p_slot);
+  if (s != IM_OK) return s;
+  // device CSR: with per-slot p, slots with T = 0 are never live and are
+  // dropped; the rest keep T - 1 per slot
+  std::vector<uint32_t> rp(n + 1), col, split(n), tm1;
+  col.reserve(nnz);
+  if (p_slot) tm1.reserve(nnz);
+  for (uint32_t u = 0; u < n; ++u) {
+    rp[u] = (uint32_t)col.size();
+    for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+      if (p_slot) {
+        const uint64_t T = thr_of(p_slot[j]);
+        if (T == 0) continue;
+        tm1.push_back((uint32_t)(T - 1));
+      }
+      col.push_back(col_idx[j]);
+    }
+    split[u] = (uint32_t)(std::lower_bound(col.begin() + rp[u], col.end(), u) - col.begin());
+  }
+  rp[n] = (uint32_t)col.size();
+  im_graph* g = new im_graph();
+  g->ctx = c;
+  g->n = n;
+  g->nnz_in = nnz;
+  g->nnz = rp[n];
+  g->per_edge = p_slot != nullptr;
+  const size_t b_rp = align256((size_t)(n + 1) * 4), b_col = align256((size_t)g->nnz * 4 + 4);
+  const size_t b_split = align256((size_t)n * 4), b_tm1 = p_slot ? align256((size_t)g->nnz * 4 + 4) : 0;
+  void* base = nullptr;
+  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1, &base);
+  if (s != IM_OK) {
+    delete g;
+    return s;
+  }
+  g->gbuf = base;
+  char* p8 = static_cast<char*>(base);
+  g->row_ptr = reinterpret_cast<uint32_t*>(p8);
+  g->col = reinterpret_cast<uint32_t*>(p8 + b_rp);
+  g->split = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col);
+  g->tm1 = p_slot ? reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split) : nullptr;
+  hipError_t e = hipMemcpyAsync(g->row_ptr, rp.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && g->nnz)
+    e = hipMemcpyAsync(g->col, col.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->split, split.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && p_slot && g->nnz)
+    e = hipMemcpyAsync(g->tm1, tm1.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    ctx_free(c, base);
+    delete g;
+    return fail(IM_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(e));
+  }
+  for (int i = 0; i < 6; ++i) (void)hipEventCreate(&g->ev[i]);
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->graphs.push_back(g);
+  }
+  *out = g;
+  return IM_OK;
+}
+
+extern "C" void im_graph_free(im_graph* g) {
+  if (!g) return;
+  im_ctx* c = g->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  while (!g->memos.empty()) memo_destroy(g, g->memos.back());
+  ctx_free(c, g->gbuf);
+  for (int i = 0; i < 6; ++i)
+    if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+  auto& v = c->graphs;
+  v.erase(std::remove(v.begin(), v.end(), g), v.end());
+  delete g;
+}
+
+extern "C" uint32_t im_graph_n(const im_graph* g) { return g ? g->n : 0; }
+extern "C" uint64_t im_graph_nnz(const im_graph* g) { return g ? g->nnz_in : 0; }
+
+im_status infuse::check_params(const im_graph* g, double p, uint32_t R) {
+  if (R == 0) return fail(IM_ERR_INVALID_ARG, "R must be >= 1");
+  if (R > (1u << 24)) return fail(IM_ERR_INVALID_ARG, "R must be <= 2^24");
+  if (!(p >= 0.0) || !(p <= 1.0)) return fail(IM_ERR_INVALID_ARG, "p must be in [0,1]");
+  // keys pack gain (<= n*R) above bitlen(n) id bits in 64 bits
+  const unsigned __int128 lim = (unsigned __int128)g->n * R << key_bits(g->n);
+  if (lim >> 64) return fail(IM_ERR_INVALID_ARG, "n*R too large for 64-bit CELF keys");
+  const unsigned __int128 words = (unsigned __int128)g->n * round_up(R, kTile);
+  if (words >> 40) return fail(IM_ERR_INVALID_ARG, "memo larger than 4 TiB");
+  return IM_OK;
+}
+
+extern "C" im_status im_set_params(im_graph* g, double p, uint32_t R, uint32_t hash_seed) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  im_status s = check_params(g, p, R);
+  if (s != IM_OK) return s;
+  g->p = p;
+  g->R = R;
+  g->seed = hash_seed;
+  g->params_set = true;
+  return IM_OK;
+}
+
+// Phase times of the last construction, once its events completed.
+static void read_build_phases(im_graph* g) {
+  if (!g->timed_build) return;
+  float a = 0, b = 0, c = 0;
+  (void)hipEventElapsedTime(&a, g->ev[0], g->ev[1]);
+  (void)hipEventElapsedTime(&b, g->ev[1], g->ev[2]);
+  (void)hipEventElapsedTime(&c, g->ev[2], g->ev[3]);
+  g->phase_ms[0] = a;
+  g->phase_ms[1] = b;
+  g->phase_ms[2] = c;
+  g->timed_build = false;
+}
+
+extern "C" im_status im_build_memo(im_graph* g) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  Memo* m = nullptr;
+  im_status s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  hipError_t e = hipStreamSynchronize(g->ctx->stream);
+  if (e == hipSuccess) read_build_phases(g);
+  memo_release(g, m);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo construction failed: %s", hipGetErrorString(e));
+  return IM_OK;
+}
+
+extern "C" im_status im_drop_memo(im_graph* g) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  (void)hipStreamSynchronize(g->ctx->stream);
+  std::lock_guard<std::recursive_mutex> lk(g->ctx->mu);
+  std::vector<Memo*> keep;
+  for (Memo* m : std::vector<Memo*>(g->memos))
+    if (m->pins == 0) memo_destroy(g, m);
+  return IM_OK;
+}
+
+extern "C" im_status im_select_seeds(im_graph* g, uint32_t K, uint32_t* seeds, int64_t* marginal,
+                                     int64_t* cover_count) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  if (K > g->n) return fail(IM_ERR_INVALID_ARG, "K = %u exceeds n = %u", K, g->n);
+  if (K && (!seeds || !marginal)) return fail(IM_ERR_INVALID_ARG, "NULL output array");
+  if (K == 0) {
+    if (cover_count) *cover_count = 0;
+    return IM_OK;
+  }
+  im_ctx* c = g->ctx;
+  Memo* m = nullptr;
+  im_status s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  CelfBuffers cb;
+  s = celf_alloc(g, m, K, c->tune.celf_width, &cb);
+  if (s != IM_OK) {
+    memo_release(g, m);
+    return s;
+  }
+  (void)hipEventRecord(g->ev[4], c->stream);
+  celf_enqueue(c, &cb, c->stream);
+  (void)hipEventRecord(g->ev[5], c->stream);
+  std::vector<uint32_t> hs(K);
+  std::vector<int64_t> hm(K);
+  int64_t cover = 0;
+  uint64_t evals = 0;
+  s = celf_collect(c, &cb, c->stream, hs.data(), hm.data(), &cover, &evals);
+  if (s == IM_OK) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, g->ev[4], g->ev[5]);
+    g->phase_ms[3] = ms;
+    read_build_phases(g);
+    g->last_evals = evals;
+    std::memcpy(seeds, hs.data(), (size_t)K * 4);
+    std::memcpy(marginal, hm.data(), (size_t)K * 8);
+    if (cover_count) *cover_count = cover;
+  }
+  ctx_free(c, cb.base);
+  memo_release(g, m);
+  return s;
+}
+
+// Dedups S; returns IM_ERR_INVALID_ARG for an id >= n.
+im_status infuse::normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out) {
+  out->assign(S, S + len);
+  for (uint32_t x : *out)
+    if (x >= g->n) return fail(IM_ERR_INVALID_ARG, "seed id %u >= n = %u", x, g->n);
+  std::sort(out->begin(), out->end());
+  out->erase(std::unique(out->begin(), out->end()), out->end());
+  return IM_OK;
+}
+
+im_status infuse::sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
+                        void** scratch, unsigned long long** dev_out) {
+  im_ctx* c = g->ctx;
+  const uint32_t len = (uint32_t)S.size();
+  const bool pair = len <= sigma_pair_max();
+  const uint32_t cwords = m->Rs / 32;
+  size_t b = align256(8) + align256((size_t)len * 4);
+  if (!pair) b += align256((size_t)g->n * cwords * 4);
+  void* base = nullptr;
+  im_status s = ctx_alloc(c, b, &base);
+  if (s != IM_OK) return s;
+  char* p8 = static_cast<char*>(base);
+  auto* out = reinterpret_cast<unsigned long long*>(p8);
+  auto* dS = reinterpret_cast<uint32_t*>(p8 + align256(8));
+  uint32_t* bm = pair ? nullptr : reinterpret_cast<uint32_t*>(p8 + align256(8) + align256((size_t)len * 4));
+  launch_fill_u32(reinterpret_cast<uint32_t*>(out), 2, 0u, st);
+  if (len) (void)hipMemcpyAsync(dS, S.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
+  const MemoView mv = m->view(g);
+  {
+    KTimer t(c, "sigma", st);
+    if (pair) {
+      if (len) launch_sigma_pair(mv, dS, len, out, st);
+    } else {
+      launch_fill_u32(bm, (uint64_t)g->n * cwords, 0u, st);
+      launch_sigma_bitmap(mv, dS, len, bm, cwords, out, st);
+    }
+  }
+  *scratch = base;
+  *dev_out = out;
+  return IM_OK;
+}
+
+extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t s_len, int64_t* count,
+                                       double* sigma) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  if (s_len && !S) return fail(IM_ERR_INVALID_ARG, "NULL seed array");
+  std::vector<uint32_t> set;
+  im_status s = normalize_set(g, S, s_len, &set);
+  if (s != IM_OK) return s;
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  if (set.empty()) {
+    if (count) *count = 0;
+    if (sigma) *sigma = 0.0;
+    return IM_OK;
+  }
+  im_ctx* c = g->ctx;
+  Memo* m = nullptr;
+  s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  void* scratch = nullptr;
+  unsigned long long* dout = nullptr;
+  s = sigma_enqueue(g, m, set, c->stream, &scratch, &dout);
+  if (s == IM_OK) {
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, dout, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      s = fail(IM_ERR_DEVICE, "sigma failed: %s", hipGetErrorString(e));
+    } else {
+      if (count) *count = (int64_t)h;
+      if (sigma) *sigma = (double)h / (double)g->R;
+    }
+    ctx_free(c, scratch);
+  }
+  memo_release(g, m);
+  return s;
+}
+
+static im_status export_range(im_graph* g, int32_t* host, uint32_t first, uint32_t cnt, int mode) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  if ((uint64_t)first + cnt > g->R) return fail(IM_ERR_INVALID_ARG, "sample range exceeds R");
+  if (cnt == 0) return IM_OK;
+  if (!host) return fail(IM_ERR_INVALID_ARG, "NULL output");
+  im_ctx* c = g->ctx;
+  Memo* m = nullptr;
+  im_status s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  const uint64_t max_words = 64ull << 20;  // staging chunk: 256 MiB
+  uint32_t vchunk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->n, max_words / cnt));
+  void* buf = nullptr;
+  s = ctx_alloc(c, (size_t)vchunk * cnt * 4, &buf);
+  if (s != IM_OK) {
+    memo_release(g, m);
+    return s;
+  }
+  const MemoView mv = m->view(g);
+  for (uint32_t v0 = 0; v0 < g->n && s == IM_OK; v0 += vchunk) {
+    const uint32_t nv = std::min(vchunk, g->n - v0);
+    launch_export(mv, m->pos, first, cnt, v0, nv, mode, static_cast<int32_t*>(buf), c->stream);
+    hipError_t e = hipMemcpyAsync(host + (uint64_t)v0 * cnt, buf, (size_t)nv * cnt * 4,
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) s = fail(IM_ERR_DEVICE, "export failed: %s", hipGetErrorString(e));
+  }
+  ctx_free(c, buf);
+  memo_release(g, m);
+  return s;
+}
+
+extern "C" im_status im_copy_labels(im_graph* g, int32_t* host, uint32_t first, uint32_t n_samples) {
+  return export_range(g, host, first, n_samples, 0);
+}
+
+extern "C" im_status im_copy_sizes(im_graph* g, int32_t* host, uint32_t first, uint32_t n_samples) {
+  return export_range(g, host, first, n_samples, 1);
+}
+
+extern "C" im_status im_copy_gains0(im_graph* g, int64_t* host) {
+  if (!g || !host) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  Memo* m = nullptr;
+  im_status s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  hipError_t e = hipMemcpyAsync(host, m->g0, (size_t)g->n * 8, hipMemcpyDeviceToHost, g->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->ctx->stream);
+  memo_release(g, m);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+  return IM_OK;
+}
+
+extern "C" im_status im_last_phase_ms(const im_graph* g, double* ms4) {
+  if (!g || !ms4) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 4; ++i) ms4[i] = g->phase_ms[i];
+  return IM_OK;
+}
+
+extern "C" uint64_t im_last_celf_evals(const im_graph* g) { return g ? g->last_evals : 0; }

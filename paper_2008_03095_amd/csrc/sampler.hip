@@ -1,0 +1,115 @@
+// Hash edge sampler set-up (Section III-A, Eq. 1-2).
+//
+// k_edge_hash   h_e = fmix32(s ^ key32(u, v)) for every CSR slot, stored
+//               beside the neighbour id ({v, h_e}, 8 bytes per slot), since
+//               the paper precomputes the m hashes once instead of hashing
+//               during traversal.
+// k_x_sort_*    X_r = fmix32(s + r) for r < R and the column order: columns
+//               hold the simulations sorted by X (ascending).  X values are
+//               distinct (fmix32 is a bijection and s + r takes R distinct
+//               values), so the order is unique.
+#include "common.h"
+
+namespace infuse {
+
+__global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, uint2* edges) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t u = wave; u < g.n; u += nwaves) {
+    const uint32_t beg = g.row_ptr[u], end = g.row_ptr[u + 1];
+    for (uint32_t j = beg + lane; j < end; j += kWave) {
+      const uint32_t v = g.col[j];
+      edges[j] = make_uint2(v, fmix32(seed ^ edge_key32(u, v, g.n)));
+    }
+  }
+}
+
+constexpr int kSortChunk = 4096;  // elements sorted per block in LDS
+
+// Sorts chunk blockIdx.x of the (X_r, r) pairs; pads with all-ones keys.
+__global__ void __launch_bounds__(1024) k_x_sort_chunk(uint32_t seed, uint32_t R, uint64_t* out) {
+  __shared__ uint64_t a[kSortChunk];
+  const uint32_t base = blockIdx.x * kSortChunk;
+  for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+    const uint32_t r = base + i;
+    a[i] = r < R ? ((uint64_t)fmix32(seed + r) << 32) | r : ~0ull;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= (uint32_t)kSortChunk; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const bool asc = (i & k) == 0;
+          const uint64_t x = a[i], y = a[ixj];
+          if ((x > y) == asc) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) out[base + i] = a[i];
+}
+
+// Global rank of each element = its rank in its own sorted chunk plus the
+// number of smaller X in every other chunk (binary search).
+__global__ void __launch_bounds__(256) k_x_sort_merge(const uint64_t* sorted, uint32_t R,
+                                                      uint32_t nchunks, uint32_t* xs, uint32_t* inv,
+                                                      uint32_t* pos) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t padded = nchunks * kSortChunk;
+  if (i >= padded) return;
+  const uint64_t key = sorted[i];
+  if (key == ~0ull) return;
+  const uint32_t x = (uint32_t)(key >> 32), r = (uint32_t)key;
+  const uint32_t c = i / kSortChunk;
+  uint32_t rank = i - c * kSortChunk;
+  for (uint32_t d = 0; d < nchunks; ++d) {
+    if (d == c) continue;
+    const uint64_t* s = sorted + (uint64_t)d * kSortChunk;
+    uint32_t lo = 0, hi = kSortChunk;  // pads (all ones) sort last and are never smaller
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if ((s[mid] >> 32) < x && s[mid] != ~0ull) lo = mid + 1; else hi = mid;
+    }
+    rank += lo;
+  }
+  xs[rank] = x;
+  inv[rank] = r;
+  pos[r] = rank;
+}
+
+__global__ void k_x_pad(uint32_t R, uint32_t Rs, uint32_t* xs, uint32_t* inv) {
+  const uint32_t q = R + blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < Rs) {
+    xs[q] = kInvalid;
+    inv[q] = kInvalid;
+  }
+}
+
+void launch_edge_hash(const GraphView& g, uint32_t seed, uint2* edges, hipStream_t st) {
+  uint32_t blocks = (g.n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(256), 0, st, g, seed, edges);
+}
+
+uint32_t x_sort_scratch_elems(uint32_t R) {
+  return (R + kSortChunk - 1) / kSortChunk * kSortChunk;
+}
+
+void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, uint32_t* xs,
+                   uint32_t* inv, uint32_t* pos, hipStream_t st) {
+  const uint32_t nchunks = (R + kSortChunk - 1) / kSortChunk;
+  hipLaunchKernelGGL(k_x_sort_chunk, dim3(nchunks), dim3(1024), 0, st, seed, R, scratch);
+  const uint32_t padded = nchunks * kSortChunk;
+  hipLaunchKernelGGL(k_x_sort_merge, dim3((padded + 255) / 256), dim3(256), 0, st, scratch, R,
+                     nchunks, xs, inv, pos);
+  if (Rs > R) hipLaunchKernelGGL(k_x_pad, dim3((Rs - R + 255) / 256), dim3(256), 0, st, R, Rs, xs, inv);
+}
+
+}  // namespace infuse
