@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of the whole hot path on one MI355X.
+
+A step = one cold pass over the large single-graph workload (R-MAT scale 18,
+edge factor 5, a/b/c/d = .57/.19/.19/.05, seed 3; p = 0.01, R = 8,192,
+K = 100, hash seed 3): hash sampler set-up, fused multi-simulation connected
+components, component-size memo and initial gains, 100 CELF steps on the
+device, and sigma(S) of the selected seeds.  The graph is resident in HBM
+before the timed region; the memo is dropped before every step.
+
+Prints one JSON line.  value = m*R per second of whole steps (edge-samples/s).
+
+    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c1]
+    python bench.py --calibrate-copy     # plain copy kernel for counter scaling
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge-samples/s (m·R/s), K-seed time; serving p50/p99 vs plain per-query launch"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hook_c4_traffic.txt")
+HOOK_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("cc.hip", "common.h")]
+
+WORKLOADS = {
+    "c4": "R-MAT scale 18, edge factor 5, a/b/c/d=.57/.19/.19/.05, seed 3; p=0.01, R=8192, K=100",
+    "c2": "Chung-Lu n=15000, gamma 2.3, m=31000, seed 2; p=0.01, R=2048, K=50",
+    "c1": "Chung-Lu n=2000, gamma 2.5, m=8000, seed 1; p=0.05, R=256, K=10",
+}
+
+
+def hook_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in HOOK_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per hook launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("TRAFFIC_JSON "):
+                    rec = json.loads(line[len("TRAFFIC_JSON "):])
+                    if rec.get("source_hash") == hook_source_hash():
+                        return rec
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(workload, samples: int):
+    """The oracle as it stands (labelling of every sample + memo-formula CELF)
+    on the first `samples` simulations of the same graph and K."""
+    import oracle
+
+    g = workload.graphs[0]
+    threads = len(os.sched_getaffinity(0))
+    s = oracle.Sampler("hash", p=workload.p, R=samples, seed=workload.seeds[0])
+    t = time.perf_counter()
+    oracle.run_memo(g, s, workload.K, threads=threads)
+    dt = time.perf_counter() - t
+    return {
+        "value": g.m * samples / dt,
+        "unit": "edge-samples/s",
+        "cores": threads,
+        "kind": "oracle",
+        "seconds": round(dt, 3),
+        "sample": (f"same graph and K={workload.K}, first {samples} of {workload.R} simulations: "
+                   f"BFS labelling of every sample + CELF on stored labels (m*{samples} "
+                   f"edge-samples in {dt:.2f} s)"),
+    }
+
+
+def calibrate_copy(gib: int = 4, reps: int = 5):
+    import torch
+
+    n = gib << 28  # int32 elements
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n * 4, "bytes_written": n * 4,
+                      "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the multi-GPU path (R-sharding with one all-reduce of "
+              "int64 gains) is a design, not part of this build; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_2008_03095_amd as P
+    from workloads import make_config
+
+    w = make_config(args.workload)
+    g = w.graphs[0]
+    p, R, K, seed = w.p, w.R, w.K, w.seeds[0]
+
+    ctx = P.Context(device=0)
+    G = P.Graph.from_csr(ctx, g)
+    G.set_params(p, R, seed)
+
+    def step():
+        G.drop_memo()
+        G.build_memo()
+        seeds, marg, cover = G.select_seeds(K)
+        cnt, _ = G.estimate_sigma(seeds)
+        if cnt != cover:
+            raise RuntimeError("sigma of the selected seeds differs from the cover count")
+        return seeds, cover
+
+    for _ in range(args.warmup):
+        step()
+    ctx.set_profiling(True)
+    ctx.reset_kernel_stats()
+    phases = np.zeros(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        seeds, cover = step()
+        phases += np.array(G.phase_ms())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_profiling(False)
+
+    ms_per_step = dt * 1e3 / args.steps
+    value = g.m * R * args.steps / dt
+    hook_n, hook_ms = ctx.kernel_stats("hook")
+    hook_avg = hook_ms / max(hook_n, 1)
+    alg_bytes = 4 * g.n * R  # one memo word written per (vertex, simulation)
+    achieved = alg_bytes / (hook_avg * 1e-3) / 1e9
+    traffic = read_traffic()
+    phases /= args.steps
+    t_cc = phases[1]
+    stats = {k: ctx.kernel_stats(k) for k in ("edge_hash", "x_sort", "hook", "link", "flatten",
+                                               "count", "gain0", "sigma")}
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n": g.n, "m": g.m,
+                   "R": R, "K": K, "p": p, "hash_seed": seed},
+        "k_seed_ms": ms_per_step,
+        "phase_ms": {"sampler_prep": phases[0], "components": phases[1], "gains0": phases[2],
+                     "celf": phases[3]},
+        "edge_samples_per_s_components": g.m * R / (t_cc * 1e-3) if t_cc > 0 else None,
+        "celf_evals": G.celf_evals(),
+        "cover_count": cover,
+        "kernel_avg_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in stats.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_hook",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "algorithmic_bytes": alg_bytes,
+            "avg_launch_ms": hook_avg,
+        },
+        "cpu_baseline": None,
+    }
+    G.free()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, min(args.cpu_samples, R))
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,7 @@ def _load():
     lib.orc_is_live.argtypes = [u32, u32, u64]
     lib.orc_is_live.restype = C.c_int
     common = [u32, vp, vp, C.c_int, dbl, vp, u32, u32, vp]
-    lib.orc_label_all.argtypes = common + [vp, vp, vp, vp, C.c_int]
+    lib.orc_label_all.argtypes = common + [vp, vp, vp, vp, vp, C.c_int]
     lib.orc_label_all.restype = C.c_int
     lib.orc_label_range.argtypes = common + [u32, u32, vp]
     lib.orc_label_range.restype = C.c_int
@@ -70,6 +70,8 @@ def _load():
     lib.orc_gain.restype = i64
     lib.orc_celf.argtypes = common + [vp, u32, vp, vp, vp, vp, C.c_int]
     lib.orc_celf.restype = C.c_int
+    lib.orc_celf_memo.argtypes = [u32, u32, vp, vp, vp, u32, vp, vp, vp, vp]
+    lib.orc_celf_memo.restype = C.c_int
     _lib = lib
     return lib
 
@@ -133,21 +135,25 @@ def is_live(h: int, x: int, t: int) -> bool:
 
 
 def label_all(g, s: Sampler, want_labels: bool = False, digest_w: Optional[np.ndarray] = None,
-              threads: int = 1):
-    """Returns (g0 int64[n], labels int32[n][R] or None, digests uint64[R] or None)."""
+              threads: int = 1, want_sizes: bool = False):
+    """Returns (g0 int64[n], labels int32[n][R] or None, digests uint64[R] or None),
+    plus sizes uint32[n][R] as a fourth item when want_sizes is set."""
     lib = _load()
     keep, a = _args(g, s)
     g0 = np.zeros(g.n, dtype=np.int64)
     labels = np.empty((g.n, s.R), dtype=np.int32) if want_labels else None
+    sizes = np.empty((g.n, s.R), dtype=np.uint32) if want_sizes else None
     dig = None
     dw = None
     if digest_w is not None:
         dw = np.ascontiguousarray(digest_w, dtype=np.uint64)
         dig = np.zeros(s.R, dtype=np.uint64)
-    rc = lib.orc_label_all(*a, _ptr(g0), _ptr(labels), _ptr(dig), _ptr(dw), int(threads))
+    rc = lib.orc_label_all(*a, _ptr(g0), _ptr(labels), _ptr(sizes), _ptr(dig), _ptr(dw), int(threads))
     if rc != 0:
         raise RuntimeError("oracle: allocation failure")
     del keep
+    if want_sizes:
+        return g0, labels, dig, sizes
     return g0, labels, dig
 
 
@@ -206,3 +212,35 @@ def run(g, s: Sampler, K: int, want_labels: bool = False, digest_w=None, threads
     seeds, marg, cover, evals = celf(g, s, K, g0, threads=threads)
     return dict(g0=g0, labels=labels, digests=dig, seeds=seeds, marginal=marg, cover=cover,
                 evals=evals)
+
+
+def celf_memo(labels: np.ndarray, sizes: np.ndarray, g0: np.ndarray, K: int):
+    """CELF evaluating gains from stored labels and sizes (memo formula).
+    Returns (seeds, marginal, cover, n_evals)."""
+    lib = _load()
+    n, R = labels.shape
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint32)
+    g0 = np.ascontiguousarray(g0, dtype=np.int64)
+    seeds = np.zeros(K, dtype=np.uint32)
+    marg = np.zeros(K, dtype=np.int64)
+    cover = C.c_int64(0)
+    evals = C.c_uint64(0)
+    rc = lib.orc_celf_memo(n, R, _ptr(labels), _ptr(sizes), _ptr(g0), int(K), _ptr(seeds),
+                           _ptr(marg), C.byref(cover), C.byref(evals))
+    if rc == -2:
+        raise ValueError("K > n")
+    if rc != 0:
+        raise RuntimeError("oracle: allocation failure")
+    return seeds, marg, int(cover.value), int(evals.value)
+
+
+def run_memo(g, s: Sampler, K: int, digest_w=None, threads: int = 1, keep_arrays: bool = False) -> dict:
+    """Whole method with the memo-formula CELF (Algorithm 7's evaluation)."""
+    g0, labels, dig, sizes = label_all(g, s, want_labels=True, digest_w=digest_w, threads=threads,
+                                       want_sizes=True)
+    seeds, marg, cover, evals = celf_memo(labels, sizes, g0, K)
+    out = dict(g0=g0, digests=dig, seeds=seeds, marginal=marg, cover=cover, evals=evals)
+    if keep_arrays:
+        out.update(labels=labels, sizes=sizes)
+    return out

@@ -257,6 +257,7 @@ typedef struct {
     /* task 0 */
     int64_t *g0_part;          /* [n] */
     int32_t *labels_out;       /* [n][R] or NULL */
+    uint32_t *sizes_out;       /* [n][R] or NULL: |C_r(v)| */
     uint64_t *digest_out;      /* [R] or NULL */
     const uint64_t *digest_w;  /* [n] */
     /* task 1 / 2 */
@@ -280,6 +281,8 @@ static void *job_run(void *arg) {
             for (uint32_t v = 0; v < n; ++v) jb->g0_part[v] += csize[v];
             if (jb->labels_out)
                 for (uint32_t v = 0; v < n; ++v) jb->labels_out[(uint64_t)v * g->R + r] = label[v];
+            if (jb->sizes_out)
+                for (uint32_t v = 0; v < n; ++v) jb->sizes_out[(uint64_t)v * g->R + r] = csize[v];
             if (jb->digest_out) {
                 uint64_t d = 0;
                 for (uint32_t v = 0; v < n; ++v) d += (uint64_t)(uint32_t)(label[v] + 1) * jb->digest_w[v];
@@ -345,11 +348,12 @@ static int run_jobs(orc_job *tmpl, int threads) {
 /* ---------------------------------------------------------------------- */
 
 /* Labels all R samples; accumulates g0[v] = sum_r |C_r(v)| (int64, must be
- * zeroed by the caller).  labels_out ([n][R], vertex-major, like the memo of
- * Section III-C) and digest_out ([R]) are optional. */
+ * zeroed by the caller).  labels_out and sizes_out ([n][R], vertex-major, the
+ * two arrays of Section III-C with sizes stored per vertex) and digest_out
+ * ([R]) are optional. */
 int orc_label_all(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int mode, double p,
                   const double *p_slot, uint32_t R, uint32_t seed, const uint8_t *table,
-                  int64_t *g0, int32_t *labels_out, uint64_t *digest_out,
+                  int64_t *g0, int32_t *labels_out, uint32_t *sizes_out, uint64_t *digest_out,
                   const uint64_t *digest_w, int threads) {
     orc_graph g;
     if (graph_init(&g, n, row_ptr, col, mode, p, p_slot, R, seed, table)) return -1;
@@ -359,6 +363,7 @@ int orc_label_all(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int 
     jb.task = 0;
     jb.g0_part = g0;
     jb.labels_out = labels_out;
+    jb.sizes_out = sizes_out;
     jb.digest_out = digest_out;
     jb.digest_w = digest_w;
     run_jobs(&jb, threads);
@@ -477,5 +482,60 @@ int orc_celf(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int mode,
     free(iter);
     free(is_seed);
     graph_free(&g);
+    return 0;
+}
+
+/* CELF whose re-evaluation uses the stored labels and sizes (the memo of
+ * Section III-C, Algorithm 7): gain(u | S) = sum_r |C_r(u)| over the samples
+ * where u's label differs from the label of every seed.  Same queue
+ * discipline as orc_celf.  labels/sizes are [n][R] vertex-major. */
+int orc_celf_memo(uint32_t n, uint32_t R, const int32_t *labels, const uint32_t *sizes,
+                  const int64_t *g0, uint32_t K, uint32_t *seeds, int64_t *marginal,
+                  int64_t *cover_count, uint64_t *n_evals) {
+    if (K > n) return -2;
+    int64_t *mg = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    uint32_t *iter = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    uint8_t *is_seed = (uint8_t *)calloc(n ? n : 1, 1);
+    if (!mg || !iter || !is_seed) return -1;
+    for (uint32_t v = 0; v < n; ++v) mg[v] = g0[v];
+    uint32_t s_size = 0;
+    int64_t cover = 0;
+    uint64_t evals = 0;
+    while (s_size < K) {
+        int64_t best = -1;
+        uint32_t top = 0;
+        for (uint32_t v = 0; v < n; ++v) {
+            if (is_seed[v]) continue;
+            if (mg[v] > best) {
+                best = mg[v];
+                top = v;
+            }
+        }
+        if (iter[top] == s_size) {
+            seeds[s_size] = top;
+            marginal[s_size] = mg[top];
+            cover += mg[top];
+            is_seed[top] = 1;
+            ++s_size;
+        } else {
+            const int32_t *lu = labels + (uint64_t)top * R;
+            const uint32_t *su = sizes + (uint64_t)top * R;
+            int64_t gain = 0;
+            for (uint32_t r = 0; r < R; ++r) {
+                int covered = 0;
+                for (uint32_t k = 0; k < s_size && !covered; ++k)
+                    covered = labels[(uint64_t)seeds[k] * R + r] == lu[r];
+                if (!covered) gain += su[r];
+            }
+            mg[top] = gain;
+            iter[top] = s_size;
+            ++evals;
+        }
+    }
+    *cover_count = cover;
+    if (n_evals) *n_evals = evals;
+    free(mg);
+    free(iter);
+    free(is_seed);
     return 0;
 }

@@ -18,9 +18,9 @@
 //              merged by lock-free union: the larger root is linked under the
 //              smaller with compare-and-swap, so every root stays the minimum
 //              of its tree in any interleaving.
-//   k_compress every non-root entry is replaced by its root, and each root's
-//              -1 is decremented once per member: afterwards roots hold
-//              -|component| (the size memo) and members hold the label.
+//   k_flatten  every non-root entry is replaced by its root;
+//   k_count    each member decrements its root's -1 once: afterwards roots
+//              hold -|component| (the size memo) and members hold the label.
 //   k_gain0    mg_v = sum over columns of |C_q(v)| (Algorithm 5, int64).
 //
 // Work skipping.  Columns are sorted by X, so a 256-column tile spans a
@@ -201,22 +201,35 @@ __global__ void __launch_bounds__(256) k_hook(GraphView g, MemoView m, uint32_t 
   }
 }
 
+// Root of x in column q, halving the path on the way.  Entries only move
+// from "root" (-1) to a parent id and from a parent to an ancestor, so a
+// stale cached value is always an older state of the same tree: plain loads
+// are safe, and a root seen here that was linked meanwhile is caught by the
+// compare-and-swap in unite.  Halving writes an ancestor into a non-root
+// entry, which leaves it in the same tree; it is an atomic store because
+// every write to the memo in this kernel goes through device-scope atomics
+// (the L2 caches of the eight XCDs are not coherent with each other within
+// a kernel).
 __device__ inline uint32_t find_root(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
   while (true) {
-    const int32_t p = __hip_atomic_load(&M[(uint64_t)x * Rs + q], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t p = M[(uint64_t)x * Rs + q];
     if (p < 0) return x;
-    x = (uint32_t)p;
+    const int32_t gp = M[(uint64_t)p * Rs + q];
+    if (gp < 0) return (uint32_t)p;
+    __hip_atomic_store(&M[(uint64_t)x * Rs + q], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = (uint32_t)gp;
   }
 }
 
 // Union of a and b in column q.  Roots hold -1 during linking; linking the
-// larger root under the smaller keeps every root its tree's minimum.
+// larger root under the smaller keeps every root its tree's minimum.  A
+// failed compare-and-swap returns the entry's current parent, from which the
+// walk continues: every retry moves one side to a strictly smaller id, so the
+// loop ends.
 __device__ inline void unite(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
-  while (true) {
-    a = find_root(M, Rs, a, q);
-    b = find_root(M, Rs, b, q);
-    if (a == b) return;
+  a = find_root(M, Rs, a, q);
+  b = find_root(M, Rs, b, q);
+  while (a != b) {
     if (a < b) {
       const uint32_t t = a;
       a = b;
@@ -227,6 +240,8 @@ __device__ inline void unite(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, ui
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return;
+    a = find_root(M, Rs, (uint32_t)expected, q);
+    b = find_root(M, Rs, b, q);
   }
 }
 
@@ -272,7 +287,10 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m, uint32_t 
   }
 }
 
-__global__ void __launch_bounds__(256) k_compress(MemoView m, uint32_t chunk, uint32_t wpv) {
+// k_flatten: every non-root entry of a flagged tile is replaced by its root
+// (plain loads and stores only; a stale value read during the walk is an
+// older ancestor, so every walk still ends at the root).
+__global__ void __launch_bounds__(256) k_flatten(MemoView m, uint32_t chunk, uint32_t wpv) {
   const WaveJob job = wave_job(m.n, m.ntiles, chunk, wpv);
   if (!job.ok) return;
   const uint32_t lane = threadIdx.x & 63, v = job.v;
@@ -284,11 +302,13 @@ __global__ void __launch_bounds__(256) k_compress(MemoView m, uint32_t chunk, ui
     if (!((mybits >> (t - job.t0)) & 1u)) continue;
     const uint32_t q0 = t * kTile + lane * kPerLane;
     const int4 cur = *reinterpret_cast<const int4*>(row + q0);
-    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+    int4 out = cur;
+    int32_t* o = &out.x;
+    bool changed = false;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t q = q0 + i;
-      const int32_t val = vals[i];
+      const int32_t val = o[i];
       if (q >= m.R || val < 0) continue;
       uint32_t c = (uint32_t)val;
       while (true) {
@@ -296,9 +316,53 @@ __global__ void __launch_bounds__(256) k_compress(MemoView m, uint32_t chunk, ui
         if (p < 0) break;
         c = (uint32_t)p;
       }
-      if (c != (uint32_t)val) row[q] = (int32_t)c;
-      atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+      if (c != (uint32_t)val) {
+        o[i] = (int32_t)c;
+        changed = true;
+      }
     }
+    if (changed) *reinterpret_cast<int4*>(row + q0) = out;
+  }
+}
+
+// k_count: each member entry (now pointing at its root) decrements its
+// root's -1 once, so roots end at -|component|.  Only atomics write the memo
+// here.  Workgroup = one 256-column tile x a block of vertices; counts for
+// roots below kHotRoots are summed in LDS first, because large components
+// (in power-law graphs the giant one) are rooted at small ids and their
+// members would otherwise all hit the same words.
+constexpr uint32_t kHotRoots = 64;
+constexpr uint32_t kCountBlockVerts = 4096;
+
+__global__ void __launch_bounds__(256) k_count(MemoView m) {
+  __shared__ uint32_t hot[kHotRoots][kTile];
+  const uint32_t t = blockIdx.x % m.ntiles;
+  const uint32_t v0 = (blockIdx.x / m.ntiles) * kCountBlockVerts;
+  const uint32_t v1 = min(v0 + kCountBlockVerts, m.n);
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (uint32_t i = threadIdx.x; i < kHotRoots * kTile; i += blockDim.x) (&hot[0][0])[i] = 0;
+  __syncthreads();
+  const uint32_t word = t >> 5, bit = t & 31;
+  const uint32_t q0 = t * kTile + lane * kPerLane;
+  for (uint32_t v = v0 + wv; v < v1; v += 4) {
+    if (!((uni(m.tmask[(uint64_t)v * m.mwords + word]) >> bit) & 1u)) continue;
+    const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + q0);
+    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t q = q0 + i;
+      const int32_t c = vals[i];
+      if (q >= m.R || c < 0) continue;
+      if ((uint32_t)c < kHotRoots) atomicAdd(&hot[c][lane * kPerLane + i], 1u);
+      else atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kHotRoots * kTile; i += blockDim.x) {
+    const uint32_t cnt = (&hot[0][0])[i];
+    if (!cnt) continue;
+    const uint32_t c = i / kTile, q = t * kTile + i % kTile;
+    atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -(int32_t)cnt);
   }
 }
 
@@ -378,7 +442,12 @@ void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk, hipStrea
 
 void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {
   const uint32_t wpv = waves_per_vertex(m, chunk);
-  hipLaunchKernelGGL(k_compress, grid_for(m.n, wpv), dim3(256), 0, st, m, chunk, wpv);
+  hipLaunchKernelGGL(k_flatten, grid_for(m.n, wpv), dim3(256), 0, st, m, chunk, wpv);
+}
+
+void launch_count(const MemoView& m, hipStream_t st) {
+  const uint32_t vblocks = (m.n + kCountBlockVerts - 1) / kCountBlockVerts;
+  hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m);
 }
 
 void launch_gain0(const MemoView& m, hipStream_t st) {

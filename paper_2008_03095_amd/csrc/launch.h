@@ -16,6 +16,7 @@ void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st
 void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_compress(const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_count(const MemoView& m, hipStream_t st);
 void launch_gain0(const MemoView& m, hipStream_t st);
 
 // celf.hip

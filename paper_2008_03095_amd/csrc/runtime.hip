@@ -280,8 +280,12 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     launch_link(g->view(), mv, chunk_tiles, st);
   }
   {
-    KTimer t(c, "compress", st);
+    KTimer t(c, "flatten", st);
     launch_compress(mv, chunk_tiles, st);
+  }
+  {
+    KTimer t(c, "count", st);
+    launch_count(mv, st);
   }
   if (timed) (void)hipEventRecord(g->ev[2], st);
   {

@@ -28,3 +28,16 @@ def min_id_labels(n: int, u: np.ndarray, v: np.ndarray) -> np.ndarray:
     mins = np.full(comp.max() + 1 if n else 0, n, dtype=np.int64)
     np.minimum.at(mins, comp, np.arange(n))
     return mins[comp].astype(np.int32)
+
+
+def combine_digests(digests: np.ndarray) -> str:
+    """Checksum of all per-sample digests (weights independent of the label weights)."""
+    w = splitmix64_stream(0xC0FFEE, 0, digests.size) | np.uint64(1)
+    with np.errstate(over="ignore"):
+        return "%016x" % int((digests.astype(np.uint64) * w).sum(dtype=np.uint64))
+
+
+def gains_checksum(g0: np.ndarray) -> str:
+    w = splitmix64_stream(0x6A1, 0, g0.size) | np.uint64(1)
+    with np.errstate(over="ignore"):
+        return "%016x" % int((g0.astype(np.uint64) * w).sum(dtype=np.uint64))

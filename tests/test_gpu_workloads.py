@@ -1,0 +1,88 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark uses, against oracle outputs stored by tests/golden/make_golden.py.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2008_03095_amd as P
+from tests.conftest import announce
+from tests.helpers import combine_digests, digest_weights, gains_checksum, label_digests
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _all_digests(G, n, R, chunk):
+    dw = digest_weights(n)
+    out = np.empty(R, dtype=np.uint64)
+    for r0 in range(0, R, chunk):
+        cnt = min(chunk, R - r0)
+        out[r0:r0 + cnt] = label_digests(G.labels(r0, cnt), dw)
+    return out
+
+
+def test_c4_large_graph(gpu_ctx):
+    gold = _golden("c4_oracle.json")
+    w = make_config("c4")
+    g = w.graphs[0]
+    assert (g.n, g.m) == (gold["n"], gold["m"])
+    announce(f"c4 n={g.n} m={g.m} R={w.R} K={w.K}")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(w.p, w.R, w.seeds[0])
+        seeds, marg, cover = G.select_seeds(w.K)
+        assert [int(x) for x in seeds] == gold["seeds"]
+        assert [int(x) for x in marg] == gold["marginal"]
+        assert cover == gold["cover"]
+        g0 = G.gains0()
+        assert int(g0.sum()) == gold["g0_sum"]
+        assert gains_checksum(g0) == gold["g0_check"]
+        for v, x in gold["g0_samples"].items():
+            assert int(g0[int(v)]) == x
+        for q in gold["sigma"]:
+            assert G.estimate_sigma(q["S"])[0] == q["count"]
+        dig = _all_digests(G, g.n, w.R, 512)
+        assert ["%016x" % int(x) for x in dig[::gold["digest_every"]]] == gold["digests"]
+        assert combine_digests(dig) == gold["label_check"]
+    finally:
+        G.free()
+
+
+def test_c3_graphs_one_by_one_and_batched(gpu_ctx):
+    gold = _golden("c3_oracle.json")["graphs"]
+    w = make_config("c3")
+    announce("c3 one by one")
+    graphs = []
+    try:
+        for g, seed, ref in zip(w.graphs, w.seeds, gold):
+            assert (g.n, g.m) == (ref["n"], ref["m"])
+            G = P.Graph.from_csr(gpu_ctx, g)
+            graphs.append(G)
+            G.set_params(0.0, w.R, seed)
+            seeds, marg, cover = G.select_seeds(w.K)
+            assert [int(x) for x in seeds] == ref["seeds"], g.name
+            assert [int(x) for x in marg] == ref["marginal"], g.name
+            assert cover == ref["cover"]
+            assert gains_checksum(G.gains0()) == ref["g0_check"]
+            assert combine_digests(_all_digests(G, g.n, w.R, 1024)) == ref["label_check"], g.name
+        announce("c3 batched")
+        for G in graphs:
+            G.drop_memo()
+        res = P.batch_select(gpu_ctx, graphs, [w.K] * len(graphs))
+        for (seeds, marg, cover), ref in zip(res, gold):
+            assert [int(x) for x in seeds] == ref["seeds"]
+            assert [int(x) for x in marg] == ref["marginal"]
+            assert cover == ref["cover"]
+    finally:
+        for G in graphs:
+            G.free()

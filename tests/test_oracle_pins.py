@@ -474,3 +474,27 @@ def test_hash_sampler_matches_its_exact_expectation():
         s = oracle.Sampler("hash", p=p, R=R, seed=seed)
         est = oracle.sigma_count(g, s, S) / R
         assert abs(est - mean) <= 5 * math.sqrt(var / R) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The memo-formula CELF (Algorithm 7's evaluation from stored labels and
+# sizes) against the RandCas CELF (Algorithm 3's re-simulation) on the same
+# samples: identical seeds and marginals
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,p,R,K,seed", [(600, 2400, 0.05, 64, 12, 2), (1500, 4000, 0.2, 32, 9, 3),
+                                            (300, 1500, 0.01, 200, 20, 4), (80, 200, 1.0, 8, 30, 5)])
+def test_memo_celf_equals_randcas_celf(n, m, p, R, K, seed):
+    g = chung_lu(n, m, 2.4, seed)
+    s = oracle.Sampler("hash", p=p, R=R, seed=seed)
+    a = oracle.run(g, s, K, threads=2)
+    b = oracle.run_memo(g, s, K, threads=2, keep_arrays=True)
+    assert np.array_equal(a["g0"], b["g0"])
+    assert list(a["seeds"]) == list(b["seeds"])
+    assert list(a["marginal"]) == list(b["marginal"])
+    assert a["cover"] == b["cover"]
+    # sizes are the per-vertex component sizes of the labels
+    L, Z = b["labels"], b["sizes"]
+    for r in range(R):
+        cnt = np.bincount(L[:, r], minlength=n)
+        assert np.array_equal(Z[:, r], cnt[L[:, r]])
