@@ -106,6 +106,10 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--cc-chunk", type=int, default=0, help="columns per wavefront in labelling")
+    ap.add_argument("--celf-width", type=int, default=0, help="CELF candidates per round")
+    ap.add_argument("--profile-celf", action="store_true",
+                    help="also time every CELF launch (perturbs the step time)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,6 +131,7 @@ def main():
     p, R, K, seed = w.p, w.R, w.K, w.seeds[0]
 
     ctx = P.Context(device=0)
+    ctx.set_tuning(cc_chunk=args.cc_chunk, celf_width=args.celf_width)
     G = P.Graph.from_csr(ctx, g)
     G.set_params(p, R, seed)
 
@@ -141,7 +146,7 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    ctx.set_profiling(True)
+    ctx.set_profiling(2 if args.profile_celf else 1)
     ctx.reset_kernel_stats()
     phases = np.zeros(4)
     torch.cuda.synchronize()
@@ -163,7 +168,8 @@ def main():
     phases /= args.steps
     t_cc = phases[1]
     stats = {k: ctx.kernel_stats(k) for k in ("edge_hash", "x_sort", "hook", "link", "flatten",
-                                               "count", "gain0", "sigma")}
+                                               "count", "gain0", "sigma", "celf_topw",
+                                               "celf_eval", "celf_bulk")}
     rec = {
         "metric": METRIC,
         "value": value,
@@ -178,7 +184,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n": g.n, "m": g.m,
-                   "R": R, "K": K, "p": p, "hash_seed": seed},
+                   "R": R, "K": K, "p": p, "hash_seed": seed, "tuning": ctx.tuning()},
         "k_seed_ms": ms_per_step,
         "phase_ms": {"sampler_prep": phases[0], "components": phases[1], "gains0": phases[2],
                      "celf": phases[3]},
@@ -186,6 +192,7 @@ def main():
         "celf_evals": G.celf_evals(),
         "cover_count": cover,
         "kernel_avg_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in stats.items()},
+        "kernel_total_ms_per_step": {k: v[1] / args.steps for k, v in stats.items()},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_hook",

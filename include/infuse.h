@@ -170,10 +170,13 @@ im_status im_set_tuning(im_ctx *ctx, const im_tuning *t);
 im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);
 
 /* Per-kernel device timing with HIP events recorded on the context stream
- * around every launch (off by default).  im_kernel_stats returns the number
- * of launches and the summed milliseconds of the named kernel since the last
- * reset. */
-im_status im_set_profiling(im_ctx *ctx, int enabled);
+ * around launches (off by default).  level 0: off; 1: the kernels that run
+ * once per memo construction or query (edge_hash, x_sort, hook, link,
+ * flatten, count, gain0, sigma); 2: also every CELF round launch
+ * (celf_topw, celf_eval, celf_bulk), whose events perturb the timing of
+ * such short kernels.  im_kernel_stats returns the number of launches and
+ * the summed milliseconds of the named kernel since the last reset. */
+im_status im_set_profiling(im_ctx *ctx, int level);
 im_status im_reset_kernel_stats(im_ctx *ctx);
 im_status im_kernel_stats(im_ctx *ctx, const char *kernel, uint64_t *launches, double *total_ms);
 

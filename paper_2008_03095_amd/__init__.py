@@ -100,8 +100,9 @@ class Context:
         check(self._lib.im_get_tuning(self.handle, C.byref(t)))
         return dict(cc_chunk=t.cc_chunk, celf_width=t.celf_width, use_graphs=bool(t.use_graphs))
 
-    def set_profiling(self, on: bool):
-        check(self._lib.im_set_profiling(self.handle, 1 if on else 0))
+    def set_profiling(self, level):
+        """0/False: off; 1/True: per-build kernels; 2: also every CELF launch."""
+        check(self._lib.im_set_profiling(self.handle, int(level)))
 
     def reset_kernel_stats(self):
         check(self._lib.im_reset_kernel_stats(self.handle))

@@ -34,7 +34,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     for (uint32_t k = 0; k < kmax; ++k)
       for (uint32_t i = 0; i < ng; ++i)
         if (k < K[i]) {
-          const uint32_t bulk_blocks = std::max(1u, std::min(2048u, (graphs[i]->n + 3) / 4));
+          const uint32_t bulk_blocks = std::max(1u, std::min(2048u, graphs[i]->n));
           launch_celf_step(cbs[i].v, bulk_blocks, c->stream);
         }
     for (uint32_t i = 0; i < ng && st == IM_OK; ++i) {

@@ -28,10 +28,10 @@
 // [X_lo >> k, X_hi >> k] where k = bitlen(T - 1).  The wavefront tests all
 // (up to 64) adjacent edges with one compare and one ballot per tile and runs
 // the per-column test only for the candidates.  k_hook records, per
-// (vertex, tile), whether any candidate exists (tmask: the tile may hold a
-// non-singleton column) and whether some column has two or more live smaller
-// neighbours (lmask: the tile needs k_link); the later kernels visit only
-// those tiles.
+// (vertex, tile), whether any candidate exists (tmask, and the work list
+// tlist: the tile may hold a non-singleton column) and whether some column
+// has two or more live smaller neighbours (work list llist: the tile needs
+// k_link); the later kernels visit only those tiles.
 #include "common.h"
 
 namespace infuse {
@@ -196,38 +196,43 @@ __global__ void __launch_bounds__(256) k_hook(GraphView g, MemoView m, uint32_t 
   }
   if (lane == 0) {
     const uint32_t word = job.t0 >> 5, sh = job.t0 & 31;
-    if (tbits) atomicOr(&m.tmask[(uint64_t)v * m.mwords + word], tbits << sh);
-    if (lbits) atomicOr(&m.lmask[(uint64_t)v * m.mwords + word], lbits << sh);
+    const uint32_t sub = blockIdx.x % kSubLists;
+    if (tbits) {
+      atomicOr(&m.tmask[(uint64_t)v * m.mwords + word], tbits << sh);
+      uint32_t at = atomicAdd(&m.counts[2 * sub], (uint32_t)__popc(tbits));
+      uint32_t* out = m.tlist + (uint64_t)sub * m.list_cap;
+      for (uint32_t b = tbits; b; b &= b - 1) out[at++] = v * m.ntiles + job.t0 + __ffs(b) - 1;
+    }
+    if (lbits) {
+      uint32_t at = atomicAdd(&m.counts[2 * sub + 1], (uint32_t)__popc(lbits));
+      uint32_t* out = m.llist + (uint64_t)sub * m.list_cap;
+      for (uint32_t b = lbits; b; b &= b - 1) out[at++] = v * m.ntiles + job.t0 + __ffs(b) - 1;
+    }
   }
 }
 
-// Root of x in column q, halving the path on the way.  Entries only move
-// from "root" (-1) to a parent id and from a parent to an ancestor, so a
-// stale cached value is always an older state of the same tree: plain loads
-// are safe, and a root seen here that was linked meanwhile is caught by the
-// compare-and-swap in unite.  Halving writes an ancestor into a non-root
-// entry, which leaves it in the same tree; it is an atomic store because
-// every write to the memo in this kernel goes through device-scope atomics
-// (the L2 caches of the eight XCDs are not coherent with each other within
-// a kernel).
-__device__ inline uint32_t find_root(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
+// Root of x in column q.  During linking entries only move from "root" (-1)
+// to a parent id of a smaller vertex, so a stale value read from a
+// non-coherent cache is an older state of the same tree: the walk still
+// ends, at a vertex that is or was a root of x's tree.  A root seen here
+// that was linked meanwhile is caught by the compare-and-swap in unite.
+__device__ inline uint32_t find_root(const int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
   while (true) {
     const int32_t p = M[(uint64_t)x * Rs + q];
     if (p < 0) return x;
-    const int32_t gp = M[(uint64_t)p * Rs + q];
-    if (gp < 0) return (uint32_t)p;
-    __hip_atomic_store(&M[(uint64_t)x * Rs + q], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    x = (uint32_t)gp;
+    x = (uint32_t)p;
   }
 }
 
-// Union of a and b in column q.  Roots hold -1 during linking; linking the
-// larger root under the smaller keeps every root its tree's minimum.  A
-// failed compare-and-swap returns the entry's current parent, from which the
-// walk continues: every retry moves one side to a strictly smaller id, so the
-// loop ends.
-__device__ inline void unite(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
-  a = find_root(M, Rs, a, q);
+// Joins root a with the tree of b in column q and returns the smallest root
+// reached.  Roots hold -1 during linking; the larger root is linked under
+// the smaller with compare-and-swap, so every root stays the minimum of its
+// tree in any interleaving.  A failed compare-and-swap returns the entry's
+// current parent, from which the walk continues: each retry moves one side
+// to a strictly smaller id, so the loop ends.  The memo is written only by
+// atomics in this kernel (the XCD L2 caches are not coherent within a
+// kernel, so plain stores must not share lines with atomics).
+__device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
   b = find_root(M, Rs, b, q);
   while (a != b) {
     if (a < b) {
@@ -239,31 +244,73 @@ __device__ inline void unite(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, ui
     if (__hip_atomic_compare_exchange_strong(&M[(uint64_t)a * Rs + q], &expected, (int32_t)b,
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
-      return;
+      return b;
     a = find_root(M, Rs, (uint32_t)expected, q);
     b = find_root(M, Rs, b, q);
   }
+  return a;
+}
+
+// Wavefront iteration over the concatenation of the kSubLists sub-lists of a
+// work list: every wavefront of the grid strides over all entries (so the
+// heavy tiles of hub vertices spread over the whole grid).  The sub-list
+// sizes are prefix-summed in LDS by each workgroup (blockDim.x == 256 ==
+// kSubLists) and an entry's sub-list found by binary search.
+struct ListIter {
+  const uint32_t* list;
+  const uint32_t* pre;  // LDS, kSubLists + 1 prefix sums
+  uint32_t cap, total, first, stride;
+  __device__ uint32_t at(uint32_t idx) const {
+    uint32_t lo = 0, hi = kSubLists;  // pre[lo] <= idx < pre[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (pre[mid] <= idx) lo = mid; else hi = mid;
+    }
+    return list[(uint64_t)lo * cap + (idx - pre[lo])];
+  }
+};
+__device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, int which,
+                                     uint32_t* pre) {
+  static_assert(kSubLists == 256, "one prefix element per thread of a 256-thread workgroup");
+  const uint32_t tid = threadIdx.x;
+  uint32_t x = m.counts[2 * tid + which];
+  pre[tid + 1] = x;
+  if (tid == 0) pre[0] = 0;
+  __syncthreads();
+  for (uint32_t off = 1; off < kSubLists; off <<= 1) {
+    const uint32_t y = tid + 1 > off ? pre[tid + 1 - off] : 0u;
+    __syncthreads();
+    x += y;
+    pre[tid + 1] = x;
+    __syncthreads();
+  }
+  ListIter it;
+  it.list = base;
+  it.pre = pre;
+  it.cap = m.list_cap;
+  it.total = uni(pre[kSubLists]);
+  it.first = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  it.stride = gridDim.x * (blockDim.x >> 6);
+  return it;
 }
 
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
-  const WaveJob job = wave_job(g.n, m.ntiles, chunk, wpv);
-  if (!job.ok) return;
-  const uint32_t lane = threadIdx.x & 63, v = job.v;
-  const uint32_t word = uni(m.lmask[(uint64_t)v * m.mwords + (job.t0 >> 5)]);
-  const uint32_t mybits = (word >> (job.t0 & 31)) & (job.t1 - job.t0 >= 32 ? ~0u : ((1u << (job.t1 - job.t0)) - 1));
-  if (!mybits) return;
-  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
-  const bool inreg = end - beg <= (uint32_t)kWave;
-  uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
-  if (inreg && beg + lane < end) {
-    const uint2 e = m.edges[beg + lane];
-    rcol = e.x;
-    rh = e.y;
-    if (PER_EDGE) rtm1 = g.tm1[beg + lane];
-  }
-  for (uint32_t t = job.t0; t < job.t1; ++t) {
-    if (!((mybits >> (t - job.t0)) & 1u)) continue;
+__global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
+  const uint32_t lane = threadIdx.x & 63;
+  __shared__ uint32_t pre[kSubLists + 1];
+  const ListIter it = list_iter(m, m.llist, 1, pre);
+  for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
+    const uint32_t e = uni(it.at(idx));
+    const uint32_t v = e / m.ntiles, t = e % m.ntiles;
+    const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
+    const bool inreg = end - beg <= (uint32_t)kWave;
+    uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
+    if (inreg && beg + lane < end) {
+      const uint2 ed = m.edges[beg + lane];
+      rcol = ed.x;
+      rh = ed.y;
+      if (PER_EDGE) rtm1 = g.tm1[beg + lane];
+    }
     TileCtx tc;
     tile_setup(m, t, lane, m.kshift, tc, PER_EDGE);
     int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
@@ -275,52 +322,64 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m, uint32_t 
                                        mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
                                      }
                                    });
+    // v's root per column, found once; every further live smaller
+    // neighbour is joined to it
+    uint32_t rv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      rv[i] = (tc.valid[i] && mn[i] != INT32_MAX) ? find_root(m.M, m.Rs, v, tc.q0 + i) : v;
     for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
                                    [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
 #pragma unroll
                                      for (int i = 0; i < 4; ++i) {
                                        const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
                                        if (live && (int32_t)u != mn[i])
-                                         unite(m.M, m.Rs, v, u, tc.q0 + i);
+                                         rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
                                      }
                                    });
   }
 }
 
-// k_flatten: every non-root entry of a flagged tile is replaced by its root
+// k_flatten: every non-root entry of a listed tile is replaced by its root
 // (plain loads and stores only; a stale value read during the walk is an
-// older ancestor, so every walk still ends at the root).
-__global__ void __launch_bounds__(256) k_flatten(MemoView m, uint32_t chunk, uint32_t wpv) {
-  const WaveJob job = wave_job(m.n, m.ntiles, chunk, wpv);
-  if (!job.ok) return;
-  const uint32_t lane = threadIdx.x & 63, v = job.v;
-  const uint32_t word = uni(m.tmask[(uint64_t)v * m.mwords + (job.t0 >> 5)]);
-  const uint32_t mybits = (word >> (job.t0 & 31)) & (job.t1 - job.t0 >= 32 ? ~0u : ((1u << (job.t1 - job.t0)) - 1));
-  if (!mybits) return;
-  int32_t* row = m.M + (uint64_t)v * m.Rs;
-  for (uint32_t t = job.t0; t < job.t1; ++t) {
-    if (!((mybits >> (t - job.t0)) & 1u)) continue;
+// older ancestor, so every walk still ends at the root).  The four columns
+// of a lane walk together, one load each per step.
+__global__ void __launch_bounds__(256) k_flatten(MemoView m) {
+  const uint32_t lane = threadIdx.x & 63;
+  __shared__ uint32_t pre[kSubLists + 1];
+  const ListIter it = list_iter(m, m.tlist, 0, pre);
+  for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
+    const uint32_t e = uni(it.at(idx));
+    const uint32_t v = e / m.ntiles, t = e % m.ntiles;
+    int32_t* row = m.M + (uint64_t)v * m.Rs;
     const uint32_t q0 = t * kTile + lane * kPerLane;
     const int4 cur = *reinterpret_cast<const int4*>(row + q0);
     int4 out = cur;
     int32_t* o = &out.x;
-    bool changed = false;
+    uint32_t c[4];
+    bool act[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t q = q0 + i;
-      const int32_t val = o[i];
-      if (q >= m.R || val < 0) continue;
-      uint32_t c = (uint32_t)val;
-      while (true) {
-        const int32_t p = m.M[(uint64_t)c * m.Rs + q];
-        if (p < 0) break;
-        c = (uint32_t)p;
-      }
-      if (c != (uint32_t)val) {
-        o[i] = (int32_t)c;
-        changed = true;
+      act[i] = q0 + i < m.R && o[i] >= 0;
+      c[i] = act[i] ? (uint32_t)o[i] : 0u;
+    }
+    while (act[0] || act[1] || act[2] || act[3]) {
+      int32_t p[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p[i] = act[i] ? m.M[(uint64_t)c[i] * m.Rs + q0 + i] : -1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (act[i] && p[i] >= 0) c[i] = (uint32_t)p[i];
+        else act[i] = false;
       }
     }
+    bool changed = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (q0 + i < m.R && o[i] >= 0 && c[i] != (uint32_t)o[i]) {
+        o[i] = (int32_t)c[i];
+        changed = true;
+      }
     if (changed) *reinterpret_cast<int4*>(row + q0) = out;
   }
 }
@@ -344,8 +403,12 @@ __global__ void __launch_bounds__(256) k_count(MemoView m) {
   __syncthreads();
   const uint32_t word = t >> 5, bit = t & 31;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  for (uint32_t v = v0 + wv; v < v1; v += 4) {
-    if (!((uni(m.tmask[(uint64_t)v * m.mwords + word]) >> bit) & 1u)) continue;
+  // 64 vertices' mask words per load; the wave then visits the flagged ones
+  for (uint32_t vb = v0 + wv * 64; vb < v1; vb += 4 * 64) {
+    const uint32_t vl = vb + lane;
+    const bool flagged = vl < v1 && ((m.tmask[(uint64_t)vl * m.mwords + word] >> bit) & 1u);
+    for (uint64_t fm = __ballot(flagged); fm; fm &= fm - 1) {
+    const uint32_t v = vb + (uint32_t)__builtin_ctzll(fm);
     const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + q0);
     const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
 #pragma unroll
@@ -355,6 +418,7 @@ __global__ void __launch_bounds__(256) k_count(MemoView m) {
       if (q >= m.R || c < 0) continue;
       if ((uint32_t)c < kHotRoots) atomicAdd(&hot[c][lane * kPerLane + i], 1u);
       else atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+    }
     }
   }
   __syncthreads();
@@ -372,32 +436,33 @@ __device__ inline uint64_t wave_sum_u64(uint64_t x) {
   return x;
 }
 
-// One wavefront per vertex: mg_v = sum_q |C_q(v)|.
+// mg_v = sum_q |C_q(v)| = R + sum over the listed tiles of v of
+// sum_q (|C_q(v)| - 1): unlisted tiles hold only singleton columns.
+__global__ void k_gain0_init(MemoView m) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < m.n) m.g0[v] = (int64_t)m.R;
+}
+
 __global__ void __launch_bounds__(256) k_gain0(MemoView m) {
-  const uint32_t v = uni((uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-  if (v >= m.n) return;
   const uint32_t lane = threadIdx.x & 63;
-  const int32_t* row = m.M + (uint64_t)v * m.Rs;
-  uint64_t sum = 0;
-  for (uint32_t t = 0; t < m.ntiles; ++t) {
+  __shared__ uint32_t pre[kSubLists + 1];
+  const ListIter it = list_iter(m, m.tlist, 0, pre);
+  for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
+    const uint32_t e = uni(it.at(idx));
+    const uint32_t v = e / m.ntiles, t = e % m.ntiles;
     const uint32_t q0 = t * kTile + lane * kPerLane;
-    const uint32_t bit = (uni(m.tmask[(uint64_t)v * m.mwords + (t >> 5)]) >> (t & 31)) & 1u;
-    if (!bit) {
-      sum += (uint64_t)min(max((int32_t)m.R - (int32_t)q0, 0), 4);
-      continue;
-    }
-    const int4 cur = *reinterpret_cast<const int4*>(row + q0);
+    const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + q0);
     const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+    int32_t sz[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t q = q0 + i;
-      if (q >= m.R) continue;
       const int32_t val = vals[i];
-      sum += (uint64_t)(val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q]);
+      sz[i] = (q0 + i >= m.R) ? 1 : (val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q0 + i]);
     }
+    uint64_t sum = (uint64_t)(sz[0] - 1) + (uint64_t)(sz[1] - 1) + (uint64_t)(sz[2] - 1) + (uint64_t)(sz[3] - 1);
+    sum = wave_sum_u64(sum);
+    if (lane == 0 && sum) atomicAdd((unsigned long long*)&m.g0[v], (unsigned long long)sum);
   }
-  sum = wave_sum_u64(sum);
-  if (lane == 0) m.g0[v] = (int64_t)sum;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value) {
@@ -432,17 +497,18 @@ void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk, hipStrea
     hipLaunchKernelGGL(k_hook<false>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
 }
 
+
 void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
-  const uint32_t wpv = waves_per_vertex(m, chunk);
+  (void)chunk;
   if (g.tm1)
-    hipLaunchKernelGGL(k_link<true>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+    hipLaunchKernelGGL(k_link<true>, dim3(kListBlocks), dim3(256), 0, st, g, m);
   else
-    hipLaunchKernelGGL(k_link<false>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+    hipLaunchKernelGGL(k_link<false>, dim3(kListBlocks), dim3(256), 0, st, g, m);
 }
 
 void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {
-  const uint32_t wpv = waves_per_vertex(m, chunk);
-  hipLaunchKernelGGL(k_flatten, grid_for(m.n, wpv), dim3(256), 0, st, m, chunk, wpv);
+  (void)chunk;
+  hipLaunchKernelGGL(k_flatten, dim3(kListBlocks), dim3(256), 0, st, m);
 }
 
 void launch_count(const MemoView& m, hipStream_t st) {
@@ -451,7 +517,8 @@ void launch_count(const MemoView& m, hipStream_t st) {
 }
 
 void launch_gain0(const MemoView& m, hipStream_t st) {
-  hipLaunchKernelGGL(k_gain0, dim3((m.n + 3) / 4), dim3(256), 0, st, m);
+  hipLaunchKernelGGL(k_gain0_init, dim3((m.n + 255) / 256), dim3(256), 0, st, m);
+  hipLaunchKernelGGL(k_gain0, dim3(kListBlocks), dim3(256), 0, st, m);
 }
 
 }  // namespace infuse

@@ -25,13 +25,34 @@ namespace infuse {
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Cross-block hand-off inside a kernel.  Data another block reads later in
+// the same kernel is written with atomics or write-through (agent-scope)
+// stores; before taking a ticket the writer waits until its memory
+// operations completed (on GFX9 vmcnt counts stores and atomics too), and
+// the last block reads with agent-scope loads.  An agent-scope fence would
+// instead write back and invalidate the whole XCD L2 in every block.
+__device__ inline void wait_memory_ops() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Wave-wide maximum of a 64-bit value with DPP row shifts and row
+// broadcasts (no LDS round trips): lane 63 ends with the maximum, which is
+// then read as a scalar.
+template <int CTRL, int ROW_MASK>
+__device__ inline uint64_t dpp_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)x, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(x >> 32), CTRL, ROW_MASK, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 __device__ inline uint64_t wave_max_u64(uint64_t x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint64_t y = __shfl_xor(x, off);
-    x = y > x ? y : x;
-  }
-  return x;
+  x = umax64(x, dpp_u64<0x111, 0xF>(x));  // row_shr:1
+  x = umax64(x, dpp_u64<0x112, 0xF>(x));  // row_shr:2
+  x = umax64(x, dpp_u64<0x114, 0xF>(x));  // row_shr:4
+  x = umax64(x, dpp_u64<0x118, 0xF>(x));  // row_shr:8
+  x = umax64(x, dpp_u64<0x142, 0xA>(x));  // row_bcast:15
+  x = umax64(x, dpp_u64<0x143, 0xC>(x));  // row_bcast:31
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
 }
 __device__ inline uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
@@ -78,10 +99,34 @@ __device__ inline uint64_t eval_tile(const CelfView& c, uint32_t u, uint32_t t, 
 __device__ void commit_block(const CelfView& c, uint64_t k) {
   const MemoView& m = c.m;
   const uint32_t id = key_id(c, k);
-  for (uint32_t q = threadIdx.x; q < m.R; q += blockDim.x) {
-    const int32_t val = m.M[(uint64_t)id * m.Rs + q];
-    const uint32_t root = val < 0 ? id : (uint32_t)val;
-    atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
+  // 32 consecutive columns share a coverage word; when they also share the
+  // root (always for singleton columns, mostly for a large component) one
+  // atomic sets all their bits
+  const uint32_t lane = threadIdx.x & 63;
+  constexpr int kBatch = 8;  // loads issued together before their atomics
+  for (uint32_t qb = 0; qb < m.R; qb += kBatch * blockDim.x) {
+    int32_t vals[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint32_t q = qb + b * blockDim.x + threadIdx.x;
+      vals[b] = q < m.R ? m.M[(uint64_t)id * m.Rs + q] : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const uint32_t q = qb + b * blockDim.x + threadIdx.x;
+      const bool valid = q < m.R;
+      const int32_t val = vals[b];
+      const uint32_t root = val < 0 ? id : (uint32_t)val;
+      const uint32_t r0 = __shfl(root, lane & ~31u);
+      const uint32_t sh = lane & 32u;
+      const uint32_t same = (uint32_t)(__ballot(valid && root == r0) >> sh);
+      const uint32_t vm = (uint32_t)(__ballot(valid) >> sh);
+      if (same == vm) {
+        if ((lane & 31) == 0 && vm) atomicOr(&c.cov[(uint64_t)r0 * c.cwords + (q >> 5)], vm);
+      } else if (valid) {
+        atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -89,7 +134,6 @@ __device__ void commit_block(const CelfView& c, uint64_t k) {
     c.seeds[s] = id;
     c.marginal[s] = (int64_t)key_gain(c, k);
     c.key[id] = 0;
-    __threadfence();
     c.st->s = s + 1;
   }
 }
@@ -133,27 +177,31 @@ __global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
     uint64_t l2 = ~0ull;
     for (uint32_t it = 0; it < W1; ++it) {
       l2 = next_below(mk, cnt, l2);
-      if (lane == 0) c.lists[(uint64_t)blockIdx.x * W1 + it] = l2;
+      if (lane == 0)
+        __hip_atomic_store(&c.lists[(uint64_t)blockIdx.x * W1 + it], l2, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    wait_memory_ops();
     last_block = atomicAdd(&c.st->ticket1, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (!last_block) return;
-  __threadfence();
-  // final merge over gridDim.x * W1 keys: W1 rounds of "largest key below
-  // the previous one" with a block reduction
-  const uint64_t total = (uint64_t)gridDim.x * W1;
+  // final merge over gridDim.x * W1 keys: every thread loads its share once
+  // (all loads in flight together), then W1 rounds of "largest key below the
+  // previous one" with a block reduction
+  constexpr int kMaxPerThread = 32;
+  const uint32_t total = gridDim.x * W1;
+  uint64_t mine[kMaxPerThread];
+  int cnt = 0;
+  for (uint32_t i = threadIdx.x; i < total && cnt < kMaxPerThread; i += blockDim.x)
+    mine[cnt++] = __hip_atomic_load(&c.lists[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint64_t prev = ~0ull;
   for (uint32_t it = 0; it < W1; ++it) {
     uint64_t best = 0;
-    for (uint64_t i = threadIdx.x; i < total; i += blockDim.x) {
-      const uint64_t k = __hip_atomic_load(&c.lists[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      best = (k < prev && k > best) ? k : best;
-    }
+    for (int i = 0; i < cnt; ++i) best = (mine[i] < prev && mine[i] > best) ? mine[i] : best;
     best = wave_max_u64(best);
     if (lane == 0) red[wv] = best;
     __syncthreads();
@@ -184,7 +232,6 @@ __global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
     for (uint32_t j = 0; j < c.W; ++j) nc += c.cand[j] != kInvalid ? 1u : 0u;
     c.st->ncand = nc;
     c.st->ticket1 = 0;
-    __threadfence();
   }
 }
 
@@ -212,28 +259,41 @@ __global__ void __launch_bounds__(256) k_celf_eval(CelfView c, uint32_t nchunks)
     }
   }
   if (threadIdx.x == 0) {
-    __threadfence();
+    wait_memory_ops();
     last_block = atomicAdd(&c.st->ticket2, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (!last_block) return;
-  __threadfence();
   __shared__ uint64_t best_sh;
   __shared__ uint32_t bulk_sh;
-  if (threadIdx.x == 0) {
-    uint64_t best = 0;
-    uint64_t ev = 0;
-    for (uint32_t j = 0; j < c.W; ++j) {
-      const uint32_t u = c.cand[j];
-      if (u == kInvalid) continue;
+  __shared__ uint64_t ck[64];
+  __shared__ uint32_t cev[64];
+  // candidate j is finished by thread j: all its loads are in flight together
+  if (threadIdx.x < c.W) {
+    const uint32_t j = threadIdx.x;
+    const uint32_t u = c.cand[j];
+    uint64_t k = 0;
+    uint32_t e = 0;
+    if (u != kInvalid) {
       if (c.iter[u] != s) {
         const uint64_t g = __hip_atomic_load(&c.candgain[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        c.key[u] = make_key(c, g, u);
+        k = make_key(c, g, u);
+        c.key[u] = k;
         c.iter[u] = s;
-        ++ev;
+        e = 1;
+      } else {
+        k = c.key[u];
       }
-      const uint64_t k = c.key[u];
-      best = k > best ? k : best;
+    }
+    ck[j] = k;
+    cev[j] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t best = 0, ev = 0;
+    for (uint32_t j = 0; j < c.W; ++j) {
+      best = ck[j] > best ? ck[j] : best;
+      ev += cev[j];
     }
     c.st->evals += ev;
     c.st->ticket2 = 0;
@@ -243,54 +303,57 @@ __global__ void __launch_bounds__(256) k_celf_eval(CelfView c, uint32_t nchunks)
     if (bulk_sh) {
       c.st->kstar = best;
       c.st->bulk_best = best;
+      c.st->bulk_rounds += 1;
     }
     best_sh = best;
-    __threadfence();
   }
   __syncthreads();
   if (!bulk_sh) commit_block(c, best_sh);
 }
 
+// One wavefront per vertex (grid-stride over vertices), no block barriers.
 __global__ void __launch_bounds__(256) k_celf_bulk(CelfView c) {
   if (c.st->s >= c.K || !c.st->need_bulk) return;
   __shared__ uint32_t last_block;
-  __shared__ uint64_t evs[4];
+  __shared__ uint64_t wbest[4], wev[4];
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t s = c.st->s;
   const uint64_t kstar = c.st->kstar;
-  const uint32_t nw = gridDim.x * 4;
   uint64_t ev = 0, best = 0;
+  const uint32_t nw = gridDim.x * 4;
   for (uint32_t v = blockIdx.x * 4 + wv; v < c.m.n; v += nw) {
     const uint64_t k = c.key[v];
     if (k <= kstar) continue;
-    uint64_t nk = k;
-    if (c.iter[v] != s) {
-      uint64_t sum = 0;
-      for (uint32_t t = 0; t < c.m.ntiles; ++t) sum += eval_tile(c, v, t, lane);
-      sum = wave_sum_u64(sum);
-      nk = make_key(c, sum, v);
-      if (lane == 0) {
-        c.key[v] = nk;
-        c.iter[v] = s;
-      }
-      ++ev;
+    if (c.iter[v] == s) {
+      best = k > best ? k : best;
+      continue;
+    }
+    uint64_t sum = 0;
+    for (uint32_t t = 0; t < c.m.ntiles; ++t) sum += eval_tile(c, v, t, lane);
+    sum = wave_sum_u64(sum);
+    const uint64_t nk = make_key(c, sum, v);
+    if (lane == 0) {
+      c.key[v] = nk;
+      c.iter[v] = s;
     }
     best = nk > best ? nk : best;
+    ++ev;
   }
   if (lane == 0) {
-    if (best) atomicMax((unsigned long long*)&c.st->bulk_best, (unsigned long long)best);
-    evs[wv] = ev;
+    wbest[wv] = best;
+    wev[wv] = ev;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint64_t e = evs[0] + evs[1] + evs[2] + evs[3];
-    if (e) atomicAdd((unsigned long long*)&c.st->evals, (unsigned long long)e);
-    __threadfence();
+    best = umax64(umax64(wbest[0], wbest[1]), umax64(wbest[2], wbest[3]));
+    ev = wev[0] + wev[1] + wev[2] + wev[3];
+    if (best) atomicMax((unsigned long long*)&c.st->bulk_best, (unsigned long long)best);
+    if (ev) atomicAdd((unsigned long long*)&c.st->evals, (unsigned long long)ev);
+    wait_memory_ops();
     last_block = atomicAdd(&c.st->ticket3, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (!last_block) return;
-  __threadfence();
   __shared__ uint64_t k_sh;
   if (threadIdx.x == 0) {
     k_sh = __hip_atomic_load(&c.st->bulk_best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -321,11 +384,23 @@ void launch_celf_init(const CelfView& c, hipStream_t st) {
   hipLaunchKernelGGL(k_celf_init, dim3((c.m.n + 255) / 256), dim3(256), 0, st, c);
 }
 
-void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st) {
+void launch_celf_topw(const CelfView& c, hipStream_t st) {
   hipLaunchKernelGGL(k_celf_topw, dim3(celf_topw_blocks(c.m.n)), dim3(256), 0, st, c);
+}
+
+void launch_celf_eval(const CelfView& c, hipStream_t st) {
   const uint32_t nchunks = (c.m.Rs + kEvalCols - 1) / kEvalCols;
   hipLaunchKernelGGL(k_celf_eval, dim3(c.W * nchunks), dim3(256), 0, st, c, nchunks);
+}
+
+void launch_celf_bulk(const CelfView& c, uint32_t bulk_blocks, hipStream_t st) {
   hipLaunchKernelGGL(k_celf_bulk, dim3(bulk_blocks), dim3(256), 0, st, c);
+}
+
+void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st) {
+  launch_celf_topw(c, st);
+  launch_celf_eval(c, st);
+  launch_celf_bulk(c, bulk_blocks, st);
 }
 
 

@@ -77,9 +77,28 @@ struct MemoView {
   const uint32_t* xs;   // [Rs] X of column q (ascending for q < R)
   int32_t* M;           // [n][Rs]
   uint32_t* tmask;      // [n][mwords]  tile may hold a non-singleton column
-  uint32_t* lmask;      // [n][mwords]  tile needs the link pass
   int64_t* g0;          // [n]
+  // work lists written by k_hook, entries v * ntiles + t, split into
+  // kSubLists sub-lists (by hook workgroup) of capacity list_cap each so
+  // that appends do not all hit one counter:
+  uint32_t* tlist;      // tiles with a candidate edge (k_flatten, k_gain0)
+  uint32_t* llist;      // tiles with a column of two or more live smaller
+                        // neighbours (k_link)
+  uint32_t* counts;     // [2 * j] = |tlist_j|, [2 * j + 1] = |llist_j|
+  uint32_t list_cap;
 };
+
+constexpr uint32_t kSubLists = 256;
+constexpr uint32_t kListBlocks = 8192;  // fixed grid of the list kernels (multiple of kSubLists)
+
+// Capacity of one sub-list.  Hook workgroup b (4 wavefronts of at most 32
+// tiles, blocks = ceil(n * wpv / 4) with wpv * chunk < ntiles + chunk)
+// writes at most 128 entries to sub-list b % kSubLists, and a sub-list
+// serves at most n * wpv / 1024 + 2 workgroups, so it receives at most
+// n * (ntiles + 31) / 256 + 256 entries.
+inline uint32_t list_capacity(uint32_t n, uint32_t ntiles) {
+  return (uint32_t)(((uint64_t)n * (ntiles + 32) + kSubLists - 1) / kSubLists + 512);
+}
 
 struct CelfState {
   uint32_t s;          // |S|
@@ -90,6 +109,7 @@ struct CelfState {
   uint64_t kstar;
   uint64_t bulk_best;
   uint64_t evals;
+  uint64_t bulk_rounds;
 };
 
 struct CelfView {

@@ -23,6 +23,9 @@ void launch_gain0(const MemoView& m, hipStream_t st);
 uint32_t celf_topw_blocks(uint32_t n);
 void launch_celf_init(const CelfView& c, hipStream_t st);
 void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
+void launch_celf_topw(const CelfView& c, hipStream_t st);
+void launch_celf_eval(const CelfView& c, hipStream_t st);
+void launch_celf_bulk(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 
 // query.hip
 uint32_t sigma_pair_max();

@@ -36,8 +36,11 @@ struct Memo {
   uint64_t* scratch = nullptr;
   int32_t* M = nullptr;
   uint32_t* tmask = nullptr;
-  uint32_t* lmask = nullptr;
   int64_t* g0 = nullptr;
+  uint32_t* tlist = nullptr;
+  uint32_t* llist = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t list_cap = 0;
   uint64_t last_use = 0;
   int pins = 0;
   hipEvent_t ready_ev = nullptr;  // recorded after construction
@@ -72,7 +75,7 @@ im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hi
 // Records HIP events around a launch on `st` when profiling is on.
 class KTimer {
  public:
-  KTimer(im_ctx* c, const char* name, hipStream_t st);
+  KTimer(im_ctx* c, const char* name, hipStream_t st, int level = 1);
   ~KTimer();
 
  private:
@@ -80,6 +83,7 @@ class KTimer {
   const char* name_;
   hipStream_t st_;
   hipEvent_t a_ = nullptr, b_ = nullptr;
+  bool on_ = false;
 };
 
 }  // namespace infuse
@@ -94,8 +98,9 @@ struct im_ctx {
   uint64_t in_use = 0;
   uint64_t use_clock = 0;
   uint64_t evictions = 0;
+  uint64_t last_bulk_rounds = 0;
   im_tuning tune = {};
-  bool profiling = false;
+  int profiling = 0;  // 0 off, 1 per-build kernels, 2 also CELF rounds
   std::vector<infuse::PendingEvent> pending;
   std::map<std::string, std::pair<uint64_t, double>> kstats;
   std::vector<im_graph*> graphs;

@@ -123,15 +123,16 @@ void ctx_free(im_ctx* c, void* p) {
 // kernel timing
 // ---------------------------------------------------------------------------
 
-KTimer::KTimer(im_ctx* c, const char* name, hipStream_t st) : c_(c), name_(name), st_(st) {
-  if (!c_->profiling) return;
+KTimer::KTimer(im_ctx* c, const char* name, hipStream_t st, int level)
+    : c_(c), name_(name), st_(st), on_(c->profiling >= level) {
+  if (!on_) return;
   (void)hipEventCreate(&a_);
   (void)hipEventCreate(&b_);
   (void)hipEventRecord(a_, st_);
 }
 
 KTimer::~KTimer() {
-  if (!c_->profiling) return;
+  if (!on_) return;
   (void)hipEventRecord(b_, st_);
   std::lock_guard<std::recursive_mutex> lk(c_->mu);
   c_->pending.push_back({name_, a_, b_});
@@ -177,8 +178,11 @@ MemoView Memo::view(const im_graph* g) const {
   v.xs = xs;
   v.M = M;
   v.tmask = tmask;
-  v.lmask = lmask;
   v.g0 = g0;
+  v.tlist = tlist;
+  v.llist = llist;
+  v.counts = counts;
+  v.list_cap = list_cap;
   return v;
 }
 
@@ -201,8 +205,10 @@ uint64_t memo_bytes(const im_graph* g, uint32_t R) {
   b += align256((size_t)Rs * 4) * 2 + align256((size_t)R * 4);
   b += align256((size_t)x_sort_scratch_elems(R) * 8);
   b += align256((size_t)g->n * Rs * 4);
-  b += align256((size_t)g->n * mwords * 4) * 2;
+  b += align256((size_t)g->n * mwords * 4);
   b += align256((size_t)g->n * 8);
+  b += align256((size_t)list_capacity(g->n, ntiles) * kSubLists * 4) * 2;
+  b += align256((size_t)kSubLists * 2 * 4);
   return b;
 }
 
@@ -248,8 +254,11 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->scratch = reinterpret_cast<uint64_t*>(take((size_t)x_sort_scratch_elems(R) * 8));
   m->M = reinterpret_cast<int32_t*>(take((size_t)g->n * m->Rs * 4));
   m->tmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
-  m->lmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
   m->g0 = reinterpret_cast<int64_t*>(take((size_t)g->n * 8));
+  m->list_cap = list_capacity(g->n, m->ntiles);
+  m->tlist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
+  m->llist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
+  m->counts = reinterpret_cast<uint32_t*>(take((size_t)kSubLists * 2 * 4));
   {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     g->memos.push_back(m);
@@ -269,7 +278,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
   }
   launch_fill_u32(m->tmask, (uint64_t)g->n * m->mwords, 0u, st);
-  launch_fill_u32(m->lmask, (uint64_t)g->n * m->mwords, 0u, st);
+  launch_fill_u32(m->counts, kSubLists * 2, 0u, st);
   if (timed) (void)hipEventRecord(g->ev[1], st);
   {
     KTimer t(c, "hook", st);
@@ -341,6 +350,11 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   const uint32_t n = g->n;
   const uint32_t cwords = m->Rs / 32;
   const uint32_t tb = celf_topw_blocks(n);
+  // the last top-W block merges tb * (W + 1) keys held in registers (at most
+  // 8192); the width only changes how many candidates a round evaluates
+  const uint32_t wmax = 8192 / tb;
+  if (wmax < 2) return fail(IM_ERR_INVALID_ARG, "graph too large for on-device CELF (n > 2^22)");
+  W = std::max(1u, std::min(W, wmax - 1));
   size_t b = 0;
   b += align256((size_t)n * 8);
   b += align256((size_t)n * 4);
@@ -382,10 +396,20 @@ void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   const CelfView& v = cb->v;
   launch_fill_u32(v.cov, (uint64_t)v.m.n * v.cwords, 0u, st);
   launch_celf_init(v, st);
-  const uint32_t bulk_blocks = std::max(1u, std::min(2048u, (v.m.n + 3) / 4));
+  const uint32_t bulk_blocks = std::max(1u, std::min(2048u, v.m.n));
   for (uint32_t k = 0; k < v.K; ++k) {
-    KTimer t(c, "celf_step", st);
-    launch_celf_step(v, bulk_blocks, st);
+    {
+      KTimer t(c, "celf_topw", st, 2);
+      launch_celf_topw(v, st);
+    }
+    {
+      KTimer t(c, "celf_eval", st, 2);
+      launch_celf_eval(v, st);
+    }
+    {
+      KTimer t(c, "celf_bulk", st, 2);
+      launch_celf_bulk(v, bulk_blocks, st);
+    }
   }
 }
 
@@ -405,7 +429,7 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
   for (uint32_t i = 0; i < v.K; ++i) tot += marginal[i];
   if (cover) *cover = tot;
   if (evals) *evals = hs.evals;
-  (void)c;
+  c->last_bulk_rounds = hs.bulk_rounds;
   return IM_OK;
 }
 
@@ -481,9 +505,10 @@ extern "C" im_status im_get_tuning(const im_ctx* c, im_tuning* t) {
   return IM_OK;
 }
 
-extern "C" im_status im_set_profiling(im_ctx* c, int enabled) {
+extern "C" im_status im_set_profiling(im_ctx* c, int level) {
   if (!c) return fail(IM_ERR_INVALID_ARG, "NULL context");
-  c->profiling = enabled != 0;
+  if (level < 0 || level > 2) return fail(IM_ERR_INVALID_ARG, "profiling level must be 0, 1 or 2");
+  c->profiling = level;
   return IM_OK;
 }
 
@@ -631,6 +656,9 @@ im_status infuse::check_params(const im_graph* g, double p, uint32_t R) {
   if (lim >> 64) return fail(IM_ERR_INVALID_ARG, "n*R too large for 64-bit CELF keys");
   const unsigned __int128 words = (unsigned __int128)g->n * round_up(R, kTile);
   if (words >> 40) return fail(IM_ERR_INVALID_ARG, "memo larger than 4 TiB");
+  // work-list entries are v * ntiles + t in 32 bits
+  if ((uint64_t)g->n * (round_up(R, kTile) / kTile) >= (1ull << 32))
+    return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) must be below 2^32");
   return IM_OK;
 }
 
