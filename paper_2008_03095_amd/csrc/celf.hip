@@ -140,15 +140,21 @@ __device__ void commit_block(const CelfView& c, uint64_t k) {
 
 constexpr int kTopPerLane = 16;  // keys per lane in k_celf_topw
 
-// Largest key below `last` among this lane's keys, then over the wave.
-__device__ inline uint64_t next_below(const uint64_t* kk, int cnt, uint64_t last) {
+// Largest key below `last` among a lane's CNT keys (compile-time count, so
+// the array stays in registers), then over the wave.
+template <int CNT>
+__device__ inline uint64_t next_below(const uint64_t (&kk)[CNT], uint64_t last) {
   uint64_t best = 0;
-  for (int i = 0; i < cnt; ++i) {
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
     const uint64_t k = kk[i];
     best = (k < last && k > best) ? k : best;
   }
   return wave_max_u64(best);
 }
+
+constexpr int kWaveMergePerLane = 5;     // 4 lists of <= 65 keys over 64 lanes
+constexpr int kFinalMergePerThread = 32; // <= 8192 keys over 256 threads
 
 __global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
   if (c.st->s >= c.K) return;
@@ -166,17 +172,20 @@ __global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
   }
   uint64_t last = ~0ull;
   for (uint32_t it = 0; it < W1; ++it) {
-    last = next_below(kk, kTopPerLane, last);
+    last = next_below(kk, last);
     if (lane == 0) wl[wv][it] = last;
   }
   __syncthreads();
   if (wv == 0) {  // merge the 4 wave lists
-    uint64_t mk[5];
-    int cnt = 0;
-    for (uint32_t i = lane; i < 4 * W1; i += 64) mk[cnt++] = wl[i / W1][i % W1];
+    uint64_t mk[kWaveMergePerLane];
+#pragma unroll
+    for (int j = 0; j < kWaveMergePerLane; ++j) {
+      const uint32_t i = lane + 64 * j;
+      mk[j] = i < 4 * W1 ? wl[i / W1][i % W1] : 0;
+    }
     uint64_t l2 = ~0ull;
     for (uint32_t it = 0; it < W1; ++it) {
-      l2 = next_below(mk, cnt, l2);
+      l2 = next_below(mk, l2);
       if (lane == 0)
         __hip_atomic_store(&c.lists[(uint64_t)blockIdx.x * W1 + it], l2, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -189,20 +198,19 @@ __global__ void __launch_bounds__(256) k_celf_topw(CelfView c) {
   }
   __syncthreads();
   if (!last_block) return;
-  // final merge over gridDim.x * W1 keys: every thread loads its share once
-  // (all loads in flight together), then W1 rounds of "largest key below the
-  // previous one" with a block reduction
-  constexpr int kMaxPerThread = 32;
+  // final merge over gridDim.x * W1 (<= 8192) keys: every thread loads its
+  // share once (all loads in flight together), then W1 rounds of "largest
+  // key below the previous one" with a block reduction
   const uint32_t total = gridDim.x * W1;
-  uint64_t mine[kMaxPerThread];
-  int cnt = 0;
-  for (uint32_t i = threadIdx.x; i < total && cnt < kMaxPerThread; i += blockDim.x)
-    mine[cnt++] = __hip_atomic_load(&c.lists[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t mine[kFinalMergePerThread];
+#pragma unroll
+  for (int j = 0; j < kFinalMergePerThread; ++j) {
+    const uint32_t i = threadIdx.x + 256 * j;
+    mine[j] = i < total ? __hip_atomic_load(&c.lists[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  }
   uint64_t prev = ~0ull;
   for (uint32_t it = 0; it < W1; ++it) {
-    uint64_t best = 0;
-    for (int i = 0; i < cnt; ++i) best = (mine[i] < prev && mine[i] > best) ? mine[i] : best;
-    best = wave_max_u64(best);
+    const uint64_t best = next_below(mine, prev);
     if (lane == 0) red[wv] = best;
     __syncthreads();
     uint64_t b = red[0];
