@@ -465,7 +465,7 @@ extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator*
     }
     c->own_stream = true;
   }
-  c->tune.cc_chunk = 2048;
+  c->tune.cc_chunk = 1024;
   c->tune.celf_width = 16;
   c->tune.use_graphs = 0;
   *out = c;
