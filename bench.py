@@ -167,9 +167,11 @@ def main():
     traffic = read_traffic()
     phases /= args.steps
     t_cc = phases[1]
-    stats = {k: ctx.kernel_stats(k) for k in ("edge_hash", "x_sort", "hook", "link", "flatten",
-                                               "count", "gain0", "sigma", "celf_topw",
-                                               "celf_eval", "celf_bulk")}
+    names = ["edge_hash", "x_sort", "hook", "link", "flatten", "count", "gain0", "sigma", "celf",
+             "celf_topw", "celf_eval", "celf_bulk"]
+    if args.profile_celf:
+        names += ["celf.barrier", "celf.eval", "celf.pool", "celf.rebuild", "celf.bulk"]
+    stats = {k: ctx.kernel_stats(k) for k in names}
     rec = {
         "metric": METRIC,
         "value": value,
@@ -192,6 +194,7 @@ def main():
         "celf_evals": G.celf_evals(),
         "cover_count": cover,
         "kernel_avg_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in stats.items()},
+        "kernel_launches_per_step": {k: v[0] / args.steps for k, v in stats.items()},
         "kernel_total_ms_per_step": {k: v[1] / args.steps for k, v in stats.items()},
         "roofline": {
             "bound": "hbm",

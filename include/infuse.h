@@ -159,12 +159,16 @@ uint64_t im_graph_nnz(const im_graph *g);
  *   cc_chunk    simulations handled by one wavefront per vertex in the
  *               labelling kernels (multiple of 256)
  *   celf_width  candidates re-evaluated together per CELF round
- *   use_graphs  1 = replay CELF rounds from a captured hipGraph             */
+ *   use_graphs  1 = replay CELF rounds from a captured hipGraph
+ *   celf_mode   1 = all greedy steps in one persistent cooperative kernel
+ *               (default where the device supports cooperative launch),
+ *               2 = one launch per step and phase                            */
 typedef struct {
     uint32_t cc_chunk;
     uint32_t celf_width;
     uint32_t use_graphs;
-    uint32_t reserved[5];
+    uint32_t celf_mode;
+    uint32_t reserved[4];
 } im_tuning;
 im_status im_set_tuning(im_ctx *ctx, const im_tuning *t);
 im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);

@@ -26,17 +26,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     if (K[i]) st = celf_alloc(graphs[i], memos[i], K[i], c->tune.celf_width, &cbs[i]);
   if (st == IM_OK) {
     for (uint32_t i = 0; i < ng; ++i)
-      if (K[i]) {
-        launch_fill_u32(cbs[i].v.cov, (uint64_t)cbs[i].v.m.n * cbs[i].v.cwords, 0u, c->stream);
-        launch_celf_init(cbs[i].v, c->stream);
-      }
-    const uint32_t kmax = ng ? *std::max_element(K, K + ng) : 0;
-    for (uint32_t k = 0; k < kmax; ++k)
-      for (uint32_t i = 0; i < ng; ++i)
-        if (k < K[i]) {
-          const uint32_t bulk_blocks = std::max(1u, std::min(2048u, graphs[i]->n));
-          launch_celf_step(cbs[i].v, bulk_blocks, c->stream);
-        }
+      if (K[i]) celf_enqueue(c, &cbs[i], c->stream);
     for (uint32_t i = 0; i < ng && st == IM_OK; ++i) {
       if (!K[i]) {
         if (cover) cover[i] = 0;

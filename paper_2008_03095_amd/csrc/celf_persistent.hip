@@ -1,0 +1,753 @@
+// CELF on the memo (Algorithm 7) as one persistent, cooperative kernel.
+//
+// A grid of co-resident workgroups runs all K greedy steps.  Keys pack the
+// gain above the id bits (larger id = smaller key), so key order is gain
+// descending, then id ascending.  A key computed for the current |S| is
+// "fresh" and exact; older keys are upper bounds (the coverage objective is
+// submodular).  Every workgroup holds the same candidate pool in LDS, in two
+// parts:
+//   S  stale entries, sorted by key, consumed from the front (head);
+//   F  entries re-evaluated in this step, unsorted, with their maximum;
+// and out_bound, at least every key outside the pool.  Per step:
+//   * max F above the S front and above out_bound -> commit it (the exact
+//     maximiser, as in lazy greedy);
+//   * else, S front above out_bound -> evaluate the next W entries of S with
+//     the whole grid (W starts at one grid's worth of candidates and doubles
+//     within the step), move them to F;
+//   * else (the largest key is outside the pool) -> rebuild the pool; if
+//     that already happened in this step, first evaluate every stale vertex
+//     whose key exceeds max F at once (bulk), with the whole grid.
+// On commit, the rest of F is sorted and merged back into S.  All workgroups
+// decide from identical data, so only gains, coverage bits and keys cross
+// workgroups.  Evaluations also test the last committed seed's component
+// directly, so a commit needs no barrier before the next round.
+//
+// Rebuild: a radix select (11-bit digits from the top bit of the largest
+// key) finds a threshold above which at most kPool keys lie, the keys above
+// it are collected and split into S (sorted) and F.
+//
+// Memory rules (the XCD L2 caches are not coherent with each other inside a
+// kernel): data written during the kernel and read by another workgroup goes
+// through device-scope atomics or agent-scope stores and is read with
+// agent-scope loads; the memo is read-only here.  Grid barriers are
+// hierarchical (16 arrival counters, then one) and give up after a time
+// limit: they raise an error flag and every workgroup returns.
+#include "common.h"
+
+namespace infuse {
+
+constexpr uint32_t kPool = 2048;               // pool entries per workgroup
+constexpr uint32_t kPBlock = 256;              // threads per workgroup
+constexpr uint32_t kPer = kPool / kPBlock;     // pool entries per thread
+constexpr uint32_t kMaxCand = 1024;            // evaluations per round
+constexpr uint32_t kGroups = 16;               // barrier arrival groups
+constexpr uint32_t kDigitBits = 11;
+constexpr uint32_t kBins = 1u << kDigitBits;
+constexpr uint64_t kSpinTicks = 200000000;     // 2 s of the 100 MHz clock
+constexpr uint64_t kRunTicks = 3000000000ull;  // 30 s
+
+// Device scratch of one run (zeroed by the host before the launch).
+struct PCelfScratch {
+  uint32_t err;  // 1 barrier time-out, 2 inconsistent state, 4 run time-out
+  uint32_t pool_cnt;
+  uint32_t bulk_cnt;
+  uint32_t pad0;
+  uint64_t out_bound;
+  uint64_t kmax;
+  uint64_t pad1[4];
+  uint64_t prof[8];                   // workgroup 0's phase clock, then counts
+  uint32_t arrive[kGroups][32];       // one 128-byte line per group
+  uint32_t top[32];
+  uint32_t release[kGroups][32];
+  uint64_t gains[3][kMaxCand];        // per-round candidate gains, rotated
+  uint32_t hist[kBins];
+  uint32_t pool_id[kPool];
+  uint64_t pool_key[kPool];
+};
+
+struct PCelfArgs {
+  CelfView c;
+  PCelfScratch* x;
+  uint32_t* blist;   // [n] bulk candidates
+  uint64_t* bgain;   // [n] their gains
+  uint32_t w0;       // candidates of the first round of a step
+};
+
+__device__ inline uint32_t p_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline void p_wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ inline uint64_t ld64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ld32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t p_wsum(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+__device__ inline uint64_t p_wmax(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t y = __shfl_xor(x, off);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Phase clock of a workgroup (100 MHz real-time counter); workgroup 0
+// reports it.
+struct PClock {
+  enum { kBarrier = 0, kEval = 1, kPoolOps = 2, kRebuild = 3, kBulk = 4, kPhases = 5 };
+  uint64_t acc[kPhases];
+  uint64_t mark;
+  uint32_t barriers, rounds, rebuilds, bulks;
+  __device__ void start() {
+    for (int i = 0; i < kPhases; ++i) acc[i] = 0;
+    barriers = rounds = rebuilds = bulks = 0;
+    mark = __builtin_amdgcn_s_memrealtime();
+  }
+  __device__ void lap(int phase) {
+    const uint64_t t = __builtin_amdgcn_s_memrealtime();
+    acc[phase] += t - mark;
+    mark = t;
+  }
+};
+
+struct PoolLds {
+  uint64_t skey[kPool];  // S: stale, sorted descending
+  uint32_t sid[kPool];
+  uint64_t fkey[kPool];  // F: fresh this step, unsorted
+  uint32_t fid[kPool];
+  uint32_t wsum[kPBlock / 64];
+  uint64_t wmax[kPBlock / 64];
+  uint32_t hist[kBins];
+  uint32_t ns, head, nf, fbest;  // S size, S front, F size, index of max F
+  uint64_t out_bound;
+  uint64_t prefix;
+  uint32_t want, cap, done, shift, width;
+};
+
+// Exclusive prefix sum over the workgroup; `total` receives the sum.
+__device__ uint32_t block_exscan(PoolLds& L, uint32_t v, uint32_t& total) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  if (lane == 63) L.wsum[wv] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kPBlock / 64; ++i) {
+    const uint32_t w = L.wsum[i];
+    base += i < wv ? w : 0;
+    tot += w;
+  }
+  __syncthreads();
+  total = tot;
+  return base + x - v;
+}
+
+// Maximum over the workgroup.
+__device__ uint64_t block_max(PoolLds& L, uint64_t v) {
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = p_wmax(v);
+  if (lane == 0) L.wmax[wv] = v;
+  __syncthreads();
+  uint64_t m = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kPBlock / 64; ++i) m = L.wmax[i] > m ? L.wmax[i] : m;
+  __syncthreads();
+  return m;
+}
+
+// Grid barrier: every wave waits for its own memory operations, then one
+// thread per workgroup arrives at its group's counter; the last of a group
+// arrives at the top counter, and the last of all releases every group.
+__device__ bool grid_sync(PCelfScratch* x, uint32_t& gen, PClock& clk, int phase) {
+  __shared__ uint32_t ok_sh;
+  clk.lap(phase);
+  ++clk.barriers;
+  p_wait_vm();
+  __syncthreads();
+  ++gen;
+  if (threadIdx.x == 0) {
+    const uint32_t g = blockIdx.x % kGroups;
+    const uint32_t ng = min(kGroups, gridDim.x);
+    const uint32_t members = (gridDim.x - g + kGroups - 1) / kGroups;
+    uint32_t ok = 1;
+    if (atomicAdd(&x->arrive[g][0], 1u) + 1 == gen * members)
+      if (atomicAdd(&x->top[0], 1u) + 1 == gen * ng)
+        for (uint32_t i = 0; i < ng; ++i) st32(&x->release[i][0], gen);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while ((int32_t)(ld32(&x->release[g][0]) - gen) < 0) {
+      if (ld32(&x->err)) {
+        ok = 0;
+        break;
+      }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
+        atomicOr(&x->err, 1u);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok_sh = ok;
+  }
+  __syncthreads();
+  clk.lap(PClock::kBarrier);
+  return ok_sh != 0;
+}
+
+__device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t v) {
+  return (gain << c.B) | ((1ull << c.B) - 1 - v);
+}
+
+// This lane's share of gain(u | S) over tile t: the sizes of u's components
+// in the lane's four columns that hold no seed.  `last` is the most recent
+// seed (or kInvalid), whose coverage bits may not be visible yet: its
+// component is tested directly.
+__device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
+                                       uint32_t last) {
+  const MemoView& m = c.m;
+  const uint32_t q0 = t * kTile + lane * kPerLane;
+  const uint32_t bit = (p_uni(m.tmask[(uint64_t)u * m.mwords + (t >> 5)]) >> (t & 31)) & 1u;
+  if (!bit) return (uint64_t)min(max((int32_t)m.R - (int32_t)q0, 0), 4);
+  const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)u * m.Rs + q0);
+  int4 sl = make_int4(-1, -1, -1, -1);
+  if (last != kInvalid) sl = *reinterpret_cast<const int4*>(m.M + (uint64_t)last * m.Rs + q0);
+  const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+  const int32_t lv[4] = {sl.x, sl.y, sl.z, sl.w};
+  int32_t size[4];
+  uint32_t word[4];
+  uint32_t root[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t q = q0 + i;
+    const int32_t val = vals[i];
+    const bool shared = q < m.R && val != -1;
+    root[i] = val < 0 ? u : (uint32_t)val;
+    size[i] = val < 0 ? -val : (shared ? -m.M[(uint64_t)val * m.Rs + q] : 0);
+    word[i] = shared ? ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q >> 5)]) : 0u;
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t q = q0 + i;
+    if (q >= m.R) continue;
+    const uint32_t lroot = lv[i] < 0 ? last : (uint32_t)lv[i];
+    const bool covered = ((word[i] >> (q & 31)) & 1u) || (last != kInvalid && lroot == root[i]);
+    sum += covered ? 0 : (uint64_t)size[i];
+  }
+  return sum;
+}
+
+// Bitonic sort of key/id[0, cnt) descending, cnt a power of two.
+__device__ void lds_sort_desc(uint64_t* key, uint32_t* id, uint32_t cnt) {
+  for (uint32_t k = 2; k <= cnt; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < cnt; i += kPBlock) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const bool desc = (i & k) == 0;
+          const uint64_t a = key[i], b = key[ixj];
+          if ((a < b) == desc) {
+            key[i] = b;
+            key[ixj] = a;
+            const uint32_t t = id[i];
+            id[i] = id[ixj];
+            id[ixj] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ inline uint32_t next_pow2(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Number of entries of the descending array a[0, cnt) larger than k.
+__device__ inline uint32_t count_greater(const uint64_t* a, uint32_t cnt, uint64_t k) {
+  uint32_t lo = 0, hi = cnt;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] > k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Recomputes the index of the largest F entry.
+__device__ void f_best(PoolLds& L) {
+  const uint32_t nf = L.nf;
+  uint64_t best = 0;
+  for (uint32_t i = threadIdx.x; i < nf; i += kPBlock) best = L.fkey[i] > best ? L.fkey[i] : best;
+  best = block_max(L, best);
+  for (uint32_t i = threadIdx.x; i < nf; i += kPBlock)
+    if (L.fkey[i] == best) L.fbest = i;
+  __syncthreads();
+}
+
+// After a commit: F (without the seed) becomes stale and is merged into the
+// unconsumed part of S; S restarts at position 0.
+__device__ void pool_restale(PoolLds& L) {
+  const uint32_t nf = L.nf, head = L.head, ns = L.ns - head;
+  // sort F descending (padding keys 0 sort last)
+  const uint32_t np2 = next_pow2(nf);
+  for (uint32_t i = nf + threadIdx.x; i < np2; i += kPBlock) {
+    L.fkey[i] = 0;
+    L.fid[i] = kInvalid;
+  }
+  __syncthreads();
+  lds_sort_desc(L.fkey, L.fid, np2);
+  // merge by rank into registers, then write S
+  constexpr uint32_t kR = kPool / kPBlock;
+  uint64_t k[2 * kR];
+  uint32_t v[2 * kR], pos[2 * kR];
+#pragma unroll
+  for (uint32_t j = 0; j < kR; ++j) {
+    const uint32_t i = threadIdx.x + j * kPBlock;
+    const bool in = i < ns;
+    k[j] = in ? L.skey[head + i] : 0;
+    v[j] = in ? L.sid[head + i] : kInvalid;
+    pos[j] = in ? i + count_greater(L.fkey, nf, k[j]) : kPool;
+    const bool fin = i < nf;
+    k[kR + j] = fin ? L.fkey[i] : 0;
+    v[kR + j] = fin ? L.fid[i] : kInvalid;
+    pos[kR + j] = fin ? i + count_greater(L.skey + head, ns, k[kR + j]) : kPool;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < 2 * kR; ++j)
+    if (pos[j] < kPool) {
+      L.skey[pos[j]] = k[j];
+      L.sid[pos[j]] = v[j];
+    }
+  if (threadIdx.x == 0) {
+    L.ns = ns + nf;
+    L.head = 0;
+    L.nf = 0;
+  }
+  __syncthreads();
+}
+
+// Rebuilds the pool from the keys of all unselected vertices.
+__device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_t& gen, PClock& clk) {
+  const CelfView& c = a.c;
+  PCelfScratch* x = a.x;
+  const uint32_t n = c.m.n;
+  const uint32_t gtid = blockIdx.x * kPBlock + threadIdx.x, gstride = gridDim.x * kPBlock;
+  if (!grid_sync(x, gen, clk, PClock::kPoolOps)) return false;  // readers of the last staging are done
+  if (blockIdx.x == 0) {
+    for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
+    if (threadIdx.x == 0) {
+      st32(&x->pool_cnt, 0u);
+      st64(&x->out_bound, 0ull);
+      st64(&x->kmax, 0ull);
+    }
+  }
+  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  // largest key
+  uint64_t mx = 0;
+  for (uint32_t v = gtid; v < n; v += gstride) {
+    const uint64_t k = ld64(&c.key[v]);
+    mx = k > mx ? k : mx;
+  }
+  mx = p_wmax(mx);
+  if ((threadIdx.x & 63) == 0 && mx) atomicMax((unsigned long long*)&x->kmax, (unsigned long long)mx);
+  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  const uint64_t kmax = ld64(&x->kmax);
+  if (kmax == 0) {  // nothing unselected: the caller reports it
+    if (threadIdx.x == 0) {
+      L.ns = L.head = L.nf = 0;
+      L.out_bound = 0;
+    }
+    __syncthreads();
+    return true;
+  }
+  // radix select of a threshold: digits of up to kDigitBits bits from the
+  // top bit down; bits [shift, shift + width) form the current digit
+  const uint32_t topbit = 63 - __clzll((long long)kmax);
+  if (threadIdx.x == 0) {
+    L.prefix = 0;
+    L.want = kPool / 2;
+    L.cap = kPool;
+    L.done = 0;
+    L.width = min(kDigitBits, topbit + 1);
+    L.shift = topbit + 1 - L.width;
+  }
+  __syncthreads();
+  uint64_t thresh = 1;
+  for (;;) {
+    const uint32_t shift = L.shift, width = L.width;
+    const uint64_t prefix = L.prefix;
+    for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) L.hist[i] = 0;
+    __syncthreads();
+    for (uint32_t v = gtid; v < n; v += gstride) {
+      const uint64_t k = ld64(&c.key[v]);
+      if (k == 0) continue;
+      const uint64_t hi = (shift + width >= 64) ? 0 : (k >> (shift + width));
+      if (hi != prefix) continue;
+      atomicAdd(&L.hist[(k >> shift) & ((1u << width) - 1)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock)
+      if (L.hist[i]) atomicAdd(&x->hist[i], L.hist[i]);
+    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+    // bins from the top: thread t holds bins kBins-1-(kBPer*t .. kBPer*t+kBPer-1)
+    constexpr uint32_t kBPer = kBins / kPBlock;
+    uint32_t h[kBPer], mine = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kBPer; ++j) {
+      h[j] = ld32(&x->hist[kBins - 1 - (threadIdx.x * kBPer + j)]);
+      mine += h[j];
+    }
+    uint32_t tot;
+    uint32_t cum = block_exscan(L, mine, tot);
+    const uint32_t want = L.want, cap = L.cap;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kBPer; ++j) {
+      // bin b holds the want-th largest matching key
+      if (cum < want && want <= cum + h[j]) {
+        const uint32_t b = kBins - 1 - (threadIdx.x * kBPer + j);  // < 2^width: bins above are empty
+        L.prefix = (prefix << width) | b;
+        if (cum + h[j] <= cap || shift == 0) {
+          L.done = 1;  // threshold = lower edge of bin b
+        } else {
+          L.want = want - cum;
+          L.cap = cap - cum;
+          L.width = min(kDigitBits, shift);
+          L.shift = shift - L.width;
+        }
+      }
+      cum += h[j];
+    }
+    if (want > tot && threadIdx.x == 0) {  // fewer matching keys than wanted: take them all
+      L.done = 1;
+      L.prefix = prefix << width;
+    }
+    __syncthreads();
+    if (L.done) {
+      thresh = L.prefix << shift;
+      if (thresh == 0) thresh = 1;
+      break;
+    }
+    if (L.shift == shift) {  // no lower digit (cannot happen: shift 0 always finishes)
+      if (threadIdx.x == 0) atomicOr(&x->err, 2u);
+      return false;
+    }
+    // clear the global histogram for the next digit once every reader is done
+    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+    if (blockIdx.x == 0)
+      for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
+    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  }
+  // collect the keys at or above the threshold
+  uint64_t outside = 0;
+  for (uint32_t v = gtid; v < n; v += gstride) {
+    const uint64_t k = ld64(&c.key[v]);
+    if (k == 0) continue;
+    if (k >= thresh) {
+      const uint32_t at = atomicAdd(&x->pool_cnt, 1u);
+      if (at < kPool) {
+        st32(&x->pool_id[at], v);
+        st64(&x->pool_key[at], k);
+      }
+    } else if (k > outside) {
+      outside = k;
+    }
+  }
+  outside = p_wmax(outside);
+  if ((threadIdx.x & 63) == 0 && outside)
+    atomicMax((unsigned long long*)&x->out_bound, (unsigned long long)outside);
+  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  const uint32_t cnt = ld32(&x->pool_cnt);
+  if (cnt > kPool) {  // the threshold admits at most kPool keys
+    if (threadIdx.x == 0) atomicOr(&x->err, 2u);
+    return false;
+  }
+  // split into F (fresh: evaluated for this |S|) and S (stale, sorted)
+  uint32_t vv[kPer];
+  uint64_t kk[kPer];
+  uint32_t fr[kPer];
+  uint32_t nfm = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t i = threadIdx.x * kPer + j;
+    vv[j] = i < cnt ? ld32(&x->pool_id[i]) : kInvalid;
+    kk[j] = i < cnt ? ld64(&x->pool_key[i]) : 0;
+    fr[j] = (i < cnt && ld32(&c.iter[vv[j]]) == s) ? 1u : 0u;
+    nfm += fr[j];
+  }
+  uint32_t nfresh;
+  uint32_t fpos = block_exscan(L, nfm, nfresh);
+  uint32_t spos = min(threadIdx.x * kPer, cnt) - fpos;  // stale entries before this thread's
+#pragma unroll
+  for (uint32_t j = 0; j < kPer; ++j) {
+    const uint32_t i = threadIdx.x * kPer + j;
+    if (i >= cnt) continue;
+    if (fr[j]) {
+      L.fkey[fpos] = kk[j];
+      L.fid[fpos] = vv[j];
+      ++fpos;
+    } else {
+      L.skey[spos] = kk[j];
+      L.sid[spos] = vv[j];
+      ++spos;
+    }
+  }
+  if (threadIdx.x == 0) {
+    L.ns = cnt - nfresh;
+    L.nf = nfresh;
+    L.head = 0;
+    L.out_bound = ld64(&x->out_bound);
+  }
+  __syncthreads();
+  const uint32_t ns = L.ns;
+  const uint32_t np2 = next_pow2(ns);
+  for (uint32_t i = ns + threadIdx.x; i < np2; i += kPBlock) {
+    L.skey[i] = 0;
+    L.sid[i] = kInvalid;
+  }
+  __syncthreads();
+  lds_sort_desc(L.skey, L.sid, np2);
+  f_best(L);
+  ++clk.rebuilds;
+  clk.lap(PClock::kRebuild);
+  return true;
+}
+
+// Bulk evaluation of every stale vertex whose key exceeds kstar.
+__device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32_t last, uint32_t& gen,
+                          PClock& clk, uint64_t& evals) {
+  const CelfView& c = a.c;
+  PCelfScratch* x = a.x;
+  const uint32_t n = c.m.n, ntiles = c.m.ntiles;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t gtid = blockIdx.x * kPBlock + threadIdx.x, gstride = gridDim.x * kPBlock;
+  const uint32_t nw = gridDim.x * (kPBlock / 64);
+  const uint32_t gw = blockIdx.x * (kPBlock / 64) + (threadIdx.x >> 6);
+  // the last commit's key store and the counter reset must be visible
+  if (blockIdx.x == 0 && threadIdx.x == 0) st32(&x->bulk_cnt, 0u);
+  if (!grid_sync(x, gen, clk, PClock::kPoolOps)) return false;
+  // 1. list the candidates (wave-aggregated slots)
+  for (uint32_t base = gtid - lane; base < n; base += gstride) {
+    const uint32_t v = base + lane;
+    bool take = false;
+    if (v < n) {
+      const uint64_t k = ld64(&c.key[v]);
+      take = k > kstar && ld32(&c.iter[v]) != s;
+    }
+    const uint64_t mask = __ballot(take);
+    if (!mask) continue;
+    uint32_t slot0 = 0;
+    if (lane == 0) slot0 = atomicAdd(&x->bulk_cnt, (uint32_t)__popcll(mask));
+    slot0 = __shfl(slot0, 0);
+    if (take) {
+      const uint32_t at = slot0 + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
+      st32(&a.blist[at], v);
+      st64(&a.bgain[at], 0ull);
+    }
+  }
+  if (!grid_sync(x, gen, clk, PClock::kBulk)) return false;
+  const uint32_t cnt = ld32(&x->bulk_cnt);
+  // 2. gains, one (vertex, tile) per wave job
+  const uint64_t items = (uint64_t)cnt * ntiles;
+  for (uint64_t it = gw; it < items; it += nw) {
+    const uint32_t w = (uint32_t)(it / ntiles), t = (uint32_t)(it - (uint64_t)w * ntiles);
+    const uint32_t v = ld32(&a.blist[w]);
+    const uint64_t part = p_wsum(p_eval_tile(c, v, t, lane, last));
+    if (lane == 0 && part) atomicAdd((unsigned long long*)&a.bgain[w], (unsigned long long)part);
+  }
+  if (!grid_sync(x, gen, clk, PClock::kBulk)) return false;
+  // 3. new keys
+  for (uint32_t w = gtid; w < cnt; w += gstride) {
+    const uint32_t v = ld32(&a.blist[w]);
+    st64(&c.key[v], p_make_key(c, ld64(&a.bgain[w]), v));
+    st32(&c.iter[v], s);
+  }
+  evals += cnt;
+  ++clk.bulks;
+  clk.lap(PClock::kBulk);
+  return true;
+}
+
+__global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
+  __shared__ PoolLds L;
+  const CelfView& c = a.c;
+  PCelfScratch* x = a.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = gridDim.x * (kPBlock / 64);
+  const uint32_t gw = blockIdx.x * (kPBlock / 64) + (threadIdx.x >> 6);
+  const uint32_t ntiles = c.m.ntiles;
+  uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, step_rebuilds = 0;
+  uint64_t evals = 0;
+  PClock clk;
+  clk.start();
+  const uint64_t t_start = clk.mark;
+  if (!pool_rebuild(a, L, s, gen, clk)) return;
+  bool just_rebuilt = true;
+  while (s < c.K) {
+    if (__builtin_amdgcn_s_memrealtime() - t_start > kRunTicks) {
+      if (threadIdx.x == 0) atomicOr(&x->err, 4u);
+      return;
+    }
+    const uint32_t ns = L.ns, head = L.head, nf = L.nf;
+    const uint64_t stop = head < ns ? L.skey[head] : 0;
+    const uint64_t fbest = nf ? L.fkey[L.fbest] : 0;
+    const uint64_t ob = L.out_bound;
+    if (nf && fbest > stop && fbest > ob) {
+      // ---- commit the exact maximiser; each workgroup marks a slice of columns
+      const uint32_t id = L.fid[L.fbest];
+      const uint32_t per = (c.m.R + gridDim.x - 1) / gridDim.x;
+      const uint32_t q_lo = min(blockIdx.x * per, c.m.R), q_hi = min(q_lo + per, c.m.R);
+      for (uint32_t q = q_lo + threadIdx.x; q < q_hi; q += kPBlock) {
+        const int32_t val = c.m.M[(uint64_t)id * c.m.Rs + q];
+        const uint32_t root = val < 0 ? id : (uint32_t)val;
+        atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
+      }
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c.seeds[s] = id;
+        c.marginal[s] = (int64_t)(fbest >> c.B);
+        st64(&c.key[id], 0ull);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {  // drop the seed from F
+        const uint32_t b = L.fbest;
+        L.fkey[b] = L.fkey[nf - 1];
+        L.fid[b] = L.fid[nf - 1];
+        L.nf = nf - 1;
+      }
+      __syncthreads();
+      pool_restale(L);
+      last = id;
+      ++s;
+      rounds = 0;
+      step_rebuilds = 0;
+      just_rebuilt = false;
+      clk.lap(PClock::kPoolOps);
+      continue;
+    }
+    if (stop > ob && stop > fbest) {
+      // ---- evaluate the next W entries of S (only those above max F can win)
+      const uint32_t want = min(kMaxCand, a.w0 << min(rounds, 10u));
+      uint32_t nc = min(want, ns - head);
+      if (fbest) nc = min(nc, count_greater(L.skey + head, nc, fbest));
+      nc = min(nc, kPool - nf);
+      uint64_t* g = x->gains[ev_round % 3];
+      if (blockIdx.x == 0) {
+        uint64_t* nxt = x->gains[(ev_round + 1) % 3];
+        for (uint32_t i = threadIdx.x; i < kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
+      }
+      clk.lap(PClock::kPoolOps);
+      const uint32_t items = nc * ntiles;
+      for (uint32_t it = gw; it < items; it += nw) {
+        const uint32_t w = it / ntiles, t = it - w * ntiles;
+        const uint64_t part = p_wsum(p_eval_tile(c, L.sid[head + w], t, lane, last));
+        if (lane == 0 && part) atomicAdd((unsigned long long*)&g[w], (unsigned long long)part);
+      }
+      if (!grid_sync(x, gen, clk, PClock::kEval)) return;
+      // move the evaluated entries from S to F
+      for (uint32_t w = threadIdx.x; w < nc; w += kPBlock) {
+        const uint32_t v = L.sid[head + w];
+        const uint64_t k = p_make_key(c, ld64(&g[w]), v);
+        L.fkey[nf + w] = k;
+        L.fid[nf + w] = v;
+        if (blockIdx.x == 0) {
+          st64(&c.key[v], k);
+          st32(&c.iter[v], s);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        L.head = head + nc;
+        L.nf = nf + nc;
+      }
+      __syncthreads();
+      f_best(L);
+      evals += nc;
+      ++rounds;
+      ++ev_round;
+      ++clk.rounds;
+      just_rebuilt = false;
+      clk.lap(PClock::kPoolOps);
+      continue;
+    }
+    // ---- the pool cannot decide: the largest key is outside.  Refill the
+    // pool; when that already happened in this step, first evaluate every
+    // stale vertex above max F at once (a lower bound of this step's gain).
+    if (just_rebuilt) {  // a fresh pool always decides
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      return;
+    }
+    if (nf && step_rebuilds > 0)
+      if (!bulk_eval(a, s, fbest, last, gen, clk, evals)) return;
+    if (!pool_rebuild(a, L, s, gen, clk)) return;
+    ++step_rebuilds;
+    if (L.ns == 0 && L.nf == 0) {  // no unselected vertex: cannot happen for K <= n
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      return;
+    }
+    just_rebuilt = true;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.st->s = s;
+    c.st->evals = evals;
+    c.st->bulk_rounds = ev_round;
+    for (int i = 0; i < PClock::kPhases; ++i) x->prof[i] = clk.acc[i];
+    x->prof[5] = clk.barriers;
+    x->prof[6] = clk.rounds;
+    x->prof[7] = ((uint64_t)clk.bulks << 32) | clk.rebuilds;
+  }
+}
+
+// ---- host side --------------------------------------------------------------
+
+uint64_t pcelf_scratch_bytes() { return sizeof(PCelfScratch); }
+uint64_t pcelf_prof_offset() { return offsetof(PCelfScratch, prof); }
+uint64_t pcelf_err_offset() { return offsetof(PCelfScratch, err); }
+
+// Co-resident workgroups for a cooperative launch on `device` (0: the
+// device cannot run it).
+uint32_t pcelf_grid(int device) {
+  int coop = 0, cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_celf_persistent, kPBlock, 0) != hipSuccess || per < 1)
+    return 0;
+  return (uint32_t)cus * (uint32_t)std::min(per, 2);
+}
+
+hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint64_t* bgain,
+                                  uint32_t grid, hipStream_t st) {
+  PCelfArgs a;
+  a.c = c;
+  a.x = static_cast<PCelfScratch*>(scratch);
+  a.blist = blist;
+  a.bgain = bgain;
+  const uint32_t waves = grid * (kPBlock / 64);
+  a.w0 = std::max(8u, std::min(kMaxCand, (waves + c.m.ntiles - 1) / c.m.ntiles));
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_celf_persistent), dim3(grid), dim3(kPBlock),
+                                    args, 0, st);
+}
+
+}  // namespace infuse

@@ -27,6 +27,14 @@ void launch_celf_topw(const CelfView& c, hipStream_t st);
 void launch_celf_eval(const CelfView& c, hipStream_t st);
 void launch_celf_bulk(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 
+// celf_persistent.hip
+uint64_t pcelf_scratch_bytes();
+uint64_t pcelf_err_offset();   // u32 error flag of the persistent kernel
+uint64_t pcelf_prof_offset();  // 8 x u64: phase ticks (100 MHz) x5, barriers, rounds, rebuilds
+uint32_t pcelf_grid(int device);
+hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint64_t* bgain,
+                                  uint32_t grid, hipStream_t st);
+
 // query.hip
 uint32_t sigma_pair_max();
 void launch_sigma_pair(const MemoView& m, const uint32_t* S, uint32_t len, unsigned long long* out,

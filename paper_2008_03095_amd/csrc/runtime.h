@@ -51,6 +51,10 @@ struct CelfBuffers {
   void* base = nullptr;
   size_t bytes = 0;
   CelfView v;
+  void* pscratch = nullptr;  // state of the persistent kernel
+  uint32_t* blist = nullptr;  // [n] persistent kernel: bulk candidates
+  uint64_t* bgain = nullptr;  // [n] and their gains
+  bool persistent = false;   // enqueued as one persistent kernel
 };
 
 im_status fail(im_status s, const char* fmt, ...);
@@ -106,6 +110,12 @@ struct im_ctx {
   std::vector<im_graph*> graphs;
   std::unordered_map<void*, size_t> sizes;
   std::recursive_mutex mu;
+  // persistent CELF: workgroups of a cooperative launch (0: unavailable),
+  // and the completion of the last one enqueued
+  uint32_t coop_grid = 0;
+  hipEvent_t coop_done = nullptr;
+  bool coop_pending = false;
+  hipStream_t coop_stream = nullptr;
 };
 
 struct im_graph {

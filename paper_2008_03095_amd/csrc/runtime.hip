@@ -363,6 +363,8 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   b += align256((size_t)W * 4) + align256((size_t)W * 8);
   b += align256((size_t)std::max(K, 1u) * 4) + align256((size_t)std::max(K, 1u) * 8);
   b += align256(sizeof(CelfState));
+  b += align256(pcelf_scratch_bytes());
+  b += align256((size_t)n * 4) + align256((size_t)n * 8);
   void* base = nullptr;
   im_status s = ctx_alloc(c, b, &base);
   if (s != IM_OK) return s;
@@ -389,6 +391,10 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   v.seeds = reinterpret_cast<uint32_t*>(take((size_t)std::max(K, 1u) * 4));
   v.marginal = reinterpret_cast<int64_t*>(take((size_t)std::max(K, 1u) * 8));
   v.st = reinterpret_cast<CelfState*>(take(sizeof(CelfState)));
+  cb->pscratch = take(pcelf_scratch_bytes());
+  cb->blist = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
+  cb->bgain = reinterpret_cast<uint64_t*>(take((size_t)n * 8));
+  cb->persistent = false;
   return IM_OK;
 }
 
@@ -396,6 +402,26 @@ void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   const CelfView& v = cb->v;
   launch_fill_u32(v.cov, (uint64_t)v.m.n * v.cwords, 0u, st);
   launch_celf_init(v, st);
+  if (c->tune.celf_mode == 1 && c->coop_grid) {
+    launch_fill_u32(static_cast<uint32_t*>(cb->pscratch), pcelf_scratch_bytes() / 4, 0u, st);
+    // one persistent kernel at a time per context: two partly resident
+    // cooperative grids could each wait for the other's workgroups
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    if (c->coop_pending && c->coop_stream != st) (void)hipStreamWaitEvent(st, c->coop_done, 0);
+    hipError_t e;
+    {
+      KTimer t(c, "celf", st, 1);
+      e = launch_celf_persistent(v, cb->pscratch, cb->blist, cb->bgain, c->coop_grid, st);
+    }
+    if (e == hipSuccess) {
+      (void)hipEventRecord(c->coop_done, st);
+      c->coop_pending = true;
+      c->coop_stream = st;
+      cb->persistent = true;
+      return;
+    }
+    (void)hipGetLastError();  // not launchable here: run the per-step kernels
+  }
   const uint32_t bulk_blocks = std::max(1u, std::min(2048u, v.m.n));
   for (uint32_t k = 0; k < v.K; ++k) {
     {
@@ -417,12 +443,31 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
                        int64_t* marginal, int64_t* cover, uint64_t* evals) {
   const CelfView& v = cb->v;
   CelfState hs;
-  if (hipMemcpyAsync(seeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  uint32_t perr = 0;  // error flag of the persistent kernel
+  if ((cb->persistent && hipMemcpyAsync(&perr, static_cast<char*>(cb->pscratch) + pcelf_err_offset(), sizeof(perr),
+                                        hipMemcpyDeviceToHost, st) != hipSuccess) ||
+      hipMemcpyAsync(seeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(marginal, v.marginal, (size_t)v.K * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(&hs, v.st, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     hipError_t e = hipGetLastError();
     return fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
+  }
+  if (perr) return fail(IM_ERR_DEVICE, "persistent CELF kernel aborted (code %u)", perr);
+  if (cb->persistent && c->profiling >= 2) {
+    // phase clock of the persistent kernel: ticks of 10 ns per phase
+    uint64_t pr[8];
+    if (hipMemcpy(pr, static_cast<char*>(cb->pscratch) + pcelf_prof_offset(), sizeof(pr),
+                  hipMemcpyDeviceToHost) == hipSuccess) {
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      const char* names[5] = {"celf.barrier", "celf.eval", "celf.pool", "celf.rebuild", "celf.bulk"};
+      const uint64_t counts[5] = {pr[5], pr[6], v.K, pr[7] & 0xFFFFFFFFu, pr[7] >> 32};
+      for (int i = 0; i < 5; ++i) {
+        auto& e = c->kstats[names[i]];
+        e.first += counts[i];
+        e.second += pr[i] * 1e-5;
+      }
+    }
   }
   if (hs.s != v.K) return fail(IM_ERR_DEVICE, "CELF committed %u of %u seeds", hs.s, v.K);
   int64_t tot = 0;
@@ -468,6 +513,12 @@ extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator*
   c->tune.cc_chunk = 1024;
   c->tune.celf_width = 16;
   c->tune.use_graphs = 0;
+  c->coop_grid = pcelf_grid(device);
+  c->tune.celf_mode = c->coop_grid ? 1 : 2;
+  if (c->coop_grid && hipEventCreateWithFlags(&c->coop_done, hipEventDisableTiming) != hipSuccess) {
+    c->coop_grid = 0;
+    c->tune.celf_mode = 2;
+  }
   *out = c;
   return IM_OK;
 }
@@ -478,6 +529,7 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   resolve_pending(c);
   while (!c->graphs.empty()) im_graph_free(c->graphs.back());
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  if (c->coop_done) (void)hipEventDestroy(c->coop_done);
   delete c;
 }
 
@@ -496,6 +548,12 @@ extern "C" im_status im_set_tuning(im_ctx* c, const im_tuning* t) {
     c->tune.celf_width = t->celf_width;
   }
   if (t->use_graphs) c->tune.use_graphs = t->use_graphs == 1 ? 1 : 0;
+  if (t->celf_mode) {
+    if (t->celf_mode > 2) return fail(IM_ERR_INVALID_ARG, "celf_mode must be 1 or 2");
+    if (t->celf_mode == 1 && !c->coop_grid)
+      return fail(IM_ERR_INVALID_ARG, "the device cannot run the persistent CELF kernel");
+    c->tune.celf_mode = t->celf_mode;
+  }
   return IM_OK;
 }
 

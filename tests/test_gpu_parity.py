@@ -225,3 +225,36 @@ def test_tuning_variants_and_repeats_identical(gpu_ctx):
     finally:
         gpu_ctx.set_tuning(cc_chunk=old["cc_chunk"], celf_width=old["celf_width"])
         G.free()
+
+
+CELF_CASES = {
+    # more seeds than the persistent kernel's candidate pool: repeated pool rebuilds
+    "cl5000_K2500": (lambda: chung_lu(5000, 20000, 2.3, 5), 0.03, 512, 5, 2500),
+    # every vertex selected; the pool holds the whole graph
+    "cl300_Kn": (lambda: chung_lu(300, 1200, 2.3, 17), 0.1, 64, 17, 300),
+    # long path, large components, few tiles
+    "path3000": (lambda: path_graph(3000), 0.9, 256, 9, 40),
+    # ragged R (last tile partly used), zero-gain rounds towards the end
+    "star500_R300": (lambda: star_graph(500), 0.3, 300, 4, 499),
+}
+
+
+@pytest.mark.parametrize("mode", [P.Context.CELF_PERSISTENT, P.Context.CELF_PER_STEP])
+@pytest.mark.parametrize("case", list(CELF_CASES))
+def test_celf_modes(gpu_ctx, case, mode):
+    make, p, R, seed, K = CELF_CASES[case]
+    g = make()
+    announce(f"CELF mode {mode} {case} n={g.n} K={K}")
+    ref = oracle.run_memo(g, oracle.Sampler("hash", p=p, R=R, seed=seed), K, threads=4)
+    old = gpu_ctx.tuning()
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        gpu_ctx.set_tuning(celf_mode=mode)
+        G.set_params(p, R, seed)
+        seeds, marg, cover = G.select_seeds(K)
+        assert list(seeds) == list(ref["seeds"])
+        assert list(marg) == list(ref["marginal"])
+        assert cover == ref["cover"]
+    finally:
+        gpu_ctx.set_tuning(celf_mode=old["celf_mode"])
+        G.free()
