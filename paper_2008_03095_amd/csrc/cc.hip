@@ -45,19 +45,27 @@ struct TileCtx {
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-__device__ inline void tile_setup(const MemoView& m, uint32_t t, uint32_t lane, uint32_t kshift,
-                                  TileCtx& tc, bool per_edge) {
+// X of the lane's four columns of tile t (one 16-byte load per lane).
+__device__ inline uint4 load_tile_x(const MemoView& m, uint32_t t, uint32_t lane) {
+  return *reinterpret_cast<const uint4*>(m.xs + t * kTile + lane * kPerLane);
+}
+
+// Tile context from the loaded X values: the tile's X range comes from lane
+// 0 (first column) and the lane holding the last used column.
+__device__ inline void tile_from_x(const MemoView& m, uint32_t t, uint32_t lane, uint4 x4, uint32_t kshift,
+                                   TileCtx& tc, bool per_edge) {
   tc.q0 = t * kTile + lane * kPerLane;
-  const uint4 x4 = *reinterpret_cast<const uint4*>(m.xs + tc.q0);
   tc.x[0] = x4.x;
   tc.x[1] = x4.y;
   tc.x[2] = x4.z;
   tc.x[3] = x4.w;
 #pragma unroll
   for (int i = 0; i < 4; ++i) tc.valid[i] = tc.q0 + i < m.R;
-  const uint32_t qlast = min(t * kTile + kTile - 1, m.R - 1);
-  const uint32_t xlo = uni(m.xs[t * kTile]);
-  const uint32_t xhi = uni(m.xs[qlast]);
+  const uint32_t qlast = min(t * kTile + kTile - 1, m.R - 1) - t * kTile;  // R > t * kTile
+  const uint32_t c = qlast & 3;
+  const uint32_t pick = c == 0 ? x4.x : c == 1 ? x4.y : c == 2 ? x4.z : x4.w;
+  const uint32_t xlo = __builtin_amdgcn_readlane(x4.x, 0);
+  const uint32_t xhi = __builtin_amdgcn_readlane(pick, qlast >> 2);
   if (!per_edge) {
     tc.klo = (uint32_t)((uint64_t)xlo >> kshift);
     tc.khi = (uint32_t)((uint64_t)xhi >> kshift);
@@ -134,80 +142,167 @@ __device__ inline bool for_candidates(const GraphView& g, const MemoView& m, uin
   return any;
 }
 
-struct WaveJob {
-  uint32_t v, t0, t1;
-  bool ok;
-};
-
-__device__ inline WaveJob wave_job(uint32_t n, uint32_t ntiles, uint32_t chunk, uint32_t wpv) {
-  WaveJob w;
-  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  w.v = uni((uint32_t)(wid / wpv));
-  const uint32_t c = uni((uint32_t)(wid % wpv));
-  w.ok = w.v < n;
-  w.t0 = c * chunk;
-  w.t1 = min(w.t0 + chunk, ntiles);
-  return w;
+// Hook of one tile: for each of the lane's columns, the smallest live
+// neighbour u < v (or -1), stored as one 16-byte write.  Returns whether the
+// tile has any candidate edge (tmask bit) and whether some column has two or
+// more live smaller neighbours (lmask bit).
+template <bool PER_EDGE>
+__device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t v, uint32_t beg, uint32_t end,
+                                 uint32_t split, uint32_t lane, bool inreg, uint32_t rcol, uint32_t rh,
+                                 uint32_t rtm1, const TileCtx& tc, int32_t* row, bool& any, bool& need) {
+  int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  // candidates among all neighbours mark the tile; smaller ones hook
+  any = for_candidates<PER_EDGE, false>(
+      g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
+      [&](uint32_t u, uint32_t h, uint32_t tt, bool small) {
+        if (!small) return;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
+          cnt[i] += live ? 1u : 0u;
+          mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
+        }
+      });
+  int4 out;
+  out.x = cnt[0] ? mn[0] : -1;
+  out.y = cnt[1] ? mn[1] : -1;
+  out.z = cnt[2] ? mn[2] : -1;
+  out.w = cnt[3] ? mn[3] : -1;
+  *reinterpret_cast<int4*>(row + tc.q0) = out;
+  need = __ballot(cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1) != 0;
 }
 
+// k_hook_rows: one wavefront per vertex with at most kWave neighbours (the
+// neighbour list sits in registers) writes the vertex's whole row, tile by
+// tile; the X values of the next tile are loaded before the current tile is
+// processed, so the wave waits on loads, not on its stores.  The wave owns
+// the vertex's mask words and stores them directly.
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_hook(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
-  const WaveJob job = wave_job(g.n, m.ntiles, chunk, wpv);
-  if (!job.ok) return;
-  const uint32_t lane = threadIdx.x & 63, v = job.v;
-  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
-  const bool inreg = end - beg <= (uint32_t)kWave;
+__global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
+  const uint32_t v = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (v >= g.n) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
+  if (end - beg > (uint32_t)kWave) return;  // k_hook_hubs
+  const uint32_t split = uni(g.split[v]);
   uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
-  if (inreg && beg + lane < end) {
+  if (beg + lane < end) {
     const uint2 e = m.edges[beg + lane];
     rcol = e.x;
     rh = e.y;
     if (PER_EDGE) rtm1 = g.tm1[beg + lane];
   }
   int32_t* row = m.M + (uint64_t)v * m.Rs;
+  uint32_t* tw = m.tmask + (uint64_t)v * m.mwords;
+  uint32_t* lw = m.lmask + (uint64_t)v * m.mwords;
+  uint4 xn = load_tile_x(m, 0, lane);
   uint32_t tbits = 0, lbits = 0;
-  for (uint32_t t = job.t0; t < job.t1; ++t) {
+  for (uint32_t t = 0; t < m.ntiles; ++t) {
+    const uint4 xc = xn;
+    if (t + 1 < m.ntiles) xn = load_tile_x(m, t + 1, lane);
     TileCtx tc;
-    tile_setup(m, t, lane, m.kshift, tc, PER_EDGE);
-    int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
-    uint32_t cnt[4] = {0, 0, 0, 0};
-    // candidates among all neighbours mark the tile; smaller ones hook
-    const bool any = for_candidates<PER_EDGE, false>(
-        g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
-        [&](uint32_t u, uint32_t h, uint32_t tt, bool small) {
-          if (!small) return;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
-            cnt[i] += live ? 1u : 0u;
-            mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
-          }
-        });
-    int4 out;
-    out.x = cnt[0] ? mn[0] : -1;
-    out.y = cnt[1] ? mn[1] : -1;
-    out.z = cnt[2] ? mn[2] : -1;
-    out.w = cnt[3] ? mn[3] : -1;
-    *reinterpret_cast<int4*>(row + tc.q0) = out;
-    const bool need = cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1;
-    const uint64_t nb = __ballot(need);
-    tbits |= (any ? 1u : 0u) << (t - job.t0);
-    lbits |= (nb ? 1u : 0u) << (t - job.t0);
+    tile_from_x(m, t, lane, xc, m.kshift, tc, PER_EDGE);
+    bool any, need;
+    hook_tile<PER_EDGE>(g, m, v, beg, end, split, lane, true, rcol, rh, rtm1, tc, row, any, need);
+    tbits |= (any ? 1u : 0u) << (t & 31);
+    lbits |= (need ? 1u : 0u) << (t & 31);
+    if ((t & 31) == 31 || t + 1 == m.ntiles) {
+      if (lane == 0) {
+        tw[t >> 5] = tbits;
+        lw[t >> 5] = lbits;
+      }
+      tbits = lbits = 0;
+    }
   }
-  if (lane == 0) {
-    const uint32_t word = job.t0 >> 5, sh = job.t0 & 31;
-    const uint32_t sub = blockIdx.x % kSubLists;
-    if (tbits) {
-      atomicOr(&m.tmask[(uint64_t)v * m.mwords + word], tbits << sh);
-      uint32_t at = atomicAdd(&m.counts[2 * sub], (uint32_t)__popc(tbits));
-      uint32_t* out = m.tlist + (uint64_t)sub * m.list_cap;
-      for (uint32_t b = tbits; b; b &= b - 1) out[at++] = v * m.ntiles + job.t0 + __ffs(b) - 1;
+}
+
+// k_hook_hubs: vertices with more than kWave neighbours, one wavefront per
+// (vertex, chunk of tiles); the neighbour list is streamed in 64-slot
+// pieces.  Several wavefronts share a vertex's mask words (atomic or).
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_hook_hubs(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
+  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t hi = uni((uint32_t)(wid / wpv));
+  if (hi >= g.nhubs) return;
+  const uint32_t c = uni((uint32_t)(wid % wpv));
+  const uint32_t t0 = c * chunk, t1 = min(t0 + chunk, m.ntiles);
+  const uint32_t lane = threadIdx.x & 63, v = uni(g.hubs[hi]);
+  const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
+  int32_t* row = m.M + (uint64_t)v * m.Rs;
+  uint32_t tbits = 0, lbits = 0;
+  for (uint32_t t = t0; t < t1; ++t) {
+    TileCtx tc;
+    tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
+    bool any, need;
+    hook_tile<PER_EDGE>(g, m, v, beg, end, split, lane, false, kInvalid, 0, 0, tc, row, any, need);
+    tbits |= (any ? 1u : 0u) << (t - t0);
+    lbits |= (need ? 1u : 0u) << (t - t0);
+  }
+  if (lane == 0) {  // chunk <= 32 tiles, aligned: one mask word
+    const uint64_t word = (uint64_t)v * m.mwords + (t0 >> 5);
+    if (tbits) atomicOr(&m.tmask[word], tbits << (t0 & 31));
+    if (lbits) atomicOr(&m.lmask[word], lbits << (t0 & 31));
+  }
+}
+
+// k_lists: sub-list j lists, in vertex order, the tiles of the vertices
+// [j * vps, (j + 1) * vps) whose tmask (tlist) or lmask (llist) bit is set.
+// One workgroup per sub-list; positions come from workgroup prefix sums, so
+// no global counter is contended.
+__global__ void __launch_bounds__(256) k_lists(MemoView m) {
+  __shared__ uint32_t wsum[2][4];
+  const uint32_t j = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t vps = (m.n + kSubLists - 1) / kSubLists;
+  const uint32_t v0 = min(m.n, j * vps), v1 = min(m.n, v0 + vps);
+  uint32_t* tout = m.tlist + (uint64_t)j * m.list_cap;
+  uint32_t* lout = m.llist + (uint64_t)j * m.list_cap;
+  uint32_t tbase = 0, lbase = 0;
+  for (uint32_t vb = v0; vb < v1; vb += 256) {
+    const uint32_t v = vb + threadIdx.x;
+    uint32_t tc = 0, lc = 0;
+    if (v < v1)
+      for (uint32_t w = 0; w < m.mwords; ++w) {
+        tc += __popc(m.tmask[(uint64_t)v * m.mwords + w]);
+        lc += __popc(m.lmask[(uint64_t)v * m.mwords + w]);
+      }
+    // exclusive prefix sums of tc and lc over the workgroup
+    uint32_t ts = tc, ls = lc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t a = __shfl_up(ts, off), b = __shfl_up(ls, off);
+      if (lane >= (uint32_t)off) {
+        ts += a;
+        ls += b;
+      }
     }
-    if (lbits) {
-      uint32_t at = atomicAdd(&m.counts[2 * sub + 1], (uint32_t)__popc(lbits));
-      uint32_t* out = m.llist + (uint64_t)sub * m.list_cap;
-      for (uint32_t b = lbits; b; b &= b - 1) out[at++] = v * m.ntiles + job.t0 + __ffs(b) - 1;
+    if (lane == 63) {
+      wsum[0][wv] = ts;
+      wsum[1][wv] = ls;
     }
+    __syncthreads();
+    uint32_t tpre = 0, lpre = 0, ttot = 0, ltot = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+      tpre += i < wv ? wsum[0][i] : 0;
+      lpre += i < wv ? wsum[1][i] : 0;
+      ttot += wsum[0][i];
+      ltot += wsum[1][i];
+    }
+    __syncthreads();
+    uint32_t ta = tbase + tpre + ts - tc, la = lbase + lpre + ls - lc;
+    if (v < v1)
+      for (uint32_t w = 0; w < m.mwords; ++w) {
+        const uint32_t first = v * m.ntiles + w * 32;
+        for (uint32_t b = m.tmask[(uint64_t)v * m.mwords + w]; b; b &= b - 1) tout[ta++] = first + __ffs(b) - 1;
+        for (uint32_t b = m.lmask[(uint64_t)v * m.mwords + w]; b; b &= b - 1) lout[la++] = first + __ffs(b) - 1;
+      }
+    tbase += ttot;
+    lbase += ltot;
+  }
+  if (threadIdx.x == 0) {
+    m.counts[2 * j] = tbase;
+    m.counts[2 * j + 1] = lbase;
   }
 }
 
@@ -312,7 +407,7 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
       if (PER_EDGE) rtm1 = g.tm1[beg + lane];
     }
     TileCtx tc;
-    tile_setup(m, t, lane, m.kshift, tc, PER_EDGE);
+    tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
     int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
     for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
                                    [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
@@ -489,12 +584,25 @@ void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st
   hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(256), 0, st, p, count, value);
 }
 
-void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
+void launch_hook_rows(const GraphView& g, const MemoView& m, hipStream_t st) {
+  const dim3 rows((g.n + 3) / 4);
+  if (g.tm1)
+    hipLaunchKernelGGL(k_hook_rows<true>, rows, dim3(256), 0, st, g, m);
+  else
+    hipLaunchKernelGGL(k_hook_rows<false>, rows, dim3(256), 0, st, g, m);
+}
+
+void launch_hook_hubs(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
+  if (!g.nhubs) return;
   const uint32_t wpv = waves_per_vertex(m, chunk);
   if (g.tm1)
-    hipLaunchKernelGGL(k_hook<true>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+    hipLaunchKernelGGL(k_hook_hubs<true>, grid_for(g.nhubs, wpv), dim3(256), 0, st, g, m, chunk, wpv);
   else
-    hipLaunchKernelGGL(k_hook<false>, grid_for(g.n, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+    hipLaunchKernelGGL(k_hook_hubs<false>, grid_for(g.nhubs, wpv), dim3(256), 0, st, g, m, chunk, wpv);
+}
+
+void launch_lists(const MemoView& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_lists, dim3(kSubLists), dim3(256), 0, st, m);
 }
 
 

@@ -61,6 +61,8 @@ struct GraphView {
   const uint32_t* col;      // [nnz] ascending per row
   const uint32_t* split;    // [n]  first slot of row v whose neighbour is > v
   const uint32_t* tm1;      // [nnz] per-slot T-1, or nullptr (uniform p)
+  const uint32_t* hubs;     // [nhubs] vertices with more than kWave device neighbours
+  uint32_t nhubs;
 };
 
 // Per-memo device view.
@@ -77,10 +79,12 @@ struct MemoView {
   const uint32_t* xs;   // [Rs] X of column q (ascending for q < R)
   int32_t* M;           // [n][Rs]
   uint32_t* tmask;      // [n][mwords]  tile may hold a non-singleton column
+  uint32_t* lmask;      // [n][mwords]  tile has a column with two or more
+                        //              live smaller neighbours (needs k_link)
   int64_t* g0;          // [n]
-  // work lists written by k_hook, entries v * ntiles + t, split into
-  // kSubLists sub-lists (by hook workgroup) of capacity list_cap each so
-  // that appends do not all hit one counter:
+  // work lists built from the masks by k_lists, entries v * ntiles + t,
+  // split into kSubLists sub-lists by vertex range (sub-list j holds the
+  // vertices [j * ceil(n / kSubLists), (j + 1) * ceil(n / kSubLists))):
   uint32_t* tlist;      // tiles with a candidate edge (k_flatten, k_gain0)
   uint32_t* llist;      // tiles with a column of two or more live smaller
                         // neighbours (k_link)
@@ -91,13 +95,10 @@ struct MemoView {
 constexpr uint32_t kSubLists = 256;
 constexpr uint32_t kListBlocks = 8192;  // fixed grid of the list kernels (multiple of kSubLists)
 
-// Capacity of one sub-list.  Hook workgroup b (4 wavefronts of at most 32
-// tiles, blocks = ceil(n * wpv / 4) with wpv * chunk < ntiles + chunk)
-// writes at most 128 entries to sub-list b % kSubLists, and a sub-list
-// serves at most n * wpv / 1024 + 2 workgroups, so it receives at most
-// n * (ntiles + 31) / 256 + 256 entries.
+// Capacity of one sub-list: it holds the tiles of at most ceil(n / kSubLists)
+// vertices, each listed at most once.
 inline uint32_t list_capacity(uint32_t n, uint32_t ntiles) {
-  return (uint32_t)(((uint64_t)n * (ntiles + 32) + kSubLists - 1) / kSubLists + 512);
+  return (uint32_t)((uint64_t)((n + kSubLists - 1) / kSubLists) * ntiles);
 }
 
 struct CelfState {

@@ -13,7 +13,9 @@ void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, ui
 
 // cc.hip
 void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st);
-void launch_hook(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_hook_rows(const GraphView& g, const MemoView& m, hipStream_t st);
+void launch_hook_hubs(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_lists(const MemoView& m, hipStream_t st);
 void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_compress(const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_count(const MemoView& m, hipStream_t st);

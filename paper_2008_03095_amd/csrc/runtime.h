@@ -36,6 +36,7 @@ struct Memo {
   uint64_t* scratch = nullptr;
   int32_t* M = nullptr;
   uint32_t* tmask = nullptr;
+  uint32_t* lmask = nullptr;
   int64_t* g0 = nullptr;
   uint32_t* tlist = nullptr;
   uint32_t* llist = nullptr;
@@ -129,6 +130,8 @@ struct im_graph {
   uint32_t* col = nullptr;
   uint32_t* split = nullptr;
   uint32_t* tm1 = nullptr;
+  uint32_t* hubs = nullptr;  // vertices with more than kWave device neighbours
+  uint32_t nhubs = 0;
   double p = 0.0;
   uint32_t R = 0, seed = 0;
   bool params_set = false;

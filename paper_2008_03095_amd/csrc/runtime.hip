@@ -25,6 +25,8 @@ infuse::GraphView im_graph::view() const {
   v.col = col;
   v.split = split;
   v.tm1 = per_edge ? tm1 : nullptr;
+  v.hubs = hubs;
+  v.nhubs = nhubs;
   return v;
 }
 
@@ -178,6 +180,7 @@ MemoView Memo::view(const im_graph* g) const {
   v.xs = xs;
   v.M = M;
   v.tmask = tmask;
+  v.lmask = lmask;
   v.g0 = g0;
   v.tlist = tlist;
   v.llist = llist;
@@ -205,7 +208,7 @@ uint64_t memo_bytes(const im_graph* g, uint32_t R) {
   b += align256((size_t)Rs * 4) * 2 + align256((size_t)R * 4);
   b += align256((size_t)x_sort_scratch_elems(R) * 8);
   b += align256((size_t)g->n * Rs * 4);
-  b += align256((size_t)g->n * mwords * 4);
+  b += align256((size_t)g->n * mwords * 4) * 2;
   b += align256((size_t)g->n * 8);
   b += align256((size_t)list_capacity(g->n, ntiles) * kSubLists * 4) * 2;
   b += align256((size_t)kSubLists * 2 * 4);
@@ -254,6 +257,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->scratch = reinterpret_cast<uint64_t*>(take((size_t)x_sort_scratch_elems(R) * 8));
   m->M = reinterpret_cast<int32_t*>(take((size_t)g->n * m->Rs * 4));
   m->tmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
+  m->lmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
   m->g0 = reinterpret_cast<int64_t*>(take((size_t)g->n * 8));
   m->list_cap = list_capacity(g->n, m->ntiles);
   m->tlist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
@@ -278,11 +282,20 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
   }
   launch_fill_u32(m->tmask, (uint64_t)g->n * m->mwords, 0u, st);
+  launch_fill_u32(m->lmask, (uint64_t)g->n * m->mwords, 0u, st);
   launch_fill_u32(m->counts, kSubLists * 2, 0u, st);
   if (timed) (void)hipEventRecord(g->ev[1], st);
   {
     KTimer t(c, "hook", st);
-    launch_hook(g->view(), mv, chunk_tiles, st);
+    launch_hook_rows(g->view(), mv, st);
+  }
+  if (g->nhubs) {
+    KTimer t(c, "hook_hubs", st);
+    launch_hook_hubs(g->view(), mv, chunk_tiles, st);
+  }
+  {
+    KTimer t(c, "lists", st);
+    launch_lists(mv, st);
   }
   {
     KTimer t(c, "link", st);
@@ -646,6 +659,9 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     split[u] = (uint32_t)(std::lower_bound(col.begin() + rp[u], col.end(), u) - col.begin());
   }
   rp[n] = (uint32_t)col.size();
+  std::vector<uint32_t> hubs;
+  for (uint32_t u = 0; u < n; ++u)
+    if (rp[u + 1] - rp[u] > (uint32_t)kWave) hubs.push_back(u);
   im_graph* g = new im_graph();
   g->ctx = c;
   g->n = n;
@@ -654,8 +670,10 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   g->per_edge = p_slot != nullptr;
   const size_t b_rp = align256((size_t)(n + 1) * 4), b_col = align256((size_t)g->nnz * 4 + 4);
   const size_t b_split = align256((size_t)n * 4), b_tm1 = p_slot ? align256((size_t)g->nnz * 4 + 4) : 0;
+  const size_t b_hubs = align256((size_t)hubs.size() * 4 + 4);
+  g->nhubs = (uint32_t)hubs.size();
   void* base = nullptr;
-  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1, &base);
+  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs, &base);
   if (s != IM_OK) {
     delete g;
     return s;
@@ -666,6 +684,7 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   g->col = reinterpret_cast<uint32_t*>(p8 + b_rp);
   g->split = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col);
   g->tm1 = p_slot ? reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split) : nullptr;
+  g->hubs = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1);
   hipError_t e = hipMemcpyAsync(g->row_ptr, rp.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nnz)
     e = hipMemcpyAsync(g->col, col.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
@@ -673,6 +692,8 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     e = hipMemcpyAsync(g->split, split.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && p_slot && g->nnz)
     e = hipMemcpyAsync(g->tm1, tm1.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && g->nhubs)
+    e = hipMemcpyAsync(g->hubs, hubs.data(), (size_t)g->nhubs * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     ctx_free(c, base);
