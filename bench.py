@@ -107,7 +107,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--cc-chunk", type=int, default=0, help="columns per wavefront in labelling")
-    ap.add_argument("--celf-width", type=int, default=0, help="CELF candidates per round")
+    ap.add_argument("--celf-width", type=int, default=0, help="CELF candidates per round (per-step mode)")
+    ap.add_argument("--celf-mode", type=int, default=0, help="1 persistent kernel, 2 per-step kernels")
+    ap.add_argument("--celf-round0", type=int, default=None,
+                    help="persistent CELF: candidates of a step's first round (0 = automatic)")
     ap.add_argument("--profile-celf", action="store_true",
                     help="also time every CELF launch (perturbs the step time)")
     args = ap.parse_args()
@@ -131,7 +134,8 @@ def main():
     p, R, K, seed = w.p, w.R, w.K, w.seeds[0]
 
     ctx = P.Context(device=0)
-    ctx.set_tuning(cc_chunk=args.cc_chunk, celf_width=args.celf_width)
+    ctx.set_tuning(cc_chunk=args.cc_chunk, celf_width=args.celf_width, celf_mode=args.celf_mode,
+                   celf_round0=args.celf_round0)
     G = P.Graph.from_csr(ctx, g)
     G.set_params(p, R, seed)
 

@@ -162,13 +162,17 @@ uint64_t im_graph_nnz(const im_graph *g);
  *   use_graphs  1 = replay CELF rounds from a captured hipGraph
  *   celf_mode   1 = all greedy steps in one persistent cooperative kernel
  *               (default where the device supports cooperative launch),
- *               2 = one launch per step and phase                            */
+ *               2 = one launch per step and phase
+ *   celf_round0 persistent kernel: candidates re-evaluated in the first round
+ *               of a step (doubling in later rounds); 0 = automatic (16,
+ *               fewer when that exceeds one tile per wavefront)              */
 typedef struct {
     uint32_t cc_chunk;
     uint32_t celf_width;
     uint32_t use_graphs;
     uint32_t celf_mode;
-    uint32_t reserved[4];
+    uint32_t celf_round0;
+    uint32_t reserved[3];
 } im_tuning;
 im_status im_set_tuning(im_ctx *ctx, const im_tuning *t);
 im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);

@@ -91,19 +91,21 @@ class Context:
     CELF_PERSISTENT, CELF_PER_STEP = 1, 2
 
     def set_tuning(self, cc_chunk: int = 0, celf_width: int = 0, use_graphs: Optional[bool] = None,
-                   celf_mode: int = 0):
+                   celf_mode: int = 0, celf_round0: Optional[int] = None):
         t = im_tuning()
         t.cc_chunk = cc_chunk
         t.celf_width = celf_width
         t.use_graphs = 0 if use_graphs is None else (1 if use_graphs else 2)
         t.celf_mode = celf_mode
+        # celf_round0: None keeps the current value, 0 selects automatic
+        t.celf_round0 = 0xFFFFFFFF if celf_round0 is None else int(celf_round0)
         check(self._lib.im_set_tuning(self.handle, C.byref(t)))
 
     def tuning(self) -> dict:
         t = im_tuning()
         check(self._lib.im_get_tuning(self.handle, C.byref(t)))
         return dict(cc_chunk=t.cc_chunk, celf_width=t.celf_width, use_graphs=bool(t.use_graphs),
-                    celf_mode=t.celf_mode)
+                    celf_mode=t.celf_mode, celf_round0=t.celf_round0)
 
     def set_profiling(self, level):
         """0/False: off; 1/True: per-build kernels; 2: also every CELF launch."""

@@ -32,7 +32,7 @@ class im_allocator(C.Structure):
 
 class im_tuning(C.Structure):
     _fields_ = [("cc_chunk", C.c_uint32), ("celf_width", C.c_uint32), ("use_graphs", C.c_uint32),
-                ("celf_mode", C.c_uint32), ("reserved", C.c_uint32 * 4)]
+                ("celf_mode", C.c_uint32), ("celf_round0", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class im_server_config(C.Structure):

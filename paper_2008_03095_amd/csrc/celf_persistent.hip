@@ -69,7 +69,6 @@ struct PCelfArgs {
   CelfView c;
   PCelfScratch* x;
   uint32_t* blist;   // [n] bulk candidates
-  uint64_t* bgain;   // [n] their gains
   uint32_t w0;       // candidates of the first round of a step
 };
 
@@ -247,6 +246,48 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
     const uint32_t lroot = lv[i] < 0 ? last : (uint32_t)lv[i];
     const bool covered = ((word[i] >> (q & 31)) & 1u) || (last != kInvalid && lroot == root[i]);
     sum += covered ? 0 : (uint64_t)size[i];
+  }
+  return sum;
+}
+
+// This lane's share of gain(u | S) over the B tiles t0 .. t0 + B - 1 (t0 a
+// multiple of B, B dividing 32, tiles past the row are skipped).  Coverage
+// is read from the bitmap only, so every commit must be visible.  The loads
+// of all B tiles are issued before any is used.
+template <int B>
+__device__ inline uint64_t p_eval_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane) {
+  const MemoView& m = c.m;
+  const uint32_t bits = p_uni(m.tmask[(uint64_t)u * m.mwords + (t0 >> 5)]) >> (t0 & 31);
+  int4 cur[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    cur[b] = make_int4(-1, -1, -1, -1);
+    if (((bits >> b) & 1u) && t0 + b < m.ntiles)
+      cur[b] = *reinterpret_cast<const int4*>(m.M + (uint64_t)u * m.Rs + (t0 + b) * kTile + lane * kPerLane);
+  }
+  int32_t size[B][4];
+  uint32_t word[B][4];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
+    const int32_t vals[4] = {cur[b].x, cur[b].y, cur[b].z, cur[b].w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int32_t val = vals[i];
+      const bool shared = q0 + i < m.R && val != -1;
+      const uint32_t root = val < 0 ? u : (uint32_t)val;
+      size[b][i] = val < 0 ? -val : (shared ? -m.M[(uint64_t)val * m.Rs + q0 + i] : 0);
+      word[b][i] = shared ? ld32(&c.cov[(uint64_t)root * c.cwords + ((q0 + i) >> 5)]) : 0u;
+    }
+  }
+  uint64_t sum = 0;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
+    if (t0 + b >= m.ntiles) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (q0 + i < m.R) sum += ((word[b][i] >> ((q0 + i) & 31)) & 1u) ? 0 : (uint64_t)size[b][i];
   }
   return sum;
 }
@@ -535,7 +576,7 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
 }
 
 // Bulk evaluation of every stale vertex whose key exceeds kstar.
-__device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32_t last, uint32_t& gen,
+__device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32_t& gen,
                           PClock& clk, uint64_t& evals) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
@@ -563,25 +604,22 @@ __device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32
     if (take) {
       const uint32_t at = slot0 + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
       st32(&a.blist[at], v);
-      st64(&a.bgain[at], 0ull);
     }
   }
   if (!grid_sync(x, gen, clk, PClock::kBulk)) return false;
   const uint32_t cnt = ld32(&x->bulk_cnt);
-  // 2. gains, one (vertex, tile) per wave job
-  const uint64_t items = (uint64_t)cnt * ntiles;
-  for (uint64_t it = gw; it < items; it += nw) {
-    const uint32_t w = (uint32_t)(it / ntiles), t = (uint32_t)(it - (uint64_t)w * ntiles);
-    const uint32_t v = ld32(&a.blist[w]);
-    const uint64_t part = p_wsum(p_eval_tile(c, v, t, lane, last));
-    if (lane == 0 && part) atomicAdd((unsigned long long*)&a.bgain[w], (unsigned long long)part);
-  }
-  if (!grid_sync(x, gen, clk, PClock::kBulk)) return false;
-  // 3. new keys
-  for (uint32_t w = gtid; w < cnt; w += gstride) {
-    const uint32_t v = ld32(&a.blist[w]);
-    st64(&c.key[v], p_make_key(c, ld64(&a.bgain[w]), v));
-    st32(&c.iter[v], s);
+  // 2. one wavefront per candidate: the gain over all tiles, four at a time;
+  // the keys are read by the rebuild that follows, after its barrier
+  constexpr int kB = 4;
+  for (uint32_t w = gw; w < cnt; w += nw) {
+    const uint32_t v = p_uni(ld32(&a.blist[w]));
+    uint64_t sum = 0;
+    for (uint32_t t = 0; t < ntiles; t += kB) sum += p_eval_tiles<kB>(c, v, t, lane);
+    sum = p_wsum(sum);
+    if (lane == 0) {
+      st64(&c.key[v], p_make_key(c, sum, v));
+      st32(&c.iter[v], s);
+    }
   }
   evals += cnt;
   ++clk.bulks;
@@ -698,7 +736,7 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
       return;
     }
     if (nf && step_rebuilds > 0)
-      if (!bulk_eval(a, s, fbest, last, gen, clk, evals)) return;
+      if (!bulk_eval(a, s, fbest, gen, clk, evals)) return;
     if (!pool_rebuild(a, L, s, gen, clk)) return;
     ++step_rebuilds;
     if (L.ns == 0 && L.nf == 0) {  // no unselected vertex: cannot happen for K <= n
@@ -736,15 +774,15 @@ uint32_t pcelf_grid(int device) {
   return (uint32_t)cus * (uint32_t)std::min(per, 2);
 }
 
-hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint64_t* bgain,
-                                  uint32_t grid, hipStream_t st) {
+hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint32_t grid,
+                                  uint32_t round0, hipStream_t st) {
   PCelfArgs a;
   a.c = c;
   a.x = static_cast<PCelfScratch*>(scratch);
   a.blist = blist;
-  a.bgain = bgain;
   const uint32_t waves = grid * (kPBlock / 64);
-  a.w0 = std::max(8u, std::min(kMaxCand, (waves + c.m.ntiles - 1) / c.m.ntiles));
+  // default: 16 candidates, or fewer when 16 would exceed one tile per wavefront
+  a.w0 = round0 ? std::min(kMaxCand, round0) : std::max(1u, std::min(16u, (waves + c.m.ntiles - 1) / c.m.ntiles));
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_celf_persistent), dim3(grid), dim3(kPBlock),
                                     args, 0, st);

@@ -34,8 +34,8 @@ uint64_t pcelf_scratch_bytes();
 uint64_t pcelf_err_offset();   // u32 error flag of the persistent kernel
 uint64_t pcelf_prof_offset();  // 8 x u64: phase ticks (100 MHz) x5, barriers, rounds, rebuilds
 uint32_t pcelf_grid(int device);
-hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint64_t* bgain,
-                                  uint32_t grid, hipStream_t st);
+hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint32_t grid,
+                                  uint32_t round0, hipStream_t st);
 
 // query.hip
 uint32_t sigma_pair_max();

@@ -54,7 +54,6 @@ struct CelfBuffers {
   CelfView v;
   void* pscratch = nullptr;  // state of the persistent kernel
   uint32_t* blist = nullptr;  // [n] persistent kernel: bulk candidates
-  uint64_t* bgain = nullptr;  // [n] and their gains
   bool persistent = false;   // enqueued as one persistent kernel
 };
 

@@ -377,7 +377,7 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   b += align256((size_t)std::max(K, 1u) * 4) + align256((size_t)std::max(K, 1u) * 8);
   b += align256(sizeof(CelfState));
   b += align256(pcelf_scratch_bytes());
-  b += align256((size_t)n * 4) + align256((size_t)n * 8);
+  b += align256((size_t)n * 4);
   void* base = nullptr;
   im_status s = ctx_alloc(c, b, &base);
   if (s != IM_OK) return s;
@@ -406,7 +406,6 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   v.st = reinterpret_cast<CelfState*>(take(sizeof(CelfState)));
   cb->pscratch = take(pcelf_scratch_bytes());
   cb->blist = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
-  cb->bgain = reinterpret_cast<uint64_t*>(take((size_t)n * 8));
   cb->persistent = false;
   return IM_OK;
 }
@@ -424,7 +423,7 @@ void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
     hipError_t e;
     {
       KTimer t(c, "celf", st, 1);
-      e = launch_celf_persistent(v, cb->pscratch, cb->blist, cb->bgain, c->coop_grid, st);
+      e = launch_celf_persistent(v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0, st);
     }
     if (e == hipSuccess) {
       (void)hipEventRecord(c->coop_done, st);
@@ -566,6 +565,10 @@ extern "C" im_status im_set_tuning(im_ctx* c, const im_tuning* t) {
     if (t->celf_mode == 1 && !c->coop_grid)
       return fail(IM_ERR_INVALID_ARG, "the device cannot run the persistent CELF kernel");
     c->tune.celf_mode = t->celf_mode;
+  }
+  if (t->celf_round0 != 0xFFFFFFFFu) {
+    if (t->celf_round0 > 1024) return fail(IM_ERR_INVALID_ARG, "celf_round0 must be <= 1024");
+    c->tune.celf_round0 = t->celf_round0;
   }
   return IM_OK;
 }

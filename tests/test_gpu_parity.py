@@ -239,22 +239,31 @@ CELF_CASES = {
 }
 
 
-@pytest.mark.parametrize("mode", [P.Context.CELF_PERSISTENT, P.Context.CELF_PER_STEP])
+CELF_VARIANTS = {
+    "persistent": (P.Context.CELF_PERSISTENT, 0),
+    # one candidate in a step's first round: many rounds, pool refills and bulk passes
+    "persistent_round1": (P.Context.CELF_PERSISTENT, 1),
+    "per_step": (P.Context.CELF_PER_STEP, 0),
+}
+
+
+@pytest.mark.parametrize("variant", list(CELF_VARIANTS))
 @pytest.mark.parametrize("case", list(CELF_CASES))
-def test_celf_modes(gpu_ctx, case, mode):
+def test_celf_modes(gpu_ctx, case, variant):
+    mode, round0 = CELF_VARIANTS[variant]
     make, p, R, seed, K = CELF_CASES[case]
     g = make()
-    announce(f"CELF mode {mode} {case} n={g.n} K={K}")
+    announce(f"CELF {variant} {case} n={g.n} K={K}")
     ref = oracle.run_memo(g, oracle.Sampler("hash", p=p, R=R, seed=seed), K, threads=4)
     old = gpu_ctx.tuning()
     G = P.Graph.from_csr(gpu_ctx, g)
     try:
-        gpu_ctx.set_tuning(celf_mode=mode)
+        gpu_ctx.set_tuning(celf_mode=mode, celf_round0=round0)
         G.set_params(p, R, seed)
         seeds, marg, cover = G.select_seeds(K)
         assert list(seeds) == list(ref["seeds"])
         assert list(marg) == list(ref["marginal"])
         assert cover == ref["cover"]
     finally:
-        gpu_ctx.set_tuning(celf_mode=old["celf_mode"])
+        gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
         G.free()
