@@ -175,7 +175,8 @@ def main():
     traffic = read_traffic()
     phases /= args.steps
     t_cc = phases[1]
-    names = ["edge_hash", "x_sort", "hook", "hook_hubs", "lists", "link", "flatten", "count", "gain0",
+    names = ["edge_hash", "x_sort", "hook", "hook_hubs", "lists", "link", "link_hubs", "flatten", "count",
+             "gain0",
              "sigma", "celf",
              "celf_topw", "celf_eval", "celf_bulk"]
     if args.profile_celf:
@@ -218,6 +219,7 @@ def main():
         },
         "cpu_baseline": None,
     }
+    rec["memo_stats"] = G.memo_stats()
     G.free()
     ctx.close()
     if not args.no_cpu_baseline:

@@ -156,9 +156,11 @@ uint64_t im_graph_nnz(const im_graph *g);
 /* ---- tuning and measurement ------------------------------------------- */
 
 /* Kernel-launch shape knobs (0 keeps the current value).
- *   cc_chunk    simulations handled by one wavefront per vertex in the
- *               labelling kernels (multiple of 256)
- *   celf_width  candidates re-evaluated together per CELF round
+ *   cc_chunk    simulations handled by one wavefront of a vertex with more
+ *               than 64 neighbours when its parent pointers are set (256 *
+ *               2^k, at most 8192; default 256); lighter vertices take
+ *               their whole row in one wavefront
+ *   celf_width  per-step mode: candidates re-evaluated together per round
  *   use_graphs  1 = replay CELF rounds from a captured hipGraph
  *   celf_mode   1 = all greedy steps in one persistent cooperative kernel
  *               (default where the device supports cooperative launch),
@@ -195,6 +197,13 @@ im_status im_last_phase_ms(const im_graph *g, double *ms4);
 
 /* Number of CELF evaluations (vertex re-evaluations) of the last selection. */
 uint64_t im_last_celf_evals(const im_graph *g);
+
+/* Work counts of the resident memo for the current parameters (built if
+ * needed; waits for it): out[0] (vertex, 256-column tile) pairs that may
+ * hold a non-singleton component, out[1] pairs with a column of two or more
+ * live smaller neighbours (union work), out[2] vertices with more than 64
+ * neighbours, out[3] memo bytes. */
+im_status im_memo_stats(im_graph *g, uint64_t *out4);
 
 /* ---- batching: many graphs in one launch per phase --------------------- */
 

@@ -198,6 +198,11 @@ class Graph:
     def celf_evals(self) -> int:
         return int(self._lib.im_last_celf_evals(self.handle))
 
+    def memo_stats(self) -> dict:
+        a = (C.c_uint64 * 4)()
+        check(self._lib.im_memo_stats(self.handle, a))
+        return dict(listed_tiles=int(a[0]), link_tiles=int(a[1]), hubs=int(a[2]), memo_bytes=int(a[3]))
+
 
 def batch_select(ctx: Context, graphs: Sequence[Graph], Ks: Sequence[int]):
     """im_batch_select: every graph's memo and selection in batched launches."""

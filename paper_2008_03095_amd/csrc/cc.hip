@@ -17,7 +17,8 @@
 //   k_link     the remaining live edges (u < v, u not the hook of v) are
 //              merged by lock-free union: the larger root is linked under the
 //              smaller with compare-and-swap, so every root stays the minimum
-//              of its tree in any interleaving.
+//              of its tree in any interleaving.  The hook parent stored in the
+//              memo stands for v, so no second scan for it is needed.
 //   k_flatten  every non-root entry is replaced by its root;
 //   k_count    each member decrements its root's -1 once: afterwards roots
 //              hold -|component| (the size memo) and members hold the label.
@@ -306,16 +307,24 @@ __global__ void __launch_bounds__(256) k_lists(MemoView m) {
   }
 }
 
-// Root of x in column q.  During linking entries only move from "root" (-1)
-// to a parent id of a smaller vertex, so a stale value read from a
-// non-coherent cache is an older state of the same tree: the walk still
-// ends, at a vertex that is or was a root of x's tree.  A root seen here
-// that was linked meanwhile is caught by the compare-and-swap in unite.
-__device__ inline uint32_t find_root(const int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
+// Root of x in column q, with path halving.  Every parent has a smaller id
+// than its child (hook parents are smaller neighbours, unions put the larger
+// root under the smaller), and while linking an entry only moves from
+// "root" (-1) to a parent, or from a parent to one of its ancestors.  So a
+// stale value read from a non-coherent cache is still an ancestor (or the
+// root state of a vertex linked meanwhile, caught by the compare-and-swap in
+// unite_root), every step goes to a smaller id and the walk ends.  Each
+// visited entry is re-pointed to its grandparent with an atomic store (the
+// memo is written only by atomics while linking); a value written from a
+// stale read is still an ancestor.
+__device__ inline uint32_t find_root_halving(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
   while (true) {
     const int32_t p = M[(uint64_t)x * Rs + q];
     if (p < 0) return x;
-    x = (uint32_t)p;
+    const int32_t gp = M[(uint64_t)p * Rs + q];
+    if (gp < 0) return (uint32_t)p;
+    __hip_atomic_store(&M[(uint64_t)x * Rs + q], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = (uint32_t)gp;
   }
 }
 
@@ -328,7 +337,7 @@ __device__ inline uint32_t find_root(const int32_t* M, uint32_t Rs, uint32_t x, 
 // atomics in this kernel (the XCD L2 caches are not coherent within a
 // kernel, so plain stores must not share lines with atomics).
 __device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
-  b = find_root(M, Rs, b, q);
+  b = find_root_halving(M, Rs, b, q);
   while (a != b) {
     if (a < b) {
       const uint32_t t = a;
@@ -340,8 +349,8 @@ __device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint3
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return b;
-    a = find_root(M, Rs, (uint32_t)expected, q);
-    b = find_root(M, Rs, b, q);
+    a = find_root_halving(M, Rs, (uint32_t)expected, q);
+    b = find_root_halving(M, Rs, b, q);
   }
   return a;
 }
@@ -398,9 +407,10 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
     const uint32_t e = uni(it.at(idx));
     const uint32_t v = e / m.ntiles, t = e % m.ntiles;
     const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
-    const bool inreg = end - beg <= (uint32_t)kWave;
+    if (end - beg > (uint32_t)kWave) continue;  // hub: k_link_hubs
+    const bool inreg = true;
     uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
-    if (inreg && beg + lane < end) {
+    if (beg + lane < end) {
       const uint2 ed = m.edges[beg + lane];
       rcol = ed.x;
       rh = ed.y;
@@ -408,31 +418,75 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
     }
     TileCtx tc;
     tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
-    int32_t mn[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    // v's hook parent per column: its smallest live smaller neighbour, which
+    // linking never changes (only roots are re-pointed).  A negative entry
+    // means v has no live smaller neighbour in that column.
+    const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
+    const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
+    // root of v's tree per column, looked up when the first further live
+    // smaller neighbour needs joining
+    uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
     for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
                                    [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
 #pragma unroll
                                      for (int i = 0; i < 4; ++i) {
                                        const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
-                                       mn[i] = live ? min(mn[i], (int32_t)u) : mn[i];
-                                     }
-                                   });
-    // v's root per column, found once; every further live smaller
-    // neighbour is joined to it
-    uint32_t rv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      rv[i] = (tc.valid[i] && mn[i] != INT32_MAX) ? find_root(m.M, m.Rs, v, tc.q0 + i) : v;
-    for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
-                                   [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
-#pragma unroll
-                                     for (int i = 0; i < 4; ++i) {
-                                       const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
-                                       if (live && (int32_t)u != mn[i])
+                                       if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
+                                         if (rv[i] == kInvalid)
+                                           rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
                                          rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
+                                       }
                                      }
                                    });
   }
+}
+
+// k_link_hubs: the unions of hub vertices, one wavefront per (hub, tile,
+// piece of 64 smaller neighbours); tiles without an lmask bit are skipped.
+// The piece of a wavefront is found by binary search in the per-hub prefix
+// sums of pieces.
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
+  const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t pg = uni((uint32_t)(wid / m.ntiles)), t = uni((uint32_t)(wid % m.ntiles));
+  if (pg >= g.hub_pieces) return;
+  uint32_t lo = 0, hi = g.nhubs;  // last hub with hub_poff[h] <= pg
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (g.hub_poff[mid] <= pg)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint32_t v = uni(g.hubs[lo]);
+  if (!((m.lmask[(uint64_t)v * m.mwords + (t >> 5)] >> (t & 31)) & 1u)) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t beg = uni(g.row_ptr[v]) + (pg - uni(g.hub_poff[lo])) * (uint32_t)kWave;
+  const uint32_t end = min(beg + (uint32_t)kWave, uni(g.split[v]));  // smaller neighbours only
+  uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
+  if (beg + lane < end) {
+    const uint2 ed = m.edges[beg + lane];
+    rcol = ed.x;
+    rh = ed.y;
+    if (PER_EDGE) rtm1 = g.tm1[beg + lane];
+  }
+  TileCtx tc;
+  tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
+  const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
+  const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
+  uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
+  for_candidates<PER_EDGE, true>(g, m, v, beg, end, end, lane, true, rcol, rh, rtm1, tc,
+                                 [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
+#pragma unroll
+                                   for (int i = 0; i < 4; ++i) {
+                                     const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
+                                     if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
+                                       if (rv[i] == kInvalid)
+                                         rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
+                                       rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
+                                     }
+                                   }
+                                 });
 }
 
 // k_flatten: every non-root entry of a listed tile is replaced by its root
@@ -612,6 +666,16 @@ void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk, hipStrea
     hipLaunchKernelGGL(k_link<true>, dim3(kListBlocks), dim3(256), 0, st, g, m);
   else
     hipLaunchKernelGGL(k_link<false>, dim3(kListBlocks), dim3(256), 0, st, g, m);
+}
+
+void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st) {
+  if (!g.hub_pieces) return;
+  const uint64_t waves = (uint64_t)g.hub_pieces * m.ntiles;
+  const dim3 grid((uint32_t)((waves + 3) / 4));
+  if (g.tm1)
+    hipLaunchKernelGGL(k_link_hubs<true>, grid, dim3(256), 0, st, g, m);
+  else
+    hipLaunchKernelGGL(k_link_hubs<false>, grid, dim3(256), 0, st, g, m);
 }
 
 void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {

@@ -62,7 +62,9 @@ struct GraphView {
   const uint32_t* split;    // [n]  first slot of row v whose neighbour is > v
   const uint32_t* tm1;      // [nnz] per-slot T-1, or nullptr (uniform p)
   const uint32_t* hubs;     // [nhubs] vertices with more than kWave device neighbours
+  const uint32_t* hub_poff; // [nhubs+1] prefix sums of ceil(smaller neighbours / kWave)
   uint32_t nhubs;
+  uint32_t hub_pieces;      // hub_poff[nhubs]
 };
 
 // Per-memo device view.

@@ -17,6 +17,7 @@ void launch_hook_rows(const GraphView& g, const MemoView& m, hipStream_t st);
 void launch_hook_hubs(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_lists(const MemoView& m, hipStream_t st);
 void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st);
 void launch_compress(const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_count(const MemoView& m, hipStream_t st);
 void launch_gain0(const MemoView& m, hipStream_t st);

@@ -45,6 +45,8 @@ struct Memo {
   uint64_t last_use = 0;
   int pins = 0;
   hipEvent_t ready_ev = nullptr;  // recorded after construction
+  hipEvent_t fork_ev = nullptr;   // hub rows run on the context's side stream
+  hipEvent_t join_ev = nullptr;
   MemoView view(const im_graph* g) const;
 };
 
@@ -96,6 +98,7 @@ struct im_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t aux = nullptr;  // side stream for work that overlaps the main stream's
   im_allocator alloc = {nullptr, nullptr, nullptr};
   bool has_alloc = false;
   uint64_t budget = 0;
@@ -130,7 +133,9 @@ struct im_graph {
   uint32_t* split = nullptr;
   uint32_t* tm1 = nullptr;
   uint32_t* hubs = nullptr;  // vertices with more than kWave device neighbours
+  uint32_t* hub_poff = nullptr;  // prefix sums of their 64-slot pieces of smaller neighbours
   uint32_t nhubs = 0;
+  uint32_t hub_pieces = 0;
   double p = 0.0;
   uint32_t R = 0, seed = 0;
   bool params_set = false;

@@ -26,7 +26,9 @@ infuse::GraphView im_graph::view() const {
   v.split = split;
   v.tm1 = per_edge ? tm1 : nullptr;
   v.hubs = hubs;
+  v.hub_poff = hub_poff;
   v.nhubs = nhubs;
+  v.hub_pieces = hub_pieces;
   return v;
 }
 
@@ -193,6 +195,8 @@ void memo_destroy(im_graph* g, Memo* m) {
   auto& v = g->memos;
   v.erase(std::remove(v.begin(), v.end(), m), v.end());
   if (m->ready_ev) (void)hipEventDestroy(m->ready_ev);
+  if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
+  if (m->join_ev) (void)hipEventDestroy(m->join_ev);
   ctx_free(g->ctx, m->base);
   delete m;
 }
@@ -236,10 +240,16 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->never_live = (!g->per_edge && T == 0) ? 1u : 0u;
   m->tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
   m->kshift = bitlen32(m->tm1);
+  if (g->nhubs) {
+    if (hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming) != hipSuccess) m->fork_ev = nullptr;
+    if (hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming) != hipSuccess) m->join_ev = nullptr;
+  }
   m->bytes = memo_bytes(g, R);
   void* base = nullptr;
   im_status s = ctx_alloc(c, m->bytes, &base);
   if (s != IM_OK) {
+    if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
+    if (m->join_ev) (void)hipEventDestroy(m->join_ev);
     delete m;
     return s;
   }
@@ -285,11 +295,25 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   launch_fill_u32(m->lmask, (uint64_t)g->n * m->mwords, 0u, st);
   launch_fill_u32(m->counts, kSubLists * 2, 0u, st);
   if (timed) (void)hipEventRecord(g->ev[1], st);
+  // hub rows (few, long, latency-bound wavefronts) run on the side stream
+  // next to the bandwidth-bound light rows; the two write disjoint rows
+  const bool fork = g->nhubs && c->aux && m->fork_ev && m->join_ev;
+  if (fork) {
+    (void)hipEventRecord(m->fork_ev, st);
+    (void)hipStreamWaitEvent(c->aux, m->fork_ev, 0);
+    {
+      KTimer t(c, "hook_hubs", c->aux);
+      launch_hook_hubs(g->view(), mv, chunk_tiles, c->aux);
+    }
+    (void)hipEventRecord(m->join_ev, c->aux);
+  }
   {
     KTimer t(c, "hook", st);
     launch_hook_rows(g->view(), mv, st);
   }
-  if (g->nhubs) {
+  if (fork) {
+    (void)hipStreamWaitEvent(st, m->join_ev, 0);
+  } else if (g->nhubs) {
     KTimer t(c, "hook_hubs", st);
     launch_hook_hubs(g->view(), mv, chunk_tiles, st);
   }
@@ -297,9 +321,28 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     KTimer t(c, "lists", st);
     launch_lists(mv, st);
   }
+  // unions of hub vertices, one wavefront per (hub, tile, 64 smaller
+  // neighbours), on the side stream next to the light vertices' unions (both
+  // write the memo only by atomics)
+  const bool fork2 = g->hub_pieces && c->aux && m->fork_ev && m->join_ev;
+  if (fork2) {
+    (void)hipEventRecord(m->fork_ev, st);
+    (void)hipStreamWaitEvent(c->aux, m->fork_ev, 0);
+    {
+      KTimer t(c, "link_hubs", c->aux);
+      launch_link_hubs(g->view(), mv, c->aux);
+    }
+    (void)hipEventRecord(m->join_ev, c->aux);
+  }
   {
     KTimer t(c, "link", st);
     launch_link(g->view(), mv, chunk_tiles, st);
+  }
+  if (fork2) {
+    (void)hipStreamWaitEvent(st, m->join_ev, 0);
+  } else if (g->hub_pieces) {
+    KTimer t(c, "link_hubs", st);
+    launch_link_hubs(g->view(), mv, st);
   }
   {
     KTimer t(c, "flatten", st);
@@ -522,7 +565,8 @@ extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator*
     }
     c->own_stream = true;
   }
-  c->tune.cc_chunk = 1024;
+  if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) c->aux = nullptr;
+  c->tune.cc_chunk = 256;
   c->tune.celf_width = 16;
   c->tune.use_graphs = 0;
   c->coop_grid = pcelf_grid(device);
@@ -541,6 +585,10 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   resolve_pending(c);
   while (!c->graphs.empty()) im_graph_free(c->graphs.back());
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
   if (c->coop_done) (void)hipEventDestroy(c->coop_done);
   delete c;
 }
@@ -662,9 +710,12 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     split[u] = (uint32_t)(std::lower_bound(col.begin() + rp[u], col.end(), u) - col.begin());
   }
   rp[n] = (uint32_t)col.size();
-  std::vector<uint32_t> hubs;
+  std::vector<uint32_t> hubs, hub_poff(1, 0);
   for (uint32_t u = 0; u < n; ++u)
-    if (rp[u + 1] - rp[u] > (uint32_t)kWave) hubs.push_back(u);
+    if (rp[u + 1] - rp[u] > (uint32_t)kWave) {
+      hubs.push_back(u);
+      hub_poff.push_back(hub_poff.back() + (split[u] - rp[u] + kWave - 1) / kWave);
+    }
   im_graph* g = new im_graph();
   g->ctx = c;
   g->n = n;
@@ -674,9 +725,11 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   const size_t b_rp = align256((size_t)(n + 1) * 4), b_col = align256((size_t)g->nnz * 4 + 4);
   const size_t b_split = align256((size_t)n * 4), b_tm1 = p_slot ? align256((size_t)g->nnz * 4 + 4) : 0;
   const size_t b_hubs = align256((size_t)hubs.size() * 4 + 4);
+  const size_t b_poff = align256((size_t)hub_poff.size() * 4);
   g->nhubs = (uint32_t)hubs.size();
+  g->hub_pieces = hub_poff.back();
   void* base = nullptr;
-  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs, &base);
+  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff, &base);
   if (s != IM_OK) {
     delete g;
     return s;
@@ -688,6 +741,7 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   g->split = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col);
   g->tm1 = p_slot ? reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split) : nullptr;
   g->hubs = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1);
+  g->hub_poff = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1 + b_hubs);
   hipError_t e = hipMemcpyAsync(g->row_ptr, rp.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nnz)
     e = hipMemcpyAsync(g->col, col.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
@@ -697,6 +751,8 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     e = hipMemcpyAsync(g->tm1, tm1.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nhubs)
     e = hipMemcpyAsync(g->hubs, hubs.data(), (size_t)g->nhubs * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->hub_poff, hub_poff.data(), hub_poff.size() * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     ctx_free(c, base);
@@ -969,3 +1025,27 @@ extern "C" im_status im_last_phase_ms(const im_graph* g, double* ms4) {
 }
 
 extern "C" uint64_t im_last_celf_evals(const im_graph* g) { return g ? g->last_evals : 0; }
+
+extern "C" im_status im_memo_stats(im_graph* g, uint64_t* out4) {
+  if (!g || !out4) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  Memo* m = nullptr;
+  im_status s = memo_acquire(g, &m);
+  if (s != IM_OK) return s;
+  std::vector<uint32_t> counts(kSubLists * 2);
+  hipError_t e = hipMemcpyAsync(counts.data(), m->counts, counts.size() * 4, hipMemcpyDeviceToHost, g->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->ctx->stream);
+  if (e == hipSuccess) {
+    uint64_t t = 0, l = 0;
+    for (uint32_t j = 0; j < kSubLists; ++j) {
+      t += counts[2 * j];
+      l += counts[2 * j + 1];
+    }
+    out4[0] = t;
+    out4[1] = l;
+    out4[2] = g->nhubs;
+    out4[3] = m->bytes;
+  }
+  memo_release(g, m);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo statistics copy failed: %s", hipGetErrorString(e));
+  return IM_OK;
+}
