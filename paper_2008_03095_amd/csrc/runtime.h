@@ -65,6 +65,7 @@ void ctx_free(im_ctx* c, void* p);
 void memo_destroy(im_graph* g, Memo* m);
 uint64_t memo_bytes(const im_graph* g, uint32_t R);
 Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed);
+bool memo_matches(const im_graph* g, const Memo* m, double p, uint32_t R, uint32_t seed);
 im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out);
 im_status memo_acquire(im_graph* g, Memo** out);
 void memo_release(im_graph* g, Memo* m);
@@ -94,6 +95,19 @@ class KTimer {
 
 }  // namespace infuse
 
+namespace infuse {
+// Sub-allocator over one reservation of the context's whole budget: best fit
+// from the free ranges, which are merged with their neighbours when freed.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> by_off;        // free ranges: offset -> size
+  std::multimap<size_t, size_t> by_size;  // free ranges: size -> offset
+  void* take(size_t bytes);
+  void give(void* p, size_t bytes);
+};
+}  // namespace infuse
+
 struct im_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -103,6 +117,8 @@ struct im_ctx {
   bool has_alloc = false;
   uint64_t budget = 0;
   uint64_t in_use = 0;
+  infuse::Arena arena;     // used when budget > 0 and the reservation succeeded
+  bool arena_tried = false;
   uint64_t use_clock = 0;
   uint64_t evictions = 0;
   uint64_t last_bulk_rounds = 0;
@@ -115,6 +131,10 @@ struct im_ctx {
   std::recursive_mutex mu;
   // persistent CELF: workgroups of a cooperative launch (0: unavailable),
   // and the completion of the last one enqueued
+  // serving loop hook: number of queued queries that want memo m of graph g
+  // (evictions prefer memos nobody waits for)
+  uint32_t (*memo_demand)(void* user, const im_graph* g, const infuse::Memo* m) = nullptr;
+  void* memo_demand_user = nullptr;
   uint32_t coop_grid = 0;
   hipEvent_t coop_done = nullptr;
   bool coop_pending = false;

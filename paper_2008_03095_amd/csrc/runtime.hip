@@ -76,15 +76,63 @@ static void* raw_alloc(im_ctx* c, size_t bytes) {
   return p;
 }
 
+// Evicts one unpinned memo: the least recently used among those no queued
+// serving query wants, else the least wanted, least recently used one.
+void* Arena::take(size_t bytes) {
+  auto it = by_size.lower_bound(bytes);
+  if (it == by_size.end()) return nullptr;
+  const size_t sz = it->first, off = it->second;
+  by_size.erase(it);
+  by_off.erase(off);
+  if (sz > bytes) {
+    by_off[off + bytes] = sz - bytes;
+    by_size.emplace(sz - bytes, off + bytes);
+  }
+  return base + off;
+}
+
+void Arena::give(void* p, size_t bytes) {
+  size_t off = static_cast<size_t>(static_cast<char*>(p) - base), sz = bytes;
+  auto erase_range = [&](std::map<size_t, size_t>::iterator r) {
+    auto range = by_size.equal_range(r->second);
+    for (auto q = range.first; q != range.second; ++q)
+      if (q->second == r->first) {
+        by_size.erase(q);
+        break;
+      }
+    return by_off.erase(r);
+  };
+  auto next = by_off.lower_bound(off);
+  if (next != by_off.end() && next->first == off + sz) {
+    sz += next->second;
+    next = erase_range(next);
+  }
+  if (next != by_off.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      off = prev->first;
+      sz += prev->second;
+      erase_range(prev);
+    }
+  }
+  by_off[off] = sz;
+  by_size.emplace(sz, off);
+}
+
 static bool evict_one(im_ctx* c) {
   Memo* victim = nullptr;
   im_graph* owner = nullptr;
+  uint32_t vd = 0;
   for (im_graph* g : c->graphs)
-    for (Memo* m : g->memos)
-      if (m->pins == 0 && (!victim || m->last_use < victim->last_use)) {
+    for (Memo* m : g->memos) {
+      if (m->pins != 0) continue;
+      const uint32_t d = c->memo_demand ? c->memo_demand(c->memo_demand_user, g, m) : 0;
+      if (!victim || d < vd || (d == vd && m->last_use < victim->last_use)) {
         victim = m;
         owner = g;
+        vd = d;
       }
+    }
   if (!victim) return false;
   memo_destroy(owner, victim);
   c->evictions++;
@@ -103,8 +151,27 @@ im_status ctx_alloc(im_ctx* c, size_t bytes, void** out) {
     if (!evict_one(c))
       return fail(IM_ERR_BUDGET, "budget exhausted: %llu in use, %zu requested, budget %llu",
                   (unsigned long long)c->in_use, bytes, (unsigned long long)c->budget);
-  void* p = raw_alloc(c, bytes);
-  while (!p && evict_one(c)) p = raw_alloc(c, bytes);
+  if (c->budget && !c->arena_tried) {
+    // one reservation of the whole budget, carved up by the arena
+    c->arena_tried = true;
+    c->arena.base = static_cast<char*>(raw_alloc(c, c->budget));
+    if (c->arena.base) {
+      c->arena.size = c->budget;
+      c->arena.by_off[0] = c->budget;
+      c->arena.by_size.emplace(c->budget, 0);
+    }
+  }
+  void* p = nullptr;
+  if (c->arena.base) {
+    p = c->arena.take(bytes);
+    while (!p && evict_one(c)) p = c->arena.take(bytes);
+    if (!p)
+      return fail(IM_ERR_BUDGET, "no free range of %zu bytes in the context budget (%llu in use)", bytes,
+                  (unsigned long long)c->in_use);
+  } else {
+    p = raw_alloc(c, bytes);
+    while (!p && evict_one(c)) p = raw_alloc(c, bytes);
+  }
   if (!p) return fail(IM_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
   c->in_use += bytes;
   c->sizes[p] = bytes;
@@ -116,11 +183,17 @@ void ctx_free(im_ctx* c, void* p) {
   if (!p) return;
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   auto it = c->sizes.find(p);
+  size_t bytes = 0;
   if (it != c->sizes.end()) {
-    c->in_use -= it->second;
+    bytes = it->second;
+    c->in_use -= bytes;
     c->sizes.erase(it);
   }
-  raw_free(c, p);
+  const char* q = static_cast<const char*>(p);
+  if (c->arena.base && q >= c->arena.base && q < c->arena.base + c->arena.size)
+    c->arena.give(p, bytes);
+  else
+    raw_free(c, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,6 +267,9 @@ MemoView Memo::view(const im_graph* g) const {
 void memo_destroy(im_graph* g, Memo* m) {
   auto& v = g->memos;
   v.erase(std::remove(v.begin(), v.end(), m), v.end());
+  // the memory may next be used from another stream: construction must be over
+  // (queries using the memo hold pins, released only after they completed)
+  if (m->ready_ev) (void)hipEventSynchronize(m->ready_ev);
   if (m->ready_ev) (void)hipEventDestroy(m->ready_ev);
   if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
   if (m->join_ev) (void)hipEventDestroy(m->join_ev);
@@ -217,6 +293,10 @@ uint64_t memo_bytes(const im_graph* g, uint32_t R) {
   b += align256((size_t)list_capacity(g->n, ntiles) * kSubLists * 4) * 2;
   b += align256((size_t)kSubLists * 2 * 4);
   return b;
+}
+
+bool memo_matches(const im_graph* g, const Memo* m, double p, uint32_t R, uint32_t seed) {
+  return m->R == R && m->seed == seed && m->tkey == (g->per_edge ? 0 : thr_of(p));
 }
 
 Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
@@ -274,7 +354,9 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->llist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
   m->counts = reinterpret_cast<uint32_t*>(take((size_t)kSubLists * 2 * 4));
   {
+    // returned pinned: nothing may evict it before the caller is done with it
     std::lock_guard<std::recursive_mutex> lk(c->mu);
+    m->pins = 1;
     g->memos.push_back(m);
     m->last_use = ++c->use_clock;
   }
@@ -374,17 +456,22 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
 im_status memo_acquire(im_graph* g, Memo** out) {
   if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
   im_ctx* c = g->ctx;
-  Memo* m = memo_find(g, g->p, g->R, g->seed);
+  Memo* m = nullptr;
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    m = memo_find(g, g->p, g->R, g->seed);
+    if (m) {
+      m->pins++;  // pinned before anything else may evict it
+      m->last_use = ++c->use_clock;
+    }
+  }
   if (!m) {
-    im_status s = memo_build(g, g->p, g->R, g->seed, c->stream, &m);
+    im_status s = memo_build(g, g->p, g->R, g->seed, c->stream, &m);  // returned pinned
     if (s != IM_OK) return s;
   } else {
     g->timed_build = false;
     if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
   }
-  std::lock_guard<std::recursive_mutex> lk(c->mu);
-  m->pins++;
-  m->last_use = ++c->use_clock;
   *out = m;
   return IM_OK;
 }
@@ -584,6 +671,7 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   resolve_pending(c);
   while (!c->graphs.empty()) im_graph_free(c->graphs.back());
+  if (c->arena.base) raw_free(c, c->arena.base);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   if (c->aux) {
     (void)hipStreamSynchronize(c->aux);

@@ -144,12 +144,8 @@ static bool admit(im_server* sv, Slot& s, Ticket* t) {
   }
   im_status st = IM_OK;
   if (!m) {
-    st = memo_build(g, t->p, t->R, t->seed, s.stream, &m);
-    if (st == IM_OK) {
-      std::lock_guard<std::recursive_mutex> lk(c->mu);
-      m->pins++;
-      sv->builds++;
-    }
+    st = memo_build(g, t->p, t->R, t->seed, s.stream, &m);  // returned pinned
+    if (st == IM_OK) sv->builds++;
   } else if (m->ready_ev) {
     (void)hipStreamWaitEvent(s.stream, m->ready_ev, 0);
   }
@@ -205,6 +201,54 @@ static bool admit(im_server* sv, Slot& s, Ticket* t) {
   return true;
 }
 
+// Queued queries wanting the memo (g, m's parameters).  Called during
+// evictions: from the worker, which holds the server lock, or from a direct
+// call on another thread, which takes it.
+static uint32_t memo_demand(void* user, const im_graph* g, const Memo* m) {
+  im_server* sv = static_cast<im_server*>(user);
+  std::unique_lock<std::mutex> lk(sv->mu, std::defer_lock);
+  if (std::this_thread::get_id() != sv->worker.get_id()) lk.lock();
+  uint32_t d = 0;
+  for (const Ticket* t : sv->queue)
+    if (t->g == g && memo_matches(g, m, t->p, t->R, t->seed)) ++d;
+  return d;
+}
+
+// Index of the queued ticket to admit next.  Unless the head has waited
+// longer than kMaxBypassMs: among the next kLookahead tickets, the first
+// whose memo is resident; if none is, the first ticket of the parameter set
+// (graph, p, R, s) that most of them share, so that one construction serves
+// as many queued queries as possible.  Otherwise the head.
+constexpr size_t kLookahead = 256;
+constexpr double kMaxBypassMs = 100.0;
+
+static size_t pick_next(im_server* sv) {
+  Ticket* head = sv->queue.front();
+  const double waited = std::chrono::duration<double, std::milli>(Clock::now() - head->t_submit).count();
+  if (waited > kMaxBypassMs) return 0;
+  std::lock_guard<std::recursive_mutex> lk(sv->ctx->mu);
+  const size_t lim = std::min(kLookahead, sv->queue.size());
+  for (size_t i = 0; i < lim; ++i) {
+    Ticket* t = sv->queue[i];
+    if (!t->cancel && memo_find(t->g, t->p, t->R, t->seed)) return i;
+  }
+  size_t best = 0, best_n = 0;
+  for (size_t i = 0; i < lim; ++i) {
+    const Ticket* t = sv->queue[i];
+    if (t->cancel) continue;
+    size_t same = 0;
+    for (size_t j = i; j < lim; ++j) {
+      const Ticket* u = sv->queue[j];
+      same += (u->g == t->g && u->R == t->R && u->seed == t->seed && u->p == t->p) ? 1 : 0;
+    }
+    if (same > best_n) {
+      best_n = same;
+      best = i;
+    }
+  }
+  return best;
+}
+
 static void worker_main(im_server* sv) {
   (void)hipSetDevice(sv->ctx->device);
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -216,10 +260,10 @@ static void worker_main(im_server* sv) {
         progress = true;
       }
     while (!sv->queue.empty()) {
-      Ticket* t = sv->queue.front();
-      if (t->cancel) {
+      Ticket* h = sv->queue.front();
+      if (h->cancel) {
         sv->queue.pop_front();
-        finish(sv, t, IM_ERR_CANCELLED);
+        finish(sv, h, IM_ERR_CANCELLED);
         progress = true;
         continue;
       }
@@ -230,8 +274,13 @@ static void worker_main(im_server* sv) {
           break;
         }
       if (!free_slot) break;
-      if (!admit(sv, *free_slot, t)) break;  // waits for memory
-      sv->queue.pop_front();
+      const size_t i = pick_next(sv);
+      Ticket* t = sv->queue[i];
+      sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)i);
+      if (!admit(sv, *free_slot, t)) {  // waits for memory
+        sv->queue.insert(sv->queue.begin() + (std::ptrdiff_t)i, t);
+        break;
+      }
       progress = true;
     }
     if (sv->stop && sv->queue.empty() && sv->busy == 0) break;
@@ -263,6 +312,11 @@ extern "C" im_status im_server_create(im_ctx* c, const im_server_config* cfg, im
   }
   // work the context enqueued before (graph uploads) precedes every slot
   (void)hipStreamSynchronize(c->stream);
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->memo_demand = memo_demand;
+    c->memo_demand_user = sv;
+  }
   sv->worker = std::thread(worker_main, sv);
   *out = sv;
   return IM_OK;
@@ -363,6 +417,13 @@ extern "C" void im_server_destroy(im_server* sv) {
     sv->cv_work.notify_one();
   }
   sv->worker.join();
+  {
+    std::lock_guard<std::recursive_mutex> lk(sv->ctx->mu);
+    if (sv->ctx->memo_demand_user == sv) {
+      sv->ctx->memo_demand = nullptr;
+      sv->ctx->memo_demand_user = nullptr;
+    }
+  }
   for (Slot& s : sv->slots) {
     if (s.host) (void)hipHostFree(s.host);
     (void)hipStreamDestroy(s.stream);

@@ -20,4 +20,4 @@ from .graphs import (  # noqa: F401
     path_graph,
     random_small_graph,
 )
-from .configs import CONFIGS, make_config, config_graphs  # noqa: F401
+from .configs import CONFIGS, Query, make_config, config_graphs, serving_trace  # noqa: F401
