@@ -219,6 +219,82 @@ def serve_bench(args):
     print(json.dumps(rec), flush=True)
 
 
+def batch_bench(args):
+    """Batching workload: 64 Chung-Lu graphs (seeds 100..163, n log-uniform in
+    [1,000, 40,000], m uniform in [2n, 10n], per-edge trivalency p), R = 1,024,
+    K = 20 each: one im_batch_select call for all graphs against 64 plain
+    per-graph selections, every memo built from scratch in both."""
+    import numpy as np
+    import torch
+
+    import paper_2008_03095_amd as P
+    from workloads import make_config
+
+    w = make_config("c3")
+    ctx = P.Context(device=0)
+    Gs = [P.Graph.from_csr(ctx, g) for g in w.graphs]
+    for G, s in zip(Gs, w.seeds):
+        G.set_params(0.0, w.R, s)  # p ignored: per-slot probabilities
+    Ks = [w.K] * len(Gs)
+    es = sum(g.m for g in w.graphs) * w.R
+
+    def drop():
+        for G in Gs:
+            G.drop_memo()
+
+    def plain():
+        out = []
+        for G in Gs:
+            out.append(G.select_seeds(w.K))
+        return out
+
+    def batched():
+        return P.batch_select(ctx, Gs, Ks)
+
+    for _ in range(args.warmup):
+        drop(); plain(); drop(); batched()
+    tp, tb = [], []
+    for _ in range(args.steps):
+        drop()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rp = plain()
+        tp.append(time.perf_counter() - t)
+        drop()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rb = batched()
+        tb.append(time.perf_counter() - t)
+        for a, b in zip(rp, rb):
+            if list(a[0]) != list(b[0]) or a[2] != b[2]:
+                raise RuntimeError("batched and plain selections differ")
+    for G in Gs:
+        G.free()
+    ctx.close()
+    t_plain, t_batch = float(np.median(tp)), float(np.median(tb))
+    rec = {
+        "metric": "batched vs plain per-graph K-seed selection (64 graphs)",
+        "value": es / t_batch,
+        "unit": "edge-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "c3: 64 Chung-Lu graphs, gamma 2.5, seeds 100..163, n log-uniform in "
+                               "[1000, 40000], m uniform in [2n, 10n], per-edge trivalency p "
+                               "{0.1, 0.01, 0.001}; R=1024, K=20 each",
+                   "graphs": len(w.graphs), "sum_m": sum(g.m for g in w.graphs), "R": w.R, "K": w.K},
+        "batched_ms": t_batch * 1e3,
+        "plain_ms": t_plain * 1e3,
+        "speedup_vs_plain": t_plain / t_batch,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def calibrate_copy(gib: int = 4, reps: int = 5):
     import torch
 
@@ -237,7 +313,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c5"])
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c3", "c5"])
     ap.add_argument("--queries", type=int, default=300, help="serving workload: queries of the trace")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: concurrent query slots")
     ap.add_argument("--hbm-budget-gib", type=float, default=224.0, help="serving workload: memo budget")
@@ -262,6 +338,9 @@ def main():
         return
     if args.workload == "c5":
         serve_bench(args)
+        return
+    if args.workload == "c3":
+        batch_bench(args)
         return
 
     import numpy as np

@@ -33,6 +33,8 @@
 // tlist: the tile may hold a non-singleton column) and whether some column
 // has two or more live smaller neighbours (work list llist: the tile needs
 // k_link); the later kernels visit only those tiles.
+#include <algorithm>
+
 #include "common.h"
 
 namespace infuse {
@@ -250,7 +252,8 @@ __global__ void __launch_bounds__(256) k_hook_hubs(GraphView g, MemoView m, uint
 // k_lists: sub-list j lists, in vertex order, the tiles of the vertices
 // [j * vps, (j + 1) * vps) whose tmask (tlist) or lmask (llist) bit is set.
 // One workgroup per sub-list; positions come from workgroup prefix sums, so
-// no global counter is contended.
+// no global counter is contended.  It also sets mg_v = R, the gain of an all
+// singleton row, to which k_gain0 adds the listed tiles.
 __global__ void __launch_bounds__(256) k_lists(MemoView m) {
   __shared__ uint32_t wsum[2][4];
   const uint32_t j = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -262,6 +265,7 @@ __global__ void __launch_bounds__(256) k_lists(MemoView m) {
   for (uint32_t vb = v0; vb < v1; vb += 256) {
     const uint32_t v = vb + threadIdx.x;
     uint32_t tc = 0, lc = 0;
+    if (v < v1) m.g0[v] = (int64_t)m.R;
     if (v < v1)
       for (uint32_t w = 0; w < m.mwords; ++w) {
         tc += __popc(m.tmask[(uint64_t)v * m.mwords + w]);
@@ -540,13 +544,21 @@ __global__ void __launch_bounds__(256) k_flatten(MemoView m) {
 // (in power-law graphs the giant one) are rooted at small ids and their
 // members would otherwise all hit the same words.
 constexpr uint32_t kHotRoots = 64;
-constexpr uint32_t kCountBlockVerts = 4096;
+constexpr uint32_t kCountMaxBlockVerts = 4096;
 
-__global__ void __launch_bounds__(256) k_count(MemoView m) {
+// Vertices per workgroup of k_count: enough workgroups to fill the device
+// (about 2048), multiples of 256, at most kCountMaxBlockVerts.
+static uint32_t count_block_verts(const MemoView& m) {
+  const uint64_t want = ((uint64_t)m.n * m.ntiles + 2047) / 2048;
+  const uint64_t vb = (want + 255) / 256 * 256;
+  return (uint32_t)std::min<uint64_t>(kCountMaxBlockVerts, std::max<uint64_t>(256, vb));
+}
+
+__global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts) {
   __shared__ uint32_t hot[kHotRoots][kTile];
   const uint32_t t = blockIdx.x % m.ntiles;
-  const uint32_t v0 = (blockIdx.x / m.ntiles) * kCountBlockVerts;
-  const uint32_t v1 = min(v0 + kCountBlockVerts, m.n);
+  const uint32_t v0 = (blockIdx.x / m.ntiles) * block_verts;
+  const uint32_t v1 = min(v0 + block_verts, m.n);
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < kHotRoots * kTile; i += blockDim.x) (&hot[0][0])[i] = 0;
   __syncthreads();
@@ -587,10 +599,6 @@ __device__ inline uint64_t wave_sum_u64(uint64_t x) {
 
 // mg_v = sum_q |C_q(v)| = R + sum over the listed tiles of v of
 // sum_q (|C_q(v)| - 1): unlisted tiles hold only singleton columns.
-__global__ void k_gain0_init(MemoView m) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < m.n) m.g0[v] = (int64_t)m.R;
-}
 
 __global__ void __launch_bounds__(256) k_gain0(MemoView m) {
   const uint32_t lane = threadIdx.x & 63;
@@ -684,12 +692,12 @@ void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {
 }
 
 void launch_count(const MemoView& m, hipStream_t st) {
-  const uint32_t vblocks = (m.n + kCountBlockVerts - 1) / kCountBlockVerts;
-  hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m);
+  const uint32_t bv = count_block_verts(m);
+  const uint32_t vblocks = (m.n + bv - 1) / bv;
+  hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m, bv);
 }
 
 void launch_gain0(const MemoView& m, hipStream_t st) {
-  hipLaunchKernelGGL(k_gain0_init, dim3((m.n + 255) / 256), dim3(256), 0, st, m);
   hipLaunchKernelGGL(k_gain0, dim3(kListBlocks), dim3(256), 0, st, m);
 }
 

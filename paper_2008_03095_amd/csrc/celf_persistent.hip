@@ -65,11 +65,19 @@ struct PCelfScratch {
   uint64_t pool_key[kPool];
 };
 
-struct PCelfArgs {
+// One selection: the graph's CELF state, its scratch and bulk list.
+struct PCelfJob {
   CelfView c;
   PCelfScratch* x;
   uint32_t* blist;   // [n] bulk candidates
   uint32_t w0;       // candidates of the first round of a step
+};
+
+// The workgroups that run one selection together: their number and this
+// workgroup's index among them.  Barriers and every grid-stride loop are
+// over the group.
+struct Grp {
+  uint32_t nb, bi;
 };
 
 __device__ inline uint32_t p_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -172,7 +180,7 @@ __device__ uint64_t block_max(PoolLds& L, uint64_t v) {
 // Grid barrier: every wave waits for its own memory operations, then one
 // thread per workgroup arrives at its group's counter; the last of a group
 // arrives at the top counter, and the last of all releases every group.
-__device__ bool grid_sync(PCelfScratch* x, uint32_t& gen, PClock& clk, int phase) {
+__device__ bool grid_sync(PCelfScratch* x, const Grp& G, uint32_t& gen, PClock& clk, int phase) {
   __shared__ uint32_t ok_sh;
   clk.lap(phase);
   ++clk.barriers;
@@ -180,9 +188,9 @@ __device__ bool grid_sync(PCelfScratch* x, uint32_t& gen, PClock& clk, int phase
   __syncthreads();
   ++gen;
   if (threadIdx.x == 0) {
-    const uint32_t g = blockIdx.x % kGroups;
-    const uint32_t ng = min(kGroups, gridDim.x);
-    const uint32_t members = (gridDim.x - g + kGroups - 1) / kGroups;
+    const uint32_t g = G.bi % kGroups;
+    const uint32_t ng = min(kGroups, G.nb);
+    const uint32_t members = (G.nb - g + kGroups - 1) / kGroups;
     uint32_t ok = 1;
     if (atomicAdd(&x->arrive[g][0], 1u) + 1 == gen * members)
       if (atomicAdd(&x->top[0], 1u) + 1 == gen * ng)
@@ -389,13 +397,14 @@ __device__ void pool_restale(PoolLds& L) {
 }
 
 // Rebuilds the pool from the keys of all unselected vertices.
-__device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_t& gen, PClock& clk) {
+__device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t s, uint32_t& gen,
+                             PClock& clk) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
   const uint32_t n = c.m.n;
-  const uint32_t gtid = blockIdx.x * kPBlock + threadIdx.x, gstride = gridDim.x * kPBlock;
-  if (!grid_sync(x, gen, clk, PClock::kPoolOps)) return false;  // readers of the last staging are done
-  if (blockIdx.x == 0) {
+  const uint32_t gtid = G.bi * kPBlock + threadIdx.x, gstride = G.nb * kPBlock;
+  if (!grid_sync(x, G, gen, clk, PClock::kPoolOps)) return false;  // readers of the last staging are done
+  if (G.bi == 0) {
     for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
     if (threadIdx.x == 0) {
       st32(&x->pool_cnt, 0u);
@@ -403,7 +412,7 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
       st64(&x->kmax, 0ull);
     }
   }
-  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   // largest key
   uint64_t mx = 0;
   for (uint32_t v = gtid; v < n; v += gstride) {
@@ -412,7 +421,7 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
   }
   mx = p_wmax(mx);
   if ((threadIdx.x & 63) == 0 && mx) atomicMax((unsigned long long*)&x->kmax, (unsigned long long)mx);
-  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint64_t kmax = ld64(&x->kmax);
   if (kmax == 0) {  // nothing unselected: the caller reports it
     if (threadIdx.x == 0) {
@@ -450,7 +459,7 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock)
       if (L.hist[i]) atomicAdd(&x->hist[i], L.hist[i]);
-    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+    if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
     // bins from the top: thread t holds bins kBins-1-(kBPer*t .. kBPer*t+kBPer-1)
     constexpr uint32_t kBPer = kBins / kPBlock;
     uint32_t h[kBPer], mine = 0;
@@ -495,10 +504,10 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
       return false;
     }
     // clear the global histogram for the next digit once every reader is done
-    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
-    if (blockIdx.x == 0)
+    if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
+    if (G.bi == 0)
       for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
-    if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+    if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   }
   // collect the keys at or above the threshold
   uint64_t outside = 0;
@@ -518,7 +527,7 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
   outside = p_wmax(outside);
   if ((threadIdx.x & 63) == 0 && outside)
     atomicMax((unsigned long long*)&x->out_bound, (unsigned long long)outside);
-  if (!grid_sync(x, gen, clk, PClock::kRebuild)) return false;
+  if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint32_t cnt = ld32(&x->pool_cnt);
   if (cnt > kPool) {  // the threshold admits at most kPool keys
     if (threadIdx.x == 0) atomicOr(&x->err, 2u);
@@ -576,18 +585,18 @@ __device__ bool pool_rebuild(const PCelfArgs& a, PoolLds& L, uint32_t s, uint32_
 }
 
 // Bulk evaluation of every stale vertex whose key exceeds kstar.
-__device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32_t& gen,
+__device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t kstar, uint32_t& gen,
                           PClock& clk, uint64_t& evals) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
   const uint32_t n = c.m.n, ntiles = c.m.ntiles;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t gtid = blockIdx.x * kPBlock + threadIdx.x, gstride = gridDim.x * kPBlock;
-  const uint32_t nw = gridDim.x * (kPBlock / 64);
-  const uint32_t gw = blockIdx.x * (kPBlock / 64) + (threadIdx.x >> 6);
+  const uint32_t gtid = G.bi * kPBlock + threadIdx.x, gstride = G.nb * kPBlock;
+  const uint32_t nw = G.nb * (kPBlock / 64);
+  const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   // the last commit's key store and the counter reset must be visible
-  if (blockIdx.x == 0 && threadIdx.x == 0) st32(&x->bulk_cnt, 0u);
-  if (!grid_sync(x, gen, clk, PClock::kPoolOps)) return false;
+  if (G.bi == 0 && threadIdx.x == 0) st32(&x->bulk_cnt, 0u);
+  if (!grid_sync(x, G, gen, clk, PClock::kPoolOps)) return false;
   // 1. list the candidates (wave-aggregated slots)
   for (uint32_t base = gtid - lane; base < n; base += gstride) {
     const uint32_t v = base + lane;
@@ -606,7 +615,7 @@ __device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32
       st32(&a.blist[at], v);
     }
   }
-  if (!grid_sync(x, gen, clk, PClock::kBulk)) return false;
+  if (!grid_sync(x, G, gen, clk, PClock::kBulk)) return false;
   const uint32_t cnt = ld32(&x->bulk_cnt);
   // 2. one wavefront per candidate: the gain over all tiles, four at a time;
   // the keys are read by the rebuild that follows, after its barrier
@@ -627,20 +636,19 @@ __device__ bool bulk_eval(const PCelfArgs& a, uint32_t s, uint64_t kstar, uint32
   return true;
 }
 
-__global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
-  __shared__ PoolLds L;
+__device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nw = gridDim.x * (kPBlock / 64);
-  const uint32_t gw = blockIdx.x * (kPBlock / 64) + (threadIdx.x >> 6);
+  const uint32_t nw = G.nb * (kPBlock / 64);
+  const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   const uint32_t ntiles = c.m.ntiles;
   uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, step_rebuilds = 0;
   uint64_t evals = 0;
   PClock clk;
   clk.start();
   const uint64_t t_start = clk.mark;
-  if (!pool_rebuild(a, L, s, gen, clk)) return;
+  if (!pool_rebuild(a, G, L, s, gen, clk)) return;
   bool just_rebuilt = true;
   while (s < c.K) {
     if (__builtin_amdgcn_s_memrealtime() - t_start > kRunTicks) {
@@ -654,14 +662,14 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
     if (nf && fbest > stop && fbest > ob) {
       // ---- commit the exact maximiser; each workgroup marks a slice of columns
       const uint32_t id = L.fid[L.fbest];
-      const uint32_t per = (c.m.R + gridDim.x - 1) / gridDim.x;
-      const uint32_t q_lo = min(blockIdx.x * per, c.m.R), q_hi = min(q_lo + per, c.m.R);
+      const uint32_t per = (c.m.R + G.nb - 1) / G.nb;
+      const uint32_t q_lo = min(G.bi * per, c.m.R), q_hi = min(q_lo + per, c.m.R);
       for (uint32_t q = q_lo + threadIdx.x; q < q_hi; q += kPBlock) {
         const int32_t val = c.m.M[(uint64_t)id * c.m.Rs + q];
         const uint32_t root = val < 0 ? id : (uint32_t)val;
         atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
       }
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (G.bi == 0 && threadIdx.x == 0) {
         c.seeds[s] = id;
         c.marginal[s] = (int64_t)(fbest >> c.B);
         st64(&c.key[id], 0ull);
@@ -690,7 +698,7 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
       if (fbest) nc = min(nc, count_greater(L.skey + head, nc, fbest));
       nc = min(nc, kPool - nf);
       uint64_t* g = x->gains[ev_round % 3];
-      if (blockIdx.x == 0) {
+      if (G.bi == 0) {
         uint64_t* nxt = x->gains[(ev_round + 1) % 3];
         for (uint32_t i = threadIdx.x; i < kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
       }
@@ -701,14 +709,14 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
         const uint64_t part = p_wsum(p_eval_tile(c, L.sid[head + w], t, lane, last));
         if (lane == 0 && part) atomicAdd((unsigned long long*)&g[w], (unsigned long long)part);
       }
-      if (!grid_sync(x, gen, clk, PClock::kEval)) return;
+      if (!grid_sync(x, G, gen, clk, PClock::kEval)) return;
       // move the evaluated entries from S to F
       for (uint32_t w = threadIdx.x; w < nc; w += kPBlock) {
         const uint32_t v = L.sid[head + w];
         const uint64_t k = p_make_key(c, ld64(&g[w]), v);
         L.fkey[nf + w] = k;
         L.fid[nf + w] = v;
-        if (blockIdx.x == 0) {
+        if (G.bi == 0) {
           st64(&c.key[v], k);
           st32(&c.iter[v], s);
         }
@@ -732,20 +740,20 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
     // pool; when that already happened in this step, first evaluate every
     // stale vertex above max F at once (a lower bound of this step's gain).
     if (just_rebuilt) {  // a fresh pool always decides
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      if (G.bi == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
       return;
     }
     if (nf && step_rebuilds > 0)
-      if (!bulk_eval(a, s, fbest, gen, clk, evals)) return;
-    if (!pool_rebuild(a, L, s, gen, clk)) return;
+      if (!bulk_eval(a, G, s, fbest, gen, clk, evals)) return;
+    if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     ++step_rebuilds;
     if (L.ns == 0 && L.nf == 0) {  // no unselected vertex: cannot happen for K <= n
-      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      if (G.bi == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
       return;
     }
     just_rebuilt = true;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (G.bi == 0 && threadIdx.x == 0) {
     c.st->s = s;
     c.st->evals = evals;
     c.st->bulk_rounds = ev_round;
@@ -753,6 +761,46 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(PCelfArgs a) {
     x->prof[5] = clk.barriers;
     x->prof[6] = clk.rounds;
     x->prof[7] = ((uint64_t)clk.bulks << 32) | clk.rebuilds;
+  }
+}
+
+// Many selections in one launch, each with its own scratch.  With `first`
+// (prefix sums of workgroups per selection, njobs + 1 entries, every
+// selection at least one workgroup), selection j runs on workgroups
+// first[j] .. first[j+1]-1.  Otherwise the grid is split into groups of
+// group_blocks workgroups (trailing workgroups that make no whole group
+// return at once) and group g runs the selections g, g + groups, ... one
+// after the other.
+__global__ void __launch_bounds__(kPBlock) k_celf_persistent(const PCelfJob* __restrict__ jobs, uint32_t njobs,
+                                                            uint32_t group_blocks,
+                                                            const uint32_t* __restrict__ first) {
+  __shared__ PoolLds L;
+  uint32_t j0, step;
+  Grp G;
+  if (first) {
+    if (blockIdx.x >= first[njobs]) return;
+    uint32_t lo = 0, hi = njobs;  // last j with first[j] <= blockIdx.x
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (first[mid] <= blockIdx.x)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    G = Grp{first[lo + 1] - first[lo], blockIdx.x - first[lo]};
+    j0 = lo;
+    step = njobs;  // this selection only
+  } else {
+    const uint32_t groups = gridDim.x / group_blocks;
+    j0 = blockIdx.x / group_blocks;
+    if (j0 >= groups) return;
+    G = Grp{group_blocks, blockIdx.x % group_blocks};
+    step = groups;
+  }
+  // one call site, the description read in place (its fields stay scalar)
+  for (uint32_t j = j0; j < njobs; j += step) {
+    run_celf(jobs[j], G, L);
+    __syncthreads();
   }
 }
 
@@ -774,16 +822,29 @@ uint32_t pcelf_grid(int device) {
   return (uint32_t)cus * (uint32_t)std::min(per, 2);
 }
 
-hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint32_t grid,
-                                  uint32_t round0, hipStream_t st) {
-  PCelfArgs a;
-  a.c = c;
-  a.x = static_cast<PCelfScratch*>(scratch);
-  a.blist = blist;
-  const uint32_t waves = grid * (kPBlock / 64);
-  // default: 16 candidates, or fewer when 16 would exceed one tile per wavefront
-  a.w0 = round0 ? std::min(kMaxCand, round0) : std::max(1u, std::min(16u, (waves + c.m.ntiles - 1) / c.m.ntiles));
-  void* args[] = {&a};
+static_assert(sizeof(PCelfJob) <= 512, "the host keeps one description in 512 bytes");
+uint64_t pcelf_job_bytes() { return sizeof(PCelfJob); }
+
+// Candidates of a step's first round: `round0` if set, else 16, or fewer
+// when 16 would exceed one tile per wavefront of the group.
+static uint32_t pcelf_w0(const CelfView& c, uint32_t group_blocks, uint32_t round0) {
+  const uint32_t waves = group_blocks * (kPBlock / 64);
+  return round0 ? std::min(kMaxCand, round0) : std::max(1u, std::min(16u, (waves + c.m.ntiles - 1) / c.m.ntiles));
+}
+
+void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* blist, uint32_t group_blocks,
+                    uint32_t round0) {
+  PCelfJob* j = static_cast<PCelfJob*>(host_job);
+  j->c = c;
+  j->x = static_cast<PCelfScratch*>(scratch);
+  j->blist = blist;
+  j->w0 = pcelf_w0(c, group_blocks, round0);
+}
+
+hipError_t launch_celf_persistent(const void* jobs, uint32_t njobs, uint32_t grid, uint32_t group_blocks,
+                                  const uint32_t* first, hipStream_t st) {
+  const PCelfJob* j = static_cast<const PCelfJob*>(jobs);
+  void* args[] = {&j, &njobs, &group_blocks, &first};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_celf_persistent), dim3(grid), dim3(kPBlock),
                                     args, 0, st);
 }

@@ -35,8 +35,16 @@ uint64_t pcelf_scratch_bytes();
 uint64_t pcelf_err_offset();   // u32 error flag of the persistent kernel
 uint64_t pcelf_prof_offset();  // 8 x u64: phase ticks (100 MHz) x5, barriers, rounds, rebuilds
 uint32_t pcelf_grid(int device);
-hipError_t launch_celf_persistent(const CelfView& c, void* scratch, uint32_t* blist, uint32_t grid,
-                                  uint32_t round0, hipStream_t st);
+uint64_t pcelf_job_bytes();
+// Writes the description of one selection (for a group of group_blocks
+// workgroups) into host memory of pcelf_job_bytes() bytes.
+void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* blist, uint32_t group_blocks,
+                    uint32_t round0);
+// jobs: device array of njobs descriptions.  first: device prefix sums of
+// workgroups per description (njobs + 1 entries, each at least one), or
+// nullptr for grid / group_blocks equal groups taking descriptions in turn.
+hipError_t launch_celf_persistent(const void* jobs, uint32_t njobs, uint32_t grid, uint32_t group_blocks,
+                                  const uint32_t* first, hipStream_t st);
 
 // query.hip
 uint32_t sigma_pair_max();

@@ -55,6 +55,8 @@ struct CelfBuffers {
   size_t bytes = 0;
   CelfView v;
   void* pscratch = nullptr;  // state of the persistent kernel
+  void* pjob = nullptr;      // its description of this selection (device copy of hjob)
+  alignas(16) unsigned char hjob[512];
   uint32_t* blist = nullptr;  // [n] persistent kernel: bulk candidates
   bool persistent = false;   // enqueued as one persistent kernel
 };
@@ -73,6 +75,10 @@ im_status check_params(const im_graph* g, double p, uint32_t R);
 uint32_t key_bits(uint32_t n);
 im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuffers* cb);
 void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st);
+void celf_prepare(CelfBuffers* cb, hipStream_t st);
+bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_t group_blocks,
+                            const uint32_t* first, hipStream_t st);
+void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st);
 im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
                        int64_t* marginal, int64_t* cover, uint64_t* evals);
 im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out);
@@ -113,6 +119,8 @@ struct im_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t aux = nullptr;  // side stream for work that overlaps the main stream's
+  std::vector<hipStream_t> bstreams;  // memo construction of batched graphs (created on first use)
+  std::vector<hipEvent_t> bevents;
   im_allocator alloc = {nullptr, nullptr, nullptr};
   bool has_alloc = false;
   uint64_t budget = 0;

@@ -346,6 +346,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->pos = reinterpret_cast<uint32_t*>(take((size_t)R * 4));
   m->scratch = reinterpret_cast<uint64_t*>(take((size_t)x_sort_scratch_elems(R) * 8));
   m->M = reinterpret_cast<int32_t*>(take((size_t)g->n * m->Rs * 4));
+  // the two mask arrays are adjacent (one fill clears both)
   m->tmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
   m->lmask = reinterpret_cast<uint32_t*>(take((size_t)g->n * m->mwords * 4));
   m->g0 = reinterpret_cast<int64_t*>(take((size_t)g->n * 8));
@@ -373,13 +374,15 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     KTimer t(c, "x_sort", st);
     launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
   }
-  launch_fill_u32(m->tmask, (uint64_t)g->n * m->mwords, 0u, st);
-  launch_fill_u32(m->lmask, (uint64_t)g->n * m->mwords, 0u, st);
-  launch_fill_u32(m->counts, kSubLists * 2, 0u, st);
+  // hub vertices' mask words are or-ed into; k_lists writes every count
+  launch_fill_u32(m->tmask, (uint64_t)(reinterpret_cast<char*>(m->lmask) - reinterpret_cast<char*>(m->tmask)) / 4 +
+                                (uint64_t)g->n * m->mwords, 0u, st);
   if (timed) (void)hipEventRecord(g->ev[1], st);
   // hub rows (few, long, latency-bound wavefronts) run on the side stream
   // next to the bandwidth-bound light rows; the two write disjoint rows
-  const bool fork = g->nhubs && c->aux && m->fork_ev && m->join_ev;
+  // (only for the context stream: other streams, such as the batch streams,
+  // already run several constructions side by side)
+  const bool fork = g->nhubs && c->aux && m->fork_ev && m->join_ev && st == c->stream;
   if (fork) {
     (void)hipEventRecord(m->fork_ev, st);
     (void)hipStreamWaitEvent(c->aux, m->fork_ev, 0);
@@ -406,7 +409,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   // unions of hub vertices, one wavefront per (hub, tile, 64 smaller
   // neighbours), on the side stream next to the light vertices' unions (both
   // write the memo only by atomics)
-  const bool fork2 = g->hub_pieces && c->aux && m->fork_ev && m->join_ev;
+  const bool fork2 = g->hub_pieces && c->aux && m->fork_ev && m->join_ev && st == c->stream;
   if (fork2) {
     (void)hipEventRecord(m->fork_ev, st);
     (void)hipStreamWaitEvent(c->aux, m->fork_ev, 0);
@@ -506,7 +509,7 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   b += align256((size_t)W * 4) + align256((size_t)W * 8);
   b += align256((size_t)std::max(K, 1u) * 4) + align256((size_t)std::max(K, 1u) * 8);
   b += align256(sizeof(CelfState));
-  b += align256(pcelf_scratch_bytes());
+  b += align256(pcelf_scratch_bytes()) + align256(pcelf_job_bytes());
   b += align256((size_t)n * 4);
   void* base = nullptr;
   im_status s = ctx_alloc(c, b, &base);
@@ -535,35 +538,60 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
   v.marginal = reinterpret_cast<int64_t*>(take((size_t)std::max(K, 1u) * 8));
   v.st = reinterpret_cast<CelfState*>(take(sizeof(CelfState)));
   cb->pscratch = take(pcelf_scratch_bytes());
+  cb->pjob = take(pcelf_job_bytes());
   cb->blist = reinterpret_cast<uint32_t*>(take((size_t)n * 4));
   cb->persistent = false;
   return IM_OK;
 }
 
-void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+// Clears the coverage bitmap and the state of a selection.
+void celf_prepare(CelfBuffers* cb, hipStream_t st) {
   const CelfView& v = cb->v;
   launch_fill_u32(v.cov, (uint64_t)v.m.n * v.cwords, 0u, st);
   launch_celf_init(v, st);
+  launch_fill_u32(static_cast<uint32_t*>(cb->pscratch), pcelf_scratch_bytes() / 4, 0u, st);
+}
+
+// One persistent launch over `njobs` selections (device descriptions).
+// Returns false when the device cannot run it.
+bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_t group_blocks,
+                            const uint32_t* first, hipStream_t st) {
+  // one persistent kernel at a time per context: two partly resident
+  // cooperative grids could each wait for the other's workgroups
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  if (c->coop_pending && c->coop_stream != st) (void)hipStreamWaitEvent(st, c->coop_done, 0);
+  hipError_t e;
+  {
+    KTimer t(c, "celf", st, 1);
+    e = launch_celf_persistent(jobs, njobs, c->coop_grid, group_blocks, first, st);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  (void)hipEventRecord(c->coop_done, st);
+  c->coop_pending = true;
+  c->coop_stream = st;
+  return true;
+}
+
+void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+  celf_prepare(cb, st);
   if (c->tune.celf_mode == 1 && c->coop_grid) {
-    launch_fill_u32(static_cast<uint32_t*>(cb->pscratch), pcelf_scratch_bytes() / 4, 0u, st);
-    // one persistent kernel at a time per context: two partly resident
-    // cooperative grids could each wait for the other's workgroups
-    std::lock_guard<std::recursive_mutex> lk(c->mu);
-    if (c->coop_pending && c->coop_stream != st) (void)hipStreamWaitEvent(st, c->coop_done, 0);
-    hipError_t e;
-    {
-      KTimer t(c, "celf", st, 1);
-      e = launch_celf_persistent(v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0, st);
-    }
-    if (e == hipSuccess) {
-      (void)hipEventRecord(c->coop_done, st);
-      c->coop_pending = true;
-      c->coop_stream = st;
+    pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0);
+    if (hipMemcpyAsync(cb->pjob, cb->hjob, pcelf_job_bytes(), hipMemcpyHostToDevice, st) == hipSuccess &&
+        celf_launch_persistent(c, cb->pjob, 1, c->coop_grid, nullptr, st)) {
       cb->persistent = true;
       return;
     }
     (void)hipGetLastError();  // not launchable here: run the per-step kernels
   }
+  celf_enqueue_steps(c, cb, st);
+}
+
+// The per-step kernels (three launches per greedy step).
+void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+  const CelfView& v = cb->v;
   const uint32_t bulk_blocks = std::max(1u, std::min(2048u, v.m.n));
   for (uint32_t k = 0; k < v.K; ++k) {
     {
@@ -672,6 +700,11 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   resolve_pending(c);
   while (!c->graphs.empty()) im_graph_free(c->graphs.back());
   if (c->arena.base) raw_free(c, c->arena.base);
+  for (hipStream_t b : c->bstreams) {
+    (void)hipStreamSynchronize(b);
+    (void)hipStreamDestroy(b);
+  }
+  for (hipEvent_t e : c->bevents) (void)hipEventDestroy(e);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   if (c->aux) {
     (void)hipStreamSynchronize(c->aux);

@@ -27,18 +27,22 @@ __global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, u
 
 constexpr int kSortChunk = 4096;  // elements sorted per block in LDS
 
-// Sorts chunk blockIdx.x of the (X_r, r) pairs; pads with all-ones keys.
+// Sorts chunk blockIdx.x of the (X_r, r) pairs; pads with all-ones keys.  A
+// single chunk sorts only the next power of two above R.
 __global__ void __launch_bounds__(1024) k_x_sort_chunk(uint32_t seed, uint32_t R, uint64_t* out) {
   __shared__ uint64_t a[kSortChunk];
   const uint32_t base = blockIdx.x * kSortChunk;
-  for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+  uint32_t len = kSortChunk;
+  if (gridDim.x == 1)
+    while (len > 2 && len / 2 >= R) len /= 2;
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
     const uint32_t r = base + i;
     a[i] = r < R ? ((uint64_t)fmix32(seed + r) << 32) | r : ~0ull;
   }
   __syncthreads();
-  for (uint32_t k = 2; k <= (uint32_t)kSortChunk; k <<= 1) {
+  for (uint32_t k = 2; k <= len; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
         const uint32_t ixj = i ^ j;
         if (ixj > i) {
           const bool asc = (i & k) == 0;
@@ -52,7 +56,47 @@ __global__ void __launch_bounds__(1024) k_x_sort_chunk(uint32_t seed, uint32_t R
       __syncthreads();
     }
   }
-  for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) out[base + i] = a[i];
+  for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) out[base + i] = i < len ? a[i] : ~0ull;
+}
+
+// R <= kSortChunk: one workgroup sorts and writes the column order and the
+// padding columns directly.
+__global__ void __launch_bounds__(1024) k_x_sort_single(uint32_t seed, uint32_t R, uint32_t Rs, uint32_t* xs,
+                                                        uint32_t* inv, uint32_t* pos) {
+  __shared__ uint64_t a[kSortChunk];
+  uint32_t len = kSortChunk;
+  while (len > 2 && len / 2 >= R) len /= 2;
+  for (uint32_t i = threadIdx.x; i < len; i += blockDim.x)
+    a[i] = i < R ? ((uint64_t)fmix32(seed + i) << 32) | i : ~0ull;
+  __syncthreads();
+  for (uint32_t k = 2; k <= len; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const bool asc = (i & k) == 0;
+          const uint64_t x = a[i], y = a[ixj];
+          if ((x > y) == asc) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t q = threadIdx.x; q < Rs; q += blockDim.x) {
+    if (q < R) {
+      const uint64_t key = a[q];
+      const uint32_t r = (uint32_t)key;
+      xs[q] = (uint32_t)(key >> 32);
+      inv[q] = r;
+      pos[r] = q;
+    } else {
+      xs[q] = kInvalid;
+      inv[q] = kInvalid;
+    }
+  }
 }
 
 // Global rank of each element = its rank in its own sorted chunk plus the
@@ -105,6 +149,10 @@ uint32_t x_sort_scratch_elems(uint32_t R) {
 void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, uint32_t* xs,
                    uint32_t* inv, uint32_t* pos, hipStream_t st) {
   const uint32_t nchunks = (R + kSortChunk - 1) / kSortChunk;
+  if (nchunks == 1) {
+    hipLaunchKernelGGL(k_x_sort_single, dim3(1), dim3(1024), 0, st, seed, R, Rs, xs, inv, pos);
+    return;
+  }
   hipLaunchKernelGGL(k_x_sort_chunk, dim3(nchunks), dim3(1024), 0, st, seed, R, scratch);
   const uint32_t padded = nchunks * kSortChunk;
   hipLaunchKernelGGL(k_x_sort_merge, dim3((padded + 255) / 256), dim3(256), 0, st, scratch, R,

@@ -267,3 +267,39 @@ def test_celf_modes(gpu_ctx, case, variant):
     finally:
         gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
         G.free()
+
+
+@pytest.mark.parametrize("variant", ["persistent", "per_step"])
+def test_batch_select_mixed(gpu_ctx, variant):
+    # graphs of different sizes and parameters in one call; K = 0, K = n and
+    # more graphs than one workgroup each would get with equal groups
+    mode, round0 = CELF_VARIANTS[variant]
+    specs = [
+        (chung_lu(400, 1600, 2.5, 41), 0.05, 256, 41, 0),
+        (chung_lu(900, 3000, 2.3, 42), 0.02, 512, 42, 12),
+        (star_graph(150), 0.3, 300, 43, 150),
+        (path_graph(700), 0.9, 256, 44, 25),
+        (chung_lu(2500, 9000, 2.5, 45), 0.03, 1024, 45, 40),
+    ] + [(chung_lu(200 + 37 * i, 800 + 90 * i, 2.5, 60 + i), 0.05, 256, 60 + i, 3 + i % 7) for i in range(40)]
+    announce(f"batch_select {variant} {len(specs)} graphs")
+    old = gpu_ctx.tuning()
+    Gs = []
+    try:
+        gpu_ctx.set_tuning(celf_mode=mode, celf_round0=round0)
+        for g, p, R, s, K in specs:
+            G = P.Graph.from_csr(gpu_ctx, g)
+            G.set_params(p, R, s)
+            Gs.append(G)
+        res = P.batch_select(gpu_ctx, Gs, [K for *_, K in specs])
+        for (g, p, R, s, K), (seeds, marg, cover) in zip(specs, res):
+            if K == 0:
+                assert len(seeds) == 0 and cover == 0
+                continue
+            ref = oracle.run_memo(g, oracle.Sampler("hash", p=p, R=R, seed=s), K, threads=4)
+            assert list(seeds) == list(ref["seeds"]), (g.n, K)
+            assert list(marg) == list(ref["marginal"])
+            assert cover == ref["cover"]
+    finally:
+        gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
+        for G in Gs:
+            G.free()
