@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-samples/s (m·R/s), K-seed time; serving p50/p99 vs plain per-query launch"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hook_c4_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hook_rows_c4_traffic.txt")
 HOOK_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("cc.hip", "common.h")]
 
 WORKLOADS = {
