@@ -320,6 +320,9 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--weights", default="const", choices=["const", "uniform", "normal"],
+                    help="edge probabilities: the workload's constant p, or per edge U[0,0.1] or "
+                         "N(0.05,0.025) clipped (the paper's other weight settings)")
     ap.add_argument("--cc-chunk", type=int, default=0, help="columns per wavefront in labelling")
     ap.add_argument("--celf-width", type=int, default=0, help="CELF candidates per round (per-step mode)")
     ap.add_argument("--celf-mode", type=int, default=0, help="1 persistent kernel, 2 per-step kernels")
@@ -352,6 +355,10 @@ def main():
     w = make_config(args.workload)
     g = w.graphs[0]
     p, R, K, seed = w.p, w.R, w.K, w.seeds[0]
+    if args.weights != "const":
+        from workloads import normal_p, uniform_p
+
+        g.p_slot = uniform_p(g, seed) if args.weights == "uniform" else normal_p(g, seed)
 
     ctx = P.Context(device=0)
     ctx.set_tuning(cc_chunk=args.cc_chunk, celf_width=args.celf_width, celf_mode=args.celf_mode,
@@ -416,7 +423,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n": g.n, "m": g.m,
-                   "R": R, "K": K, "p": p, "hash_seed": seed, "tuning": ctx.tuning()},
+                   "R": R, "K": K, "p": p if args.weights == "const" else args.weights,
+                   "hash_seed": seed, "tuning": ctx.tuning()},
         "k_seed_ms": ms_per_step,
         "phase_ms": {"sampler_prep": phases[0], "components": phases[1], "gains0": phases[2],
                      "celf": phases[3]},

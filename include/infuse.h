@@ -161,7 +161,9 @@ uint64_t im_graph_nnz(const im_graph *g);
  *               2^k, at most 8192; default 256); lighter vertices take
  *               their whole row in one wavefront
  *   celf_width  per-step mode: candidates re-evaluated together per round
- *   use_graphs  1 = replay CELF rounds from a captured hipGraph
+ *   use_graphs  per-step mode: 1 = the K steps' launches are captured into
+ *               one hipGraph (kernel nodes only) and launched once, 2 = direct
+ *               launches (default)
  *   celf_mode   1 = all greedy steps in one persistent cooperative kernel
  *               (default where the device supports cooperative launch),
  *               2 = one launch per step and phase

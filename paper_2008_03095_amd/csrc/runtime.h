@@ -120,6 +120,13 @@ struct im_ctx {
   bool own_stream = false;
   hipStream_t aux = nullptr;  // side stream for work that overlaps the main stream's
   std::vector<hipStream_t> bstreams;  // memo construction of batched graphs (created on first use)
+  // launched CELF graphs, destroyed once their completion event has fired
+  struct GraphRun {
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    hipEvent_t done;
+  };
+  std::vector<GraphRun> graph_runs;
   std::vector<hipEvent_t> bevents;
   im_allocator alloc = {nullptr, nullptr, nullptr};
   bool has_alloc = false;

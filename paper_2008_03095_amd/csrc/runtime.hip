@@ -589,8 +589,58 @@ void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   celf_enqueue_steps(c, cb, st);
 }
 
-// The per-step kernels (three launches per greedy step).
+// The per-step kernels (three launches per greedy step).  With use_graphs
+// the K steps are captured into one graph (kernel nodes only) and launched
+// once.
+static void celf_steps_direct(im_ctx* c, CelfBuffers* cb, hipStream_t st);
+
+// Destroys the launched CELF graphs that have completed (all of them when
+// `wait`).
+static void sweep_graph_runs(im_ctx* c, bool wait) {
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto& v = c->graph_runs;
+  for (size_t i = 0; i < v.size();) {
+    if (wait) (void)hipEventSynchronize(v[i].done);
+    if (hipEventQuery(v[i].done) != hipSuccess) {
+      ++i;
+      continue;
+    }
+    (void)hipGraphExecDestroy(v[i].exec);
+    (void)hipGraphDestroy(v[i].graph);
+    (void)hipEventDestroy(v[i].done);
+    v[i] = v.back();
+    v.pop_back();
+  }
+}
+
 void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+  sweep_graph_runs(c, false);
+  if (c->tune.use_graphs && c->profiling < 2) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      celf_steps_direct(c, cb, st);
+      ok = hipStreamEndCapture(st, &graph) == hipSuccess && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipGraphLaunch(exec, st) == hipSuccess && hipEventRecord(done, st) == hipSuccess;
+    if (ok) {
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      c->graph_runs.push_back({exec, graph, done});
+      return;
+    }
+    (void)hipGetLastError();  // capture not possible here: launch directly
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (done) (void)hipEventDestroy(done);
+  }
+  celf_steps_direct(c, cb, st);
+}
+
+static void celf_steps_direct(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   const CelfView& v = cb->v;
   const uint32_t bulk_blocks = std::max(1u, std::min(2048u, v.m.n));
   for (uint32_t k = 0; k < v.K; ++k) {
@@ -699,6 +749,7 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   resolve_pending(c);
   while (!c->graphs.empty()) im_graph_free(c->graphs.back());
+  sweep_graph_runs(c, true);
   if (c->arena.base) raw_free(c, c->arena.base);
   for (hipStream_t b : c->bstreams) {
     (void)hipStreamSynchronize(b);

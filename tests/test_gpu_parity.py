@@ -11,8 +11,8 @@ import oracle
 import paper_2008_03095_amd as P
 from tests.conftest import announce
 from tests.helpers import digest_weights, label_digests
-from workloads import (chung_lu, from_edge_list, make_config, path_graph, random_small_graph,
-                       star_graph, trivalency_p)
+from workloads import (chung_lu, from_edge_list, make_config, normal_p, path_graph, random_small_graph,
+                       star_graph, trivalency_p, uniform_p)
 
 pytestmark = pytest.mark.gpu
 
@@ -102,6 +102,17 @@ def test_per_slot_probabilities(gpu_ctx):
     g = chung_lu(3000, 15000, 2.5, 101)
     g.p_slot = trivalency_p(g, 101)
     _full_check(gpu_ctx, g, 0.0, 512, 101, 8, sigma_sets=[[0, 1], [10, 20, 30]], name="trivalency")
+
+
+@pytest.mark.parametrize("setting", ["uniform", "normal"])
+def test_weight_settings(gpu_ctx, setting):
+    # the paper's other weight settings as per-slot probabilities: U[0, 0.1]
+    # and N(0.05, 0.025) clipped; a graph with hubs (degree > 64) and ragged R
+    g = chung_lu(4000, 30000, 2.1, 7)
+    assert int((g.degrees() > 64).sum()) > 0
+    g.p_slot = uniform_p(g, 7) if setting == "uniform" else normal_p(g, 7)
+    _full_check(gpu_ctx, g, 0.0, 600, 7, 15, sigma_sets=[[0, 5, 9], list(range(0, 4000, 97))],
+                name=f"weights {setting}")
 
 
 def test_per_slot_zero_and_one(gpu_ctx):
@@ -240,17 +251,19 @@ CELF_CASES = {
 
 
 CELF_VARIANTS = {
-    "persistent": (P.Context.CELF_PERSISTENT, 0),
+    "persistent": (P.Context.CELF_PERSISTENT, 0, False),
     # one candidate in a step's first round: many rounds, pool refills and bulk passes
-    "persistent_round1": (P.Context.CELF_PERSISTENT, 1),
-    "per_step": (P.Context.CELF_PER_STEP, 0),
+    "persistent_round1": (P.Context.CELF_PERSISTENT, 1, False),
+    "per_step": (P.Context.CELF_PER_STEP, 0, False),
+    # the per-step launches captured into one hipGraph
+    "per_step_graph": (P.Context.CELF_PER_STEP, 0, True),
 }
 
 
 @pytest.mark.parametrize("variant", list(CELF_VARIANTS))
 @pytest.mark.parametrize("case", list(CELF_CASES))
 def test_celf_modes(gpu_ctx, case, variant):
-    mode, round0 = CELF_VARIANTS[variant]
+    mode, round0, graphs = CELF_VARIANTS[variant]
     make, p, R, seed, K = CELF_CASES[case]
     g = make()
     announce(f"CELF {variant} {case} n={g.n} K={K}")
@@ -258,14 +271,15 @@ def test_celf_modes(gpu_ctx, case, variant):
     old = gpu_ctx.tuning()
     G = P.Graph.from_csr(gpu_ctx, g)
     try:
-        gpu_ctx.set_tuning(celf_mode=mode, celf_round0=round0)
+        gpu_ctx.set_tuning(celf_mode=mode, celf_round0=round0, use_graphs=graphs)
         G.set_params(p, R, seed)
         seeds, marg, cover = G.select_seeds(K)
         assert list(seeds) == list(ref["seeds"])
         assert list(marg) == list(ref["marginal"])
         assert cover == ref["cover"]
     finally:
-        gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
+        gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"],
+                           use_graphs=old["use_graphs"])
         G.free()
 
 
@@ -273,7 +287,7 @@ def test_celf_modes(gpu_ctx, case, variant):
 def test_batch_select_mixed(gpu_ctx, variant):
     # graphs of different sizes and parameters in one call; K = 0, K = n and
     # more graphs than one workgroup each would get with equal groups
-    mode, round0 = CELF_VARIANTS[variant]
+    mode, round0, _ = CELF_VARIANTS[variant]
     specs = [
         (chung_lu(400, 1600, 2.5, 41), 0.05, 256, 41, 0),
         (chung_lu(900, 3000, 2.3, 42), 0.02, 512, 42, 12),

@@ -16,6 +16,8 @@ from .graphs import (  # noqa: F401
     rmat,
     from_edge_list,
     trivalency_p,
+    uniform_p,
+    normal_p,
     star_graph,
     path_graph,
     random_small_graph,

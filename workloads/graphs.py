@@ -194,6 +194,35 @@ def trivalency_p(g: Graph, graph_seed: int, values=(0.1, 0.01, 0.001)) -> np.nda
     return np.asarray(values, dtype=np.float64)[cls]
 
 
+def _edge_uniforms(g: Graph, seed: int, stream: int) -> np.ndarray:
+    """One uniform double in [0, 1) per slot, equal on both slots of an edge:
+    the SplitMix64 finaliser of (seed << 40) ^ (stream << 36) ^ (u * n + v),
+    u < v, top 53 bits."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+    cols = g.col.astype(np.int64)
+    lo = np.minimum(rows, cols)
+    hi = np.maximum(rows, cols)
+    key = (lo * g.n + hi).astype(np.uint64) ^ (np.uint64(seed) << np.uint64(40)) ^ (
+        np.uint64(stream) << np.uint64(36))
+    return (_mix64(key) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def uniform_p(g: Graph, seed: int, lo: float = 0.0, hi: float = 0.1) -> np.ndarray:
+    """Per-slot probabilities drawn uniformly from [lo, hi) per undirected
+    edge (the paper's third weight setting, U[0, 0.1])."""
+    return lo + (hi - lo) * _edge_uniforms(g, seed, 1)
+
+
+def normal_p(g: Graph, seed: int, mean: float = 0.05, sd: float = 0.025) -> np.ndarray:
+    """Per-slot probabilities from N(mean, sd) per undirected edge (Box-Muller
+    on two edge uniforms), clipped to [0, 1] (the paper's second weight
+    setting, N(0.05, 0.025))."""
+    u1 = _edge_uniforms(g, seed, 2)
+    u2 = _edge_uniforms(g, seed, 3)
+    z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+    return np.clip(mean + sd * z, 0.0, 1.0)
+
+
 def star_graph(n: int) -> Graph:
     """Star centred at vertex 0 with leaves 1..n-1."""
     leaves = np.arange(1, n, dtype=np.int64)
