@@ -448,6 +448,17 @@ def main():
         "cpu_baseline": None,
     }
     rec["memo_stats"] = G.memo_stats()
+    # sigma of the selected seeds without a memo (search over all samples),
+    # outside the timed steps
+    t_direct = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cnt_d, _, levels = G.estimate_sigma_direct(seeds)
+        t_direct.append(time.perf_counter() - t)
+        if cnt_d != cover:
+            raise RuntimeError("memo-free sigma differs from the cover count")
+    rec["sigma_without_memo"] = {"ms": 1e3 * min(t_direct), "levels": levels, "count": cnt_d}
     G.free()
     ctx.close()
     if not args.no_cpu_baseline:

@@ -137,6 +137,16 @@ im_status im_select_seeds(im_graph *g, uint32_t K, uint32_t *seeds, int64_t *mar
 im_status im_estimate_sigma(im_graph *g, const uint32_t *S, uint32_t s_len, int64_t *count,
                             double *sigma);
 
+/* sigma(S) without a memo: the same count as im_estimate_sigma (RandCas,
+ * Algorithm 4, on the same R hash samples), computed by a breadth-first
+ * search from S over the live edges of every sample at once, for parameter
+ * sets whose memo would not fit or is not wanted.  Needs 3 n R / 8 bytes of
+ * device memory plus the sampler state (the memo needs 4 n R); builds
+ * nothing that persists.  *levels (may be NULL) receives the number of
+ * search levels.  Same semantics and errors as im_estimate_sigma. */
+im_status im_estimate_sigma_direct(im_graph *g, const uint32_t *S, uint32_t s_len, int64_t *count,
+                                   double *sigma, uint32_t *levels);
+
 /* Copies component labels of simulations first_sample .. first_sample +
  * n_samples - 1 for every vertex into host[n][n_samples] (vertex-major).
  * Errors: IM_ERR_INVALID_ARG when the range exceeds R. */
@@ -180,6 +190,15 @@ typedef struct {
 } im_tuning;
 im_status im_set_tuning(im_ctx *ctx, const im_tuning *t);
 im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);
+
+/* Autotuner (not part of the paper's method: it picks launch shapes).  Times
+ * `reps` cold K-seed selections of g (memo dropped before each) for every
+ * candidate cc_chunk in {256, 512, 1024} and, with the persistent CELF
+ * kernel, celf_round0 in {8, 16, 32}; checks that all of them select the same
+ * seeds (IM_ERR_DEVICE otherwise), applies the fastest to g's context and
+ * writes it to *best.  g's memo is rebuilt each time (the resident memo is
+ * dropped).  Errors: NULL arguments, parameters not set, K outside 1..n. */
+im_status im_autotune(im_graph *g, uint32_t K, uint32_t reps, im_tuning *best);
 
 /* Per-kernel device timing with HIP events recorded on the context stream
  * around launches (off by default).  level 0: off; 1: the kernels that run

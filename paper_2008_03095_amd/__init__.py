@@ -107,6 +107,39 @@ class Context:
         return dict(cc_chunk=t.cc_chunk, celf_width=t.celf_width, use_graphs=bool(t.use_graphs),
                     celf_mode=t.celf_mode, celf_round0=t.celf_round0)
 
+    def autotune(self, graph: "Graph", K: int, reps: int = 2, cache: Optional[str] = None) -> dict:
+        """Launch shapes for `graph` (im_autotune), applied to this context.
+
+        With `cache` (a JSON file), a shape found before for a graph of the
+        same size class (n, slots, R, hubs) is applied without timing, and a
+        new one is stored."""
+        import json
+        import os
+
+        key = None
+        if cache:
+            rp = np.diff(np.asarray(graph._row_ptr, dtype=np.int64)) if graph._row_ptr is not None else None
+            hubs = int((rp > 64).sum()) if rp is not None else -1
+            key = f"n={graph.n},nnz={graph.nnz},R={graph.R},hubs={hubs},mode={self.tuning()['celf_mode']}"
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    known = json.load(f)
+                if key in known:
+                    self.set_tuning(cc_chunk=known[key]["cc_chunk"], celf_round0=known[key]["celf_round0"])
+                    return self.tuning()
+        t = im_tuning()
+        check(self._lib.im_autotune(graph.handle, int(K), int(reps), C.byref(t)))
+        out = self.tuning()
+        if cache:
+            known = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    known = json.load(f)
+            known[key] = out
+            with open(cache, "w") as f:
+                json.dump(known, f, indent=1, sort_keys=True)
+        return out
+
     def set_profiling(self, level):
         """0/False: off; 1/True: per-build kernels; 2: also every CELF launch."""
         check(self._lib.im_set_profiling(self.handle, int(level)))
@@ -137,6 +170,8 @@ class Graph:
                                           _ptr(rp), _ptr(cl), _ptr(ps), C.byref(out)))
         self.handle = out
         self.R = 0
+        self.nnz = int(rp[-1]) if rp.size else 0
+        self._row_ptr = rp
 
     @classmethod
     def from_csr(cls, ctx: Context, g) -> "Graph":
@@ -172,6 +207,16 @@ class Graph:
         check(self._lib.im_estimate_sigma(self.handle, _ptr(arr) if arr.size else None, int(arr.size),
                                           C.byref(cnt), C.byref(sig)))
         return int(cnt.value), float(sig.value)
+
+    def estimate_sigma_direct(self, S: Sequence[int]):
+        """sigma(S) without a memo (im_estimate_sigma_direct): (count, sigma, levels)."""
+        arr = np.ascontiguousarray(np.asarray(S, dtype=np.uint32))
+        cnt = C.c_int64()
+        sig = C.c_double()
+        lv = C.c_uint32()
+        check(self._lib.im_estimate_sigma_direct(self.handle, _ptr(arr) if arr.size else None, int(arr.size),
+                                                 C.byref(cnt), C.byref(sig), C.byref(lv)))
+        return int(cnt.value), float(sig.value), int(lv.value)
 
     def labels(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         count = self.R - first if count is None else count

@@ -66,6 +66,7 @@ SIGNATURES = {
     "im_drop_memo": (C.c_int, [vp]),
     "im_select_seeds": (C.c_int, [vp, u32, vp, vp, P(i64)]),
     "im_estimate_sigma": (C.c_int, [vp, vp, u32, P(i64), P(dbl)]),
+    "im_estimate_sigma_direct": (C.c_int, [vp, vp, u32, P(i64), P(dbl), P(u32)]),
     "im_copy_labels": (C.c_int, [vp, vp, u32, u32]),
     "im_copy_sizes": (C.c_int, [vp, vp, u32, u32]),
     "im_copy_gains0": (C.c_int, [vp, vp]),
@@ -73,6 +74,7 @@ SIGNATURES = {
     "im_graph_nnz": (u64, [vp]),
     "im_set_tuning": (C.c_int, [vp, P(im_tuning)]),
     "im_get_tuning": (C.c_int, [vp, P(im_tuning)]),
+    "im_autotune": (C.c_int, [vp, u32, u32, P(im_tuning)]),
     "im_set_profiling": (C.c_int, [vp, C.c_int]),
     "im_reset_kernel_stats": (C.c_int, [vp]),
     "im_kernel_stats": (C.c_int, [vp, C.c_char_p, P(u64), P(dbl)]),

@@ -1,0 +1,25 @@
+// Launchers of the memo-free sigma kernels (direct.hip).
+#pragma once
+
+#include "common.h"
+
+namespace infuse {
+
+struct BfsView {
+  uint32_t n, ntiles;
+  uint64_t* V;          // [n][ntiles][4] visited columns (ballot layout)
+  const uint64_t* F;    // frontier of this level
+  uint64_t* N;          // frontier of the next level
+  const uint32_t* cur;  // frontier vertices of this level
+  uint32_t* next;       // frontier vertices of the next level
+  uint32_t* ncount;     // |next|
+  uint32_t* stamp;      // [n] last level a vertex joined a frontier list
+};
+
+void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st);
+void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t ncur, uint32_t level,
+                      hipStream_t st);
+void launch_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t ntiles, hipStream_t st);
+void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st);
+
+}  // namespace infuse

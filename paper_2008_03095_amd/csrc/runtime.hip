@@ -1138,6 +1138,112 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   return s;
 }
 
+extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, uint32_t s_len, int64_t* count,
+                                              double* sigma, uint32_t* levels) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  if (s_len && !S) return fail(IM_ERR_INVALID_ARG, "NULL seed array");
+  std::vector<uint32_t> set;
+  im_status s = normalize_set(g, S, s_len, &set);
+  if (s != IM_OK) return s;
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  if (levels) *levels = 0;
+  if (set.empty()) {
+    if (count) *count = 0;
+    if (sigma) *sigma = 0.0;
+    return IM_OK;
+  }
+  im_ctx* c = g->ctx;
+  hipStream_t st = c->stream;
+  const uint32_t n = g->n, R = g->R, Rs = round_up(R, kTile), ntiles = Rs / kTile, len = (uint32_t)set.size();
+  const uint64_t T = thr_of(g->p);
+  const uint64_t words = (uint64_t)n * ntiles * 4;
+  // one allocation: sampler state, visited and two frontier bitsets, two
+  // frontier lists, level stamps, counters, S
+  const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
+  const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
+  const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
+  const size_t b_cnt = 256, b_S = align256((size_t)len * 4);
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 3 * b_list + b_cnt + b_S;
+  void* base = nullptr;
+  s = ctx_alloc(c, total, &base);
+  if (s != IM_OK) return s;
+  char* p8 = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* r = p8;
+    p8 += bytes;
+    return r;
+  };
+  MemoView mv = {};
+  mv.n = n;
+  mv.R = R;
+  mv.Rs = Rs;
+  mv.ntiles = ntiles;
+  mv.never_live = (!g->per_edge && T == 0) ? 1u : 0u;
+  mv.tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
+  mv.kshift = bitlen32(mv.tm1);
+  uint2* edges = reinterpret_cast<uint2*>(take(b_edges));
+  uint32_t* xs = reinterpret_cast<uint32_t*>(take(b_x));
+  uint32_t* inv = reinterpret_cast<uint32_t*>(take(b_x));
+  uint32_t* pos = reinterpret_cast<uint32_t*>(take(b_pos));
+  uint64_t* scr = reinterpret_cast<uint64_t*>(take(b_scr));
+  uint64_t* V = reinterpret_cast<uint64_t*>(take(b_bits));
+  uint64_t* A = reinterpret_cast<uint64_t*>(take(b_bits));
+  uint64_t* B = reinterpret_cast<uint64_t*>(take(b_bits));
+  uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
+  uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
+  uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0] next-list size, [2..3] result
+  uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
+  mv.edges = edges;
+  mv.xs = xs;
+  const GraphView gv = g->view();
+  launch_edge_hash(gv, g->seed, edges, st);
+  launch_x_sort(g->seed, R, Rs, scr, xs, inv, pos, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(V), (uint64_t)(3 * b_bits + 3 * b_list + b_cnt) / 4, 0u, st);
+  hipError_t e = hipMemcpyAsync(dS, set.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
+  BfsView bv;
+  bv.n = n;
+  bv.ntiles = ntiles;
+  bv.V = V;
+  bv.F = nullptr;
+  bv.N = A;
+  bv.cur = nullptr;
+  bv.next = L0;
+  bv.ncount = cnt;
+  bv.stamp = stamp;
+  launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
+  uint32_t ncur = len, level = 1;
+  {
+    KTimer t(c, "sigma_direct", st);
+    while (e == hipSuccess && ncur) {
+      bv.F = A;
+      bv.N = B;
+      bv.cur = L0;
+      bv.next = L1;
+      launch_fill_u32(cnt, 1, 0u, st);
+      launch_bfs_level(gv, mv, bv, ncur, level, st);
+      uint32_t nnext = 0;
+      e = hipMemcpyAsync(&nnext, cnt, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      launch_bfs_clear(A, L0, ncur, ntiles, st);  // A is all zero again
+      std::swap(A, B);
+      std::swap(L0, L1);
+      ncur = nnext;
+      ++level;
+    }
+    if (e == hipSuccess) launch_bfs_count(V, words, reinterpret_cast<unsigned long long*>(cnt + 2), st);
+  }
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt + 2, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  ctx_free(c, base);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free sigma failed: %s", hipGetErrorString(e));
+  if (count) *count = (int64_t)h;
+  if (sigma) *sigma = (double)h / (double)R;
+  if (levels) *levels = level - 1;
+  return IM_OK;
+}
+
 static im_status export_range(im_graph* g, int32_t* host, uint32_t first, uint32_t cnt, int mode) {
   if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
   if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");

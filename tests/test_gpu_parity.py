@@ -317,3 +317,66 @@ def test_batch_select_mixed(gpu_ctx, variant):
         gpu_ctx.set_tuning(celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
         for G in Gs:
             G.free()
+
+
+def test_autotune_picks_a_shape_and_keeps_results(gpu_ctx, tmp_path):
+    g = chung_lu(3000, 20000, 2.1, 8)
+    announce("autotune")
+    old = gpu_ctx.tuning()
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(0.04, 512, 8)
+        cache = str(tmp_path / "tuning.json")
+        t = gpu_ctx.autotune(G, 12, reps=1, cache=cache)
+        assert t["cc_chunk"] in (256, 512, 1024)
+        if t["celf_mode"] == P.Context.CELF_PERSISTENT:
+            assert t["celf_round0"] in (8, 16, 32)
+        again = gpu_ctx.autotune(G, 12, reps=1, cache=cache)  # from the cache
+        assert again["cc_chunk"] == t["cc_chunk"] and again["celf_round0"] == t["celf_round0"]
+        ref = oracle.run_memo(g, oracle.Sampler("hash", p=0.04, R=512, seed=8), 12, threads=4)
+        seeds, marg, cover = G.select_seeds(12)
+        assert list(seeds) == list(ref["seeds"]) and cover == ref["cover"]
+    finally:
+        gpu_ctx.set_tuning(cc_chunk=old["cc_chunk"], celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
+        G.free()
+
+
+DIRECT_CASES = {
+    "c1": (lambda: make_config("c1").graphs[0], 0.05, 256, 1, None),
+    "star300_R300": (lambda: star_graph(300), 0.2, 300, 3, None),
+    "path400_dense": (lambda: path_graph(400), 0.97, 128, 5, None),
+    "empty7": (lambda: from_edge_list(7, np.empty(0, np.int64), np.empty(0, np.int64)), 0.5, 64, 1, None),
+    "p0": (lambda: chung_lu(500, 2000, 2.5, 9), 0.0, 256, 9, None),
+    "p1": (lambda: chung_lu(500, 2000, 2.5, 9), 1.0, 64, 9, None),
+    "hubs_uniform_w": (lambda: chung_lu(4000, 30000, 2.1, 7), 0.0, 600, 7, "uniform"),
+    "trivalency": (lambda: chung_lu(3000, 15000, 2.5, 101), 0.0, 512, 101, "trivalency"),
+}
+
+
+@pytest.mark.parametrize("case", list(DIRECT_CASES))
+def test_sigma_without_memo(gpu_ctx, case):
+    make, p, R, seed, w = DIRECT_CASES[case]
+    g = make()
+    if w == "uniform":
+        g.p_slot = uniform_p(g, seed)
+    elif w == "trivalency":
+        g.p_slot = trivalency_p(g, seed)
+    announce(f"sigma without memo {case} n={g.n} R={R}")
+    s = oracle.Sampler("hash", p=p, R=R, seed=seed)
+    sets = [[0], [0, g.n - 1], list(range(0, g.n, max(1, g.n // 37))), [1, 1, 2, 2, 3]]
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(p, R, seed)
+        for S in sets:
+            S = [x for x in S if x < g.n]
+            cnt, sig, levels = G.estimate_sigma_direct(S)
+            want = oracle.sigma_count(g, s, S, threads=4)
+            assert cnt == want, (S[:5], cnt, want)
+            assert sig == pytest.approx(want / R)
+            if p == 0.0 and w is None:
+                assert cnt == len(set(S)) * R
+        assert G.estimate_sigma_direct([]) == (0, 0.0, 0)
+        with pytest.raises(P.InfuseError):
+            G.estimate_sigma_direct([g.n])
+    finally:
+        G.free()

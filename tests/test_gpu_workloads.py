@@ -51,6 +51,10 @@ def test_c4_large_graph(gpu_ctx):
             assert int(g0[int(v)]) == x
         for q in gold["sigma"]:
             assert G.estimate_sigma(q["S"])[0] == q["count"]
+        # the memo-free search reaches the same counts at full size
+        assert G.estimate_sigma_direct(gold["seeds"])[0] == gold["cover"]
+        for q in gold["sigma"][:2]:
+            assert G.estimate_sigma_direct(q["S"])[0] == q["count"]
         dig = _all_digests(G, g.n, w.R, 512)
         assert ["%016x" % int(x) for x in dig[::gold["digest_every"]]] == gold["digests"]
         assert combine_digests(dig) == gold["label_check"]
