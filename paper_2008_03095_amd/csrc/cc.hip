@@ -67,7 +67,10 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
   out.y = cnt[1] ? mn[1] : -1;
   out.z = cnt[2] ? mn[2] : -1;
   out.w = cnt[3] ? mn[3] : -1;
-  *reinterpret_cast<int4*>(row + tc.q0) = out;
+  // streaming store: the row is not read again before the next kernel
+  typedef int int4v __attribute__((ext_vector_type(4)));
+  const int4v ov = {out.x, out.y, out.z, out.w};
+  __builtin_nontemporal_store(ov, reinterpret_cast<int4v*>(row + tc.q0));
   need = __ballot(cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1) != 0;
 }
 
