@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(256) k_flatten(MemoView m) {
 // roots below kHotRoots are summed in LDS first, because large components
 // (in power-law graphs the giant one) are rooted at small ids and their
 // members would otherwise all hit the same words.
-constexpr uint32_t kHotRoots = 64;
+constexpr uint32_t kHotRoots = 8;
 constexpr uint32_t kCountMaxBlockVerts = 4096;
 
 // Vertices per workgroup of k_count: enough workgroups to fill the device

@@ -279,13 +279,22 @@ __device__ inline uint64_t p_eval_tiles(const CelfView& c, uint32_t u, uint32_t 
   for (int b = 0; b < B; ++b) {
     const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
     const int32_t vals[4] = {cur[b].x, cur[b].y, cur[b].z, cur[b].w};
+    uint32_t root[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int32_t val = vals[i];
       const bool shared = q0 + i < m.R && val != -1;
-      const uint32_t root = val < 0 ? u : (uint32_t)val;
+      root[i] = shared ? (val < 0 ? u : (uint32_t)val) : kInvalid;
       size[b][i] = val < 0 ? -val : (shared ? -m.M[(uint64_t)val * m.Rs + q0 + i] : 0);
-      word[b][i] = shared ? ld32(&c.cov[(uint64_t)root * c.cwords + ((q0 + i) >> 5)]) : 0u;
+    }
+    // the lane's four columns share one coverage word: load it once for
+    // every column whose component has the root of the first shared column
+    const uint32_t r0 = root[0] != kInvalid ? root[0] : root[1] != kInvalid ? root[1] : root[2] != kInvalid ? root[2] : root[3];
+    const uint32_t w0 = r0 != kInvalid ? ld32(&c.cov[(uint64_t)r0 * c.cwords + (q0 >> 5)]) : 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      word[b][i] = root[i] == kInvalid ? 0u : w0;  // a singleton (val -1) is never covered
+      if (root[i] != kInvalid && root[i] != r0) word[b][i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
     }
   }
   uint64_t sum = 0;
