@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/infuse.h"
+#include "arena.h"
 #include "common.h"
 
 struct im_graph;
@@ -99,19 +100,6 @@ class KTimer {
   bool on_ = false;
 };
 
-}  // namespace infuse
-
-namespace infuse {
-// Sub-allocator over one reservation of the context's whole budget: best fit
-// from the free ranges, which are merged with their neighbours when freed.
-struct Arena {
-  char* base = nullptr;
-  size_t size = 0;
-  std::map<size_t, size_t> by_off;        // free ranges: offset -> size
-  std::multimap<size_t, size_t> by_size;  // free ranges: size -> offset
-  void* take(size_t bytes);
-  void give(void* p, size_t bytes);
-};
 }  // namespace infuse
 
 struct im_ctx {

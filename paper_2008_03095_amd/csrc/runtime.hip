@@ -78,47 +78,6 @@ static void* raw_alloc(im_ctx* c, size_t bytes) {
 
 // Evicts one unpinned memo: the least recently used among those no queued
 // serving query wants, else the least wanted, least recently used one.
-void* Arena::take(size_t bytes) {
-  auto it = by_size.lower_bound(bytes);
-  if (it == by_size.end()) return nullptr;
-  const size_t sz = it->first, off = it->second;
-  by_size.erase(it);
-  by_off.erase(off);
-  if (sz > bytes) {
-    by_off[off + bytes] = sz - bytes;
-    by_size.emplace(sz - bytes, off + bytes);
-  }
-  return base + off;
-}
-
-void Arena::give(void* p, size_t bytes) {
-  size_t off = static_cast<size_t>(static_cast<char*>(p) - base), sz = bytes;
-  auto erase_range = [&](std::map<size_t, size_t>::iterator r) {
-    auto range = by_size.equal_range(r->second);
-    for (auto q = range.first; q != range.second; ++q)
-      if (q->second == r->first) {
-        by_size.erase(q);
-        break;
-      }
-    return by_off.erase(r);
-  };
-  auto next = by_off.lower_bound(off);
-  if (next != by_off.end() && next->first == off + sz) {
-    sz += next->second;
-    next = erase_range(next);
-  }
-  if (next != by_off.begin()) {
-    auto prev = std::prev(next);
-    if (prev->first + prev->second == off) {
-      off = prev->first;
-      sz += prev->second;
-      erase_range(prev);
-    }
-  }
-  by_off[off] = sz;
-  by_size.emplace(sz, off);
-}
-
 static bool evict_one(im_ctx* c) {
   Memo* victim = nullptr;
   im_graph* owner = nullptr;
@@ -154,12 +113,8 @@ im_status ctx_alloc(im_ctx* c, size_t bytes, void** out) {
   if (c->budget && !c->arena_tried) {
     // one reservation of the whole budget, carved up by the arena
     c->arena_tried = true;
-    c->arena.base = static_cast<char*>(raw_alloc(c, c->budget));
-    if (c->arena.base) {
-      c->arena.size = c->budget;
-      c->arena.by_off[0] = c->budget;
-      c->arena.by_size.emplace(c->budget, 0);
-    }
+    void* b = raw_alloc(c, c->budget);
+    if (b) c->arena.reset(b, c->budget);
   }
   void* p = nullptr;
   if (c->arena.base) {
