@@ -219,10 +219,15 @@ __global__ void __launch_bounds__(256) k_lists(MemoView m) {
 // visited entry is re-pointed to its grandparent with an atomic store (the
 // memo is written only by atomics while linking); a value written from a
 // stale read is still an ancestor.
-__device__ inline uint32_t find_root_halving(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q) {
+// The walk also ends at `stop` (a root the caller holds, or kInvalid):
+// reaching it shows that x is in the caller's tree, which is all a union
+// needs to know.
+__device__ inline uint32_t find_root_halving(int32_t* M, uint32_t Rs, uint32_t x, uint32_t q,
+                                             uint32_t stop = kInvalid) {
   while (true) {
+    if (x == stop) return x;
     const int32_t p = M[(uint64_t)x * Rs + q];
-    if (p < 0) return x;
+    if (p < 0 || (uint32_t)p == stop) return p < 0 ? x : stop;
     const int32_t gp = M[(uint64_t)p * Rs + q];
     if (gp < 0) return (uint32_t)p;
     __hip_atomic_store(&M[(uint64_t)x * Rs + q], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -239,7 +244,7 @@ __device__ inline uint32_t find_root_halving(int32_t* M, uint32_t Rs, uint32_t x
 // atomics in this kernel (the XCD L2 caches are not coherent within a
 // kernel, so plain stores must not share lines with atomics).
 __device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint32_t b, uint32_t q) {
-  b = find_root_halving(M, Rs, b, q);
+  b = find_root_halving(M, Rs, b, q, a);
   while (a != b) {
     if (a < b) {
       const uint32_t t = a;
@@ -251,8 +256,8 @@ __device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint3
                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return b;
-    a = find_root_halving(M, Rs, (uint32_t)expected, q);
-    b = find_root_halving(M, Rs, b, q);
+    a = find_root_halving(M, Rs, (uint32_t)expected, q, b);
+    b = find_root_halving(M, Rs, b, q, a);
   }
   return a;
 }
@@ -344,27 +349,27 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
 }
 
 // k_link_hubs: the unions of hub vertices, one wavefront per (hub, tile,
-// piece of 64 smaller neighbours); tiles without an lmask bit are skipped.
-// The piece of a wavefront is found by binary search in the per-hub prefix
-// sums of pieces.
+// piece of kHubPiece smaller neighbours, walked 64 at a time); tiles without
+// an lmask bit are skipped.  The piece table gives the hub and the piece's
+// first slot.
 template <bool PER_EDGE>
 __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
   const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t pg = uni((uint32_t)(wid / m.ntiles)), t = uni((uint32_t)(wid % m.ntiles));
   if (pg >= g.hub_pieces) return;
-  uint32_t lo = 0, hi = g.nhubs;  // last hub with hub_poff[h] <= pg
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (g.hub_poff[mid] <= pg)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const uint32_t v = uni(g.hubs[lo]);
+  const uint2 pc = g.hub_piece[pg];
+  const uint32_t v = uni(pc.x);
   if (!((m.lmask[(uint64_t)v * m.mwords + (t >> 5)] >> (t & 31)) & 1u)) return;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t beg = uni(g.row_ptr[v]) + (pg - uni(g.hub_poff[lo])) * (uint32_t)kWave;
-  const uint32_t end = min(beg + (uint32_t)kWave, uni(g.split[v]));  // smaller neighbours only
+  const uint32_t pbeg = uni(pc.y);
+  const uint32_t pend = min(pbeg + kHubPiece, uni(g.split[v]));  // smaller neighbours only
+  TileCtx tc;
+  tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
+  const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
+  const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
+  uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
+  for (uint32_t beg = pbeg; beg < pend; beg += kWave) {
+  const uint32_t end = min(beg + (uint32_t)kWave, pend);
   uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
   if (beg + lane < end) {
     const uint2 ed = m.edges[beg + lane];
@@ -372,11 +377,6 @@ __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
     rh = ed.y;
     if (PER_EDGE) rtm1 = g.tm1[beg + lane];
   }
-  TileCtx tc;
-  tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
-  const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
-  const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
-  uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
   for_candidates<PER_EDGE, true>(g, m, v, beg, end, end, lane, true, rcol, rh, rtm1, tc,
                                  [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
 #pragma unroll
@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
                                      }
                                    }
                                  });
+  }
 }
 
 // k_flatten: every non-root entry of a listed tile is replaced by its root

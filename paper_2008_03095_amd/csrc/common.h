@@ -62,9 +62,10 @@ struct GraphView {
   const uint32_t* split;    // [n]  first slot of row v whose neighbour is > v
   const uint32_t* tm1;      // [nnz] per-slot T-1, or nullptr (uniform p)
   const uint32_t* hubs;     // [nhubs] vertices with more than kWave device neighbours
-  const uint32_t* hub_poff; // [nhubs+1] prefix sums of ceil(smaller neighbours / kWave)
+  const uint2* hub_piece;   // [hub_pieces] {hub vertex, first slot} of each kHubPiece-slot
+                            // piece of a hub's smaller neighbours
   uint32_t nhubs;
-  uint32_t hub_pieces;      // hub_poff[nhubs]
+  uint32_t hub_pieces;      // entries of hub_piece
 };
 
 // Per-memo device view.
@@ -94,6 +95,7 @@ struct MemoView {
   uint32_t list_cap;
 };
 
+constexpr uint32_t kHubPiece = 256;  // smaller neighbours of a hub per union wavefront
 constexpr uint32_t kSubLists = 256;
 constexpr uint32_t kListBlocks = 8192;  // fixed grid of the list kernels (multiple of kSubLists)
 

@@ -156,7 +156,7 @@ struct im_graph {
   uint32_t* split = nullptr;
   uint32_t* tm1 = nullptr;
   uint32_t* hubs = nullptr;  // vertices with more than kWave device neighbours
-  uint32_t* hub_poff = nullptr;  // prefix sums of their 64-slot pieces of smaller neighbours
+  uint2* hub_piece = nullptr;  // {hub, first slot} of every 64-slot piece of their smaller neighbours
   uint32_t nhubs = 0;
   uint32_t hub_pieces = 0;
   double p = 0.0;

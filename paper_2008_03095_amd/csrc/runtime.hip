@@ -26,7 +26,7 @@ infuse::GraphView im_graph::view() const {
   v.split = split;
   v.tm1 = per_edge ? tm1 : nullptr;
   v.hubs = hubs;
-  v.hub_poff = hub_poff;
+  v.hub_piece = hub_piece;
   v.nhubs = nhubs;
   v.hub_pieces = hub_pieces;
   return v;
@@ -837,11 +837,12 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     split[u] = (uint32_t)(std::lower_bound(col.begin() + rp[u], col.end(), u) - col.begin());
   }
   rp[n] = (uint32_t)col.size();
-  std::vector<uint32_t> hubs, hub_poff(1, 0);
+  std::vector<uint32_t> hubs;
+  std::vector<uint2> hub_piece;
   for (uint32_t u = 0; u < n; ++u)
     if (rp[u + 1] - rp[u] > (uint32_t)kWave) {
       hubs.push_back(u);
-      hub_poff.push_back(hub_poff.back() + (split[u] - rp[u] + kWave - 1) / kWave);
+      for (uint32_t j = rp[u]; j < split[u]; j += kHubPiece) hub_piece.push_back(make_uint2(u, j));
     }
   im_graph* g = new im_graph();
   g->ctx = c;
@@ -852,9 +853,9 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   const size_t b_rp = align256((size_t)(n + 1) * 4), b_col = align256((size_t)g->nnz * 4 + 4);
   const size_t b_split = align256((size_t)n * 4), b_tm1 = p_slot ? align256((size_t)g->nnz * 4 + 4) : 0;
   const size_t b_hubs = align256((size_t)hubs.size() * 4 + 4);
-  const size_t b_poff = align256((size_t)hub_poff.size() * 4);
+  const size_t b_poff = align256((size_t)hub_piece.size() * 8 + 8);
   g->nhubs = (uint32_t)hubs.size();
-  g->hub_pieces = hub_poff.back();
+  g->hub_pieces = (uint32_t)hub_piece.size();
   void* base = nullptr;
   s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff, &base);
   if (s != IM_OK) {
@@ -868,7 +869,7 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   g->split = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col);
   g->tm1 = p_slot ? reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split) : nullptr;
   g->hubs = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1);
-  g->hub_poff = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1 + b_hubs);
+  g->hub_piece = reinterpret_cast<uint2*>(p8 + b_rp + b_col + b_split + b_tm1 + b_hubs);
   hipError_t e = hipMemcpyAsync(g->row_ptr, rp.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nnz)
     e = hipMemcpyAsync(g->col, col.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
@@ -878,8 +879,8 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
     e = hipMemcpyAsync(g->tm1, tm1.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nhubs)
     e = hipMemcpyAsync(g->hubs, hubs.data(), (size_t)g->nhubs * 4, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(g->hub_poff, hub_poff.data(), hub_poff.size() * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && g->hub_pieces)
+    e = hipMemcpyAsync(g->hub_piece, hub_piece.data(), hub_piece.size() * 8, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     ctx_free(c, base);
