@@ -407,7 +407,8 @@ def main():
              "sigma", "celf",
              "celf_topw", "celf_eval", "celf_bulk"]
     if args.profile_celf:
-        names += ["celf.barrier", "celf.eval", "celf.pool", "celf.rebuild", "celf.bulk"]
+        names += ["celf.barrier", "celf.eval", "celf.commit", "celf.restale", "celf.prep", "celf.post",
+                  "celf.rebuild", "celf.bulk", "celf.sort", "celf.move"]
     stats = {k: ctx.kernel_stats(k) for k in names}
     rec = {
         "metric": METRIC,

@@ -55,8 +55,8 @@ struct PCelfScratch {
   uint64_t out_bound;
   uint64_t kmax;
   uint64_t pad1[4];
-  uint64_t prof[8];                   // workgroup 0's phase clock, then counts
-  uint32_t arrive[kGroups][32];       // one 128-byte line per group
+  uint64_t prof[16];                  // workgroup 0's phase clock, then counts
+  alignas(128) uint32_t arrive[kGroups][32];  // one 128-byte line per group
   uint32_t top[32];
   uint32_t release[kGroups][32];
   uint64_t gains[3][kMaxCand];        // per-round candidate gains, rotated
@@ -71,6 +71,7 @@ struct PCelfJob {
   PCelfScratch* x;
   uint32_t* blist;   // [n] bulk candidates
   uint32_t w0;       // candidates of the first round of a step
+  uint32_t prof;     // 1: keep the phase clock (each reading is a scalar memory access)
 };
 
 // The workgroups that run one selection together: their number and this
@@ -82,17 +83,46 @@ struct Grp {
 
 __device__ inline uint32_t p_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline void p_wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Global-memory accessors.  The buffers reach this kernel through a job
+// record in memory, so the compiler cannot prove their address space and
+// would emit flat instructions, which also hold the LDS wait counter; the
+// casts below keep every device-memory access a global one.
+#define P_GLOBAL __attribute__((address_space(1)))
+typedef int p_i4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ inline P_GLOBAL T* gp(T* p) {
+  return (P_GLOBAL T*)p;
+}
+template <class T>
+__device__ inline const P_GLOBAL T* gp(const T* p) {
+  return (const P_GLOBAL T*)p;
+}
+__device__ inline p_i4 ldg4(const int32_t* p) { return *(const P_GLOBAL p_i4*)p; }
+__device__ inline int32_t ldg(const int32_t* p) { return *gp(p); }
+__device__ inline uint32_t ldg(const uint32_t* p) { return *gp(p); }
 __device__ inline uint64_t ld64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline uint32_t ld32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void st64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void st32(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t g_add(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void g_add64(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void g_or(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_or(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void g_max64(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_max(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline uint64_t p_wsum(uint64_t x) {
 #pragma unroll
@@ -111,16 +141,20 @@ __device__ inline uint64_t p_wmax(uint64_t x) {
 // Phase clock of a workgroup (100 MHz real-time counter); workgroup 0
 // reports it.
 struct PClock {
-  enum { kBarrier = 0, kEval = 1, kPoolOps = 2, kRebuild = 3, kBulk = 4, kPhases = 5 };
+  enum { kBarrier = 0, kEval = 1, kCommit = 2, kRestale = 3, kPrep = 4, kPost = 5, kRebuild = 6, kBulk = 7,
+         kSort = 8, kMove = 9, kPhases = 10 };
   uint64_t acc[kPhases];
   uint64_t mark;
   uint32_t barriers, rounds, rebuilds, bulks;
-  __device__ void start() {
+  bool on;
+  __device__ void start(bool enable) {
     for (int i = 0; i < kPhases; ++i) acc[i] = 0;
     barriers = rounds = rebuilds = bulks = 0;
-    mark = __builtin_amdgcn_s_memrealtime();
+    on = enable;
+    mark = on ? __builtin_amdgcn_s_memrealtime() : 0;
   }
   __device__ void lap(int phase) {
+    if (!on) return;
     const uint64_t t = __builtin_amdgcn_s_memrealtime();
     acc[phase] += t - mark;
     mark = t;
@@ -135,6 +169,7 @@ struct PoolLds {
   uint32_t wsum[kPBlock / 64];
   uint64_t wmax[kPBlock / 64];
   uint32_t hist[kBins];
+  uint32_t cg[64];               // restale of a small F: S entries above each F entry
   uint32_t ns, head, nf, fbest;  // S size, S front, F size, index of max F
   uint64_t out_bound;
   uint64_t prefix;
@@ -192,8 +227,8 @@ __device__ bool grid_sync(PCelfScratch* x, const Grp& G, uint32_t& gen, PClock& 
     const uint32_t ng = min(kGroups, G.nb);
     const uint32_t members = (G.nb - g + kGroups - 1) / kGroups;
     uint32_t ok = 1;
-    if (atomicAdd(&x->arrive[g][0], 1u) + 1 == gen * members)
-      if (atomicAdd(&x->top[0], 1u) + 1 == gen * ng)
+    if (g_add(&x->arrive[g][0], 1u) + 1 == gen * members)
+      if (g_add(&x->top[0], 1u) + 1 == gen * ng)
         for (uint32_t i = 0; i < ng; ++i) st32(&x->release[i][0], gen);
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     while ((int32_t)(ld32(&x->release[g][0]) - gen) < 0) {
@@ -202,7 +237,7 @@ __device__ bool grid_sync(PCelfScratch* x, const Grp& G, uint32_t& gen, PClock& 
         break;
       }
       if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
-        atomicOr(&x->err, 1u);
+        g_or(&x->err, 1u);
         ok = 0;
         break;
       }
@@ -222,79 +257,76 @@ __device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t
 // This lane's share of gain(u | S) over tile t: the sizes of u's components
 // in the lane's four columns that hold no seed.  `last` is the most recent
 // seed (or kInvalid), whose coverage bits may not be visible yet: its
-// component is tested directly.
+// component is tested directly.  The row is read without consulting tmask
+// (a tile without its bit holds -1, a singleton, in every column), which
+// saves a dependent load on this latency-bound path.
 __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
                                        uint32_t last) {
   const MemoView& m = c.m;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  const uint32_t bit = (p_uni(m.tmask[(uint64_t)u * m.mwords + (t >> 5)]) >> (t & 31)) & 1u;
-  if (!bit) return (uint64_t)min(max((int32_t)m.R - (int32_t)q0, 0), 4);
-  const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)u * m.Rs + q0);
-  int4 sl = make_int4(-1, -1, -1, -1);
-  if (last != kInvalid) sl = *reinterpret_cast<const int4*>(m.M + (uint64_t)last * m.Rs + q0);
-  const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
-  const int32_t lv[4] = {sl.x, sl.y, sl.z, sl.w};
-  int32_t size[4];
-  uint32_t word[4];
-  uint32_t root[4];
+  const bool has_last = last != kInvalid;
+  const p_i4 cur = ldg4(m.M + (uint64_t)u * m.Rs + q0);
+  const p_i4 sl = ldg4(m.M + (uint64_t)(has_last ? last : u) * m.Rs + q0);
+  // every load below has a valid address, so none waits behind a branch:
+  // a member reads its root's entry, a root or singleton its own
+  int32_t raw[4];
+  uint32_t word[4], root[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t q = q0 + i;
-    const int32_t val = vals[i];
-    const bool shared = q < m.R && val != -1;
+    const int32_t val = cur[i];
     root[i] = val < 0 ? u : (uint32_t)val;
-    size[i] = val < 0 ? -val : (shared ? -m.M[(uint64_t)val * m.Rs + q] : 0);
-    word[i] = shared ? ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q >> 5)]) : 0u;
+    raw[i] = ldg(m.M + (uint64_t)root[i] * m.Rs + q0 + i);
+    word[i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
   }
   uint64_t sum = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t q = q0 + i;
-    if (q >= m.R) continue;
-    const uint32_t lroot = lv[i] < 0 ? last : (uint32_t)lv[i];
-    const bool covered = ((word[i] >> (q & 31)) & 1u) || (last != kInvalid && lroot == root[i]);
-    sum += covered ? 0 : (uint64_t)size[i];
+    const int32_t val = cur[i];
+    const uint32_t lroot = sl[i] < 0 ? last : (uint32_t)sl[i];
+    const bool shared = val != -1;  // a singleton holds no seed
+    const bool covered = shared && (((word[i] >> (q & 31)) & 1u) || (has_last && lroot == root[i]));
+    const uint64_t size = (uint64_t)(uint32_t)(-(val < 0 ? val : raw[i]));
+    sum += (q < m.R && !covered) ? size : 0;
   }
   return sum;
 }
 
-// This lane's share of gain(u | S) over the B tiles t0 .. t0 + B - 1 (t0 a
-// multiple of B, B dividing 32, tiles past the row are skipped).  Coverage
-// is read from the bitmap only, so every commit must be visible.  The loads
-// of all B tiles are issued before any is used.
+// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
+// dividing 32; `bits` is u's tmask word shifted down to tile t0).  Tiles
+// without their bit, or past the row, read as singletons (-1) without a load.
+// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B).
+// Tiles past the row re-read the last tile (p_sum_tiles skips them), so the
+// number of loads in flight never depends on the data.  The row is read
+// whole: a tile without its tmask bit holds -1 (a singleton) in every
+// column, and almost every tile of a vertex worth re-evaluating has it.
 template <int B>
-__device__ inline uint64_t p_eval_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane) {
+__device__ inline void p_load_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane, p_i4 (&cur)[B]) {
   const MemoView& m = c.m;
-  const uint32_t bits = p_uni(m.tmask[(uint64_t)u * m.mwords + (t0 >> 5)]) >> (t0 & 31);
-  int4 cur[B];
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    cur[b] = make_int4(-1, -1, -1, -1);
-    if (((bits >> b) & 1u) && t0 + b < m.ntiles)
-      cur[b] = *reinterpret_cast<const int4*>(m.M + (uint64_t)u * m.Rs + (t0 + b) * kTile + lane * kPerLane);
-  }
-  int32_t size[B][4];
+  for (int b = 0; b < B; ++b)
+    cur[b] = ldg4(m.M + (uint64_t)u * m.Rs + min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane);
+}
+
+// This lane's share of gain(u | S) over the B tiles at t0 whose row words
+// p_load_tiles fetched.  Coverage is read from the bitmap only, so every
+// commit must be visible.  All loads have valid addresses (a member reads
+// its root's entries, anything else its own), so they issue together.
+template <int B>
+__device__ inline uint64_t p_sum_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane,
+                                       const p_i4 (&cur)[B]) {
+  const MemoView& m = c.m;
+  int32_t raw[B][4];
   uint32_t word[B][4];
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
-    const int32_t vals[4] = {cur[b].x, cur[b].y, cur[b].z, cur[b].w};
-    uint32_t root[4];
+    const uint32_t q0 = min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int32_t val = vals[i];
-      const bool shared = q0 + i < m.R && val != -1;
-      root[i] = shared ? (val < 0 ? u : (uint32_t)val) : kInvalid;
-      size[b][i] = val < 0 ? -val : (shared ? -m.M[(uint64_t)val * m.Rs + q0 + i] : 0);
-    }
-    // the lane's four columns share one coverage word: load it once for
-    // every column whose component has the root of the first shared column
-    const uint32_t r0 = root[0] != kInvalid ? root[0] : root[1] != kInvalid ? root[1] : root[2] != kInvalid ? root[2] : root[3];
-    const uint32_t w0 = r0 != kInvalid ? ld32(&c.cov[(uint64_t)r0 * c.cwords + (q0 >> 5)]) : 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      word[b][i] = root[i] == kInvalid ? 0u : w0;  // a singleton (val -1) is never covered
-      if (root[i] != kInvalid && root[i] != r0) word[b][i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
+      const int32_t val = cur[b][i];
+      const uint32_t root = val < 0 ? u : (uint32_t)val;
+      raw[b][i] = ldg(m.M + (uint64_t)root * m.Rs + q0 + i);
+      word[b][i] = ld32(&c.cov[(uint64_t)root * c.cwords + (q0 >> 5)]);
     }
   }
   uint64_t sum = 0;
@@ -303,8 +335,13 @@ __device__ inline uint64_t p_eval_tiles(const CelfView& c, uint32_t u, uint32_t 
     const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
     if (t0 + b >= m.ntiles) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (q0 + i < m.R) sum += ((word[b][i] >> ((q0 + i) & 31)) & 1u) ? 0 : (uint64_t)size[b][i];
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t q = q0 + i;
+      const int32_t val = cur[b][i];
+      const bool covered = val != -1 && ((word[b][i] >> (q & 31)) & 1u);  // a singleton holds no seed
+      const uint64_t size = (uint64_t)(uint32_t)(-(val < 0 ? val : raw[b][i]));
+      sum += (q < m.R && !covered) ? size : 0;
+    }
   }
   return sum;
 }
@@ -362,10 +399,81 @@ __device__ void f_best(PoolLds& L) {
   __syncthreads();
 }
 
+// Restale of at most 64 F entries.  Wavefront 0 ranks F across its lanes
+// (keys are distinct: the rank of an entry is the number of larger keys,
+// read from the other lanes) and finds, by binary search, how many S entries
+// lie above each F entry: cg[rank], non-decreasing in the rank.  F entry of
+// rank r goes to r + cg[r] and S entry i to i + #{r : cg[r] <= i} (an F
+// entry precedes S entry i exactly when cg[r] <= i).
+__device__ void pool_restale_small(PoolLds& L, uint32_t nf, uint32_t head, uint32_t ns, PClock& clk) {
+  const uint32_t l = threadIdx.x;
+  uint64_t fk = 0;
+  uint32_t fv = kInvalid, fpos = kPool;
+  if (l < 64) {
+    fk = l < nf ? L.fkey[l] : 0;  // keys of unselected vertices are >= 1
+    fv = l < nf ? L.fid[l] : kInvalid;
+    const uint32_t hi = (uint32_t)(fk >> 32), lo = (uint32_t)fk;
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < nf; ++j) {
+      const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, (int)j) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)j);
+      rank += kj > fk ? 1u : 0u;
+    }
+    const uint32_t c = l < nf ? count_greater(L.skey + head, ns, fk) : kPool;
+    L.cg[l < nf ? rank : l] = c;  // lanes past nf pad the slots nf .. 63
+    fpos = l < nf ? rank + c : kPool;
+  }
+  clk.lap(PClock::kSort);
+  __syncthreads();
+  constexpr uint32_t kR = kPool / kPBlock;
+  uint64_t k[kR];
+  uint32_t v[kR], sh[kR];
+#pragma unroll
+  for (uint32_t j = 0; j < kR; ++j) {
+    const uint32_t i = threadIdx.x + j * kPBlock;
+    k[j] = i < ns ? L.skey[head + i] : 0;
+    v[j] = i < ns ? L.sid[head + i] : kInvalid;
+    sh[j] = 0;
+  }
+  // sh[j] = #{r : cg[r] <= i}: eight independent searches, one probe each per step
+#pragma unroll
+  for (uint32_t step = 32; step > 0; step >>= 1) {
+    uint32_t probe[kR];
+#pragma unroll
+    for (uint32_t j = 0; j < kR; ++j) probe[j] = L.cg[sh[j] + step - 1];
+#pragma unroll
+    for (uint32_t j = 0; j < kR; ++j) sh[j] += probe[j] <= threadIdx.x + j * kPBlock ? step : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t j = 0; j < kR; ++j) {
+    const uint32_t i = threadIdx.x + j * kPBlock;
+    if (i < ns) {
+      L.skey[i + sh[j]] = k[j];
+      L.sid[i + sh[j]] = v[j];
+    }
+  }
+  if (fpos < kPool) {
+    L.skey[fpos] = fk;
+    L.sid[fpos] = fv;
+  }
+  if (threadIdx.x == 0) {
+    L.ns = ns + nf;
+    L.head = 0;
+    L.nf = 0;
+  }
+  __syncthreads();
+  clk.lap(PClock::kMove);
+}
+
 // After a commit: F (without the seed) becomes stale and is merged into the
 // unconsumed part of S; S restarts at position 0.
-__device__ void pool_restale(PoolLds& L) {
+__device__ void pool_restale(PoolLds& L, PClock& clk) {
   const uint32_t nf = L.nf, head = L.head, ns = L.ns - head;
+  if (nf <= 64) {
+    pool_restale_small(L, nf, head, ns, clk);
+    return;
+  }
   // sort F descending (padding keys 0 sort last)
   const uint32_t np2 = next_pow2(nf);
   for (uint32_t i = nf + threadIdx.x; i < np2; i += kPBlock) {
@@ -412,7 +520,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
   PCelfScratch* x = a.x;
   const uint32_t n = c.m.n;
   const uint32_t gtid = G.bi * kPBlock + threadIdx.x, gstride = G.nb * kPBlock;
-  if (!grid_sync(x, G, gen, clk, PClock::kPoolOps)) return false;  // readers of the last staging are done
+  if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;  // readers of the last staging are done
   if (G.bi == 0) {
     for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
     if (threadIdx.x == 0) {
@@ -429,7 +537,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
     mx = k > mx ? k : mx;
   }
   mx = p_wmax(mx);
-  if ((threadIdx.x & 63) == 0 && mx) atomicMax((unsigned long long*)&x->kmax, (unsigned long long)mx);
+  if ((threadIdx.x & 63) == 0 && mx) g_max64(&x->kmax, mx);
   if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint64_t kmax = ld64(&x->kmax);
   if (kmax == 0) {  // nothing unselected: the caller reports it
@@ -467,7 +575,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock)
-      if (L.hist[i]) atomicAdd(&x->hist[i], L.hist[i]);
+      if (L.hist[i]) g_add(&x->hist[i], L.hist[i]);
     if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
     // bins from the top: thread t holds bins kBins-1-(kBPer*t .. kBPer*t+kBPer-1)
     constexpr uint32_t kBPer = kBins / kPBlock;
@@ -509,7 +617,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
       break;
     }
     if (L.shift == shift) {  // no lower digit (cannot happen: shift 0 always finishes)
-      if (threadIdx.x == 0) atomicOr(&x->err, 2u);
+      if (threadIdx.x == 0) g_or(&x->err, 2u);
       return false;
     }
     // clear the global histogram for the next digit once every reader is done
@@ -524,7 +632,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
     const uint64_t k = ld64(&c.key[v]);
     if (k == 0) continue;
     if (k >= thresh) {
-      const uint32_t at = atomicAdd(&x->pool_cnt, 1u);
+      const uint32_t at = g_add(&x->pool_cnt, 1u);
       if (at < kPool) {
         st32(&x->pool_id[at], v);
         st64(&x->pool_key[at], k);
@@ -535,11 +643,11 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
   }
   outside = p_wmax(outside);
   if ((threadIdx.x & 63) == 0 && outside)
-    atomicMax((unsigned long long*)&x->out_bound, (unsigned long long)outside);
+    g_max64(&x->out_bound, outside);
   if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint32_t cnt = ld32(&x->pool_cnt);
   if (cnt > kPool) {  // the threshold admits at most kPool keys
-    if (threadIdx.x == 0) atomicOr(&x->err, 2u);
+    if (threadIdx.x == 0) g_or(&x->err, 2u);
     return false;
   }
   // split into F (fresh: evaluated for this |S|) and S (stale, sorted)
@@ -605,7 +713,7 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
   const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   // the last commit's key store and the counter reset must be visible
   if (G.bi == 0 && threadIdx.x == 0) st32(&x->bulk_cnt, 0u);
-  if (!grid_sync(x, G, gen, clk, PClock::kPoolOps)) return false;
+  if (!grid_sync(x, G, gen, clk, PClock::kBulk)) return false;
   // 1. list the candidates (wave-aggregated slots)
   for (uint32_t base = gtid - lane; base < n; base += gstride) {
     const uint32_t v = base + lane;
@@ -617,7 +725,7 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
     const uint64_t mask = __ballot(take);
     if (!mask) continue;
     uint32_t slot0 = 0;
-    if (lane == 0) slot0 = atomicAdd(&x->bulk_cnt, (uint32_t)__popcll(mask));
+    if (lane == 0) slot0 = g_add(&x->bulk_cnt, (uint32_t)__popcll(mask));
     slot0 = __shfl(slot0, 0);
     if (take) {
       const uint32_t at = slot0 + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
@@ -626,17 +734,36 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
   }
   if (!grid_sync(x, G, gen, clk, PClock::kBulk)) return false;
   const uint32_t cnt = ld32(&x->bulk_cnt);
-  // 2. one wavefront per candidate: the gain over all tiles, four at a time;
-  // the keys are read by the rebuild that follows, after its barrier
+  // 2. one wavefront per candidate: the gain over all tiles, kB at a time;
+  // the keys are read by the rebuild that follows, after its barrier.  A
+  // wavefront's candidates are w = gw + j * nw; one load brings the ids of
+  // the next 64.  The row words of the next batch (the next candidate's
+  // first batch after the last one) are requested before the gathers of
+  // the current batch, so a batch costs one memory latency, not two.
   constexpr int kB = 4;
-  for (uint32_t w = gw; w < cnt; w += nw) {
-    const uint32_t v = p_uni(ld32(&a.blist[w]));
-    uint64_t sum = 0;
-    for (uint32_t t = 0; t < ntiles; t += kB) sum += p_eval_tiles<kB>(c, v, t, lane);
-    sum = p_wsum(sum);
-    if (lane == 0) {
-      st64(&c.key[v], p_make_key(c, sum, v));
-      st32(&c.iter[v], s);
+  for (uint32_t base = gw; base < cnt; base += 64 * nw) {
+    const uint32_t nloc = min(64u, (cnt - base + nw - 1) / nw);
+    const uint32_t ids = ld32(&a.blist[min(base + lane * nw, cnt - 1)]);
+    uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane(ids);
+    p_i4 nxt[kB];
+    p_load_tiles<kB>(c, v, 0, lane, nxt);
+    for (uint32_t j = 0; j < nloc; ++j) {
+      const uint32_t vn = (uint32_t)__builtin_amdgcn_readlane(ids, (int)min(j + 1, nloc - 1));
+      uint64_t sum = 0;
+      for (uint32_t t = 0; t < ntiles; t += kB) {
+        p_i4 cur[kB];
+#pragma unroll
+        for (int b = 0; b < kB; ++b) cur[b] = nxt[b];
+        const bool more = t + kB < ntiles;
+        p_load_tiles<kB>(c, more ? v : vn, more ? t + kB : 0, lane, nxt);
+        sum += p_sum_tiles<kB>(c, v, t, lane, cur);
+      }
+      sum = p_wsum(sum);
+      if (lane == 0) {
+        st64(&c.key[v], p_make_key(c, sum, v));
+        st32(&c.iter[v], s);
+      }
+      v = vn;
     }
   }
   evals += cnt;
@@ -655,13 +782,13 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, step_rebuilds = 0;
   uint64_t evals = 0;
   PClock clk;
-  clk.start();
-  const uint64_t t_start = clk.mark;
+  clk.start(a.prof != 0);
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   if (!pool_rebuild(a, G, L, s, gen, clk)) return;
   bool just_rebuilt = true;
   while (s < c.K) {
     if (__builtin_amdgcn_s_memrealtime() - t_start > kRunTicks) {
-      if (threadIdx.x == 0) atomicOr(&x->err, 4u);
+      if (threadIdx.x == 0) g_or(&x->err, 4u);
       return;
     }
     const uint32_t ns = L.ns, head = L.head, nf = L.nf;
@@ -674,15 +801,16 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       const uint32_t per = (c.m.R + G.nb - 1) / G.nb;
       const uint32_t q_lo = min(G.bi * per, c.m.R), q_hi = min(q_lo + per, c.m.R);
       for (uint32_t q = q_lo + threadIdx.x; q < q_hi; q += kPBlock) {
-        const int32_t val = c.m.M[(uint64_t)id * c.m.Rs + q];
+        const int32_t val = ldg(c.m.M + (uint64_t)id * c.m.Rs + q);
         const uint32_t root = val < 0 ? id : (uint32_t)val;
-        atomicOr(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
+        g_or(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
       }
       if (G.bi == 0 && threadIdx.x == 0) {
-        c.seeds[s] = id;
-        c.marginal[s] = (int64_t)(fbest >> c.B);
+        *gp(c.seeds + s) = id;  // global stores: a flat one would hold the LDS waits below
+        *gp(c.marginal + s) = (int64_t)(fbest >> c.B);
         st64(&c.key[id], 0ull);
       }
+      clk.lap(PClock::kCommit);
       __syncthreads();
       if (threadIdx.x == 0) {  // drop the seed from F
         const uint32_t b = L.fbest;
@@ -691,13 +819,13 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         L.nf = nf - 1;
       }
       __syncthreads();
-      pool_restale(L);
+      pool_restale(L, clk);
       last = id;
       ++s;
       rounds = 0;
       step_rebuilds = 0;
       just_rebuilt = false;
-      clk.lap(PClock::kPoolOps);
+      clk.lap(PClock::kRestale);
       continue;
     }
     if (stop > ob && stop > fbest) {
@@ -711,12 +839,12 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         uint64_t* nxt = x->gains[(ev_round + 1) % 3];
         for (uint32_t i = threadIdx.x; i < kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
       }
-      clk.lap(PClock::kPoolOps);
+      clk.lap(PClock::kPrep);
       const uint32_t items = nc * ntiles;
       for (uint32_t it = gw; it < items; it += nw) {
         const uint32_t w = it / ntiles, t = it - w * ntiles;
         const uint64_t part = p_wsum(p_eval_tile(c, L.sid[head + w], t, lane, last));
-        if (lane == 0 && part) atomicAdd((unsigned long long*)&g[w], (unsigned long long)part);
+        if (lane == 0 && part) g_add64(&g[w], part);
       }
       if (!grid_sync(x, G, gen, clk, PClock::kEval)) return;
       // move the evaluated entries from S to F
@@ -742,14 +870,14 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       ++ev_round;
       ++clk.rounds;
       just_rebuilt = false;
-      clk.lap(PClock::kPoolOps);
+      clk.lap(PClock::kPost);
       continue;
     }
     // ---- the pool cannot decide: the largest key is outside.  Refill the
     // pool; when that already happened in this step, first evaluate every
     // stale vertex above max F at once (a lower bound of this step's gain).
     if (just_rebuilt) {  // a fresh pool always decides
-      if (G.bi == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      if (G.bi == 0 && threadIdx.x == 0) g_or(&x->err, 2u);
       return;
     }
     if (nf && step_rebuilds > 0)
@@ -757,7 +885,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     ++step_rebuilds;
     if (L.ns == 0 && L.nf == 0) {  // no unselected vertex: cannot happen for K <= n
-      if (G.bi == 0 && threadIdx.x == 0) atomicOr(&x->err, 2u);
+      if (G.bi == 0 && threadIdx.x == 0) g_or(&x->err, 2u);
       return;
     }
     just_rebuilt = true;
@@ -767,9 +895,9 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     c.st->evals = evals;
     c.st->bulk_rounds = ev_round;
     for (int i = 0; i < PClock::kPhases; ++i) x->prof[i] = clk.acc[i];
-    x->prof[5] = clk.barriers;
-    x->prof[6] = clk.rounds;
-    x->prof[7] = ((uint64_t)clk.bulks << 32) | clk.rebuilds;
+    x->prof[12] = clk.barriers;
+    x->prof[13] = clk.rounds;
+    x->prof[14] = ((uint64_t)clk.bulks << 32) | clk.rebuilds;
   }
 }
 
@@ -842,12 +970,13 @@ static uint32_t pcelf_w0(const CelfView& c, uint32_t group_blocks, uint32_t roun
 }
 
 void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* blist, uint32_t group_blocks,
-                    uint32_t round0) {
+                    uint32_t round0, bool prof) {
   PCelfJob* j = static_cast<PCelfJob*>(host_job);
   j->c = c;
   j->x = static_cast<PCelfScratch*>(scratch);
   j->blist = blist;
   j->w0 = pcelf_w0(c, group_blocks, round0);
+  j->prof = prof ? 1u : 0u;
 }
 
 hipError_t launch_celf_persistent(const void* jobs, uint32_t njobs, uint32_t grid, uint32_t group_blocks,

@@ -533,7 +533,8 @@ bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_
 void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   celf_prepare(cb, st);
   if (c->tune.celf_mode == 1 && c->coop_grid) {
-    pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0);
+    pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0,
+                   c->profiling >= 2);
     if (hipMemcpyAsync(cb->pjob, cb->hjob, pcelf_job_bytes(), hipMemcpyHostToDevice, st) == hipSuccess &&
         celf_launch_persistent(c, cb->pjob, 1, c->coop_grid, nullptr, st)) {
       cb->persistent = true;
@@ -631,13 +632,15 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
   if (perr) return fail(IM_ERR_DEVICE, "persistent CELF kernel aborted (code %u)", perr);
   if (cb->persistent && c->profiling >= 2) {
     // phase clock of the persistent kernel: ticks of 10 ns per phase
-    uint64_t pr[8];
+    uint64_t pr[15];
     if (hipMemcpy(pr, static_cast<char*>(cb->pscratch) + pcelf_prof_offset(), sizeof(pr),
                   hipMemcpyDeviceToHost) == hipSuccess) {
       std::lock_guard<std::recursive_mutex> lk(c->mu);
-      const char* names[5] = {"celf.barrier", "celf.eval", "celf.pool", "celf.rebuild", "celf.bulk"};
-      const uint64_t counts[5] = {pr[5], pr[6], v.K, pr[7] & 0xFFFFFFFFu, pr[7] >> 32};
-      for (int i = 0; i < 5; ++i) {
+      const char* names[10] = {"celf.barrier", "celf.eval",    "celf.commit", "celf.restale", "celf.prep",
+                               "celf.post",    "celf.rebuild", "celf.bulk",   "celf.sort",    "celf.move"};
+      const uint64_t counts[10] = {pr[12], pr[13], v.K, v.K, pr[13], pr[13], pr[14] & 0xFFFFFFFFu, pr[14] >> 32,
+                                   v.K, v.K};
+      for (int i = 0; i < 10; ++i) {
         auto& e = c->kstats[names[i]];
         e.first += counts[i];
         e.second += pr[i] * 1e-5;
