@@ -41,9 +41,11 @@
 namespace infuse {
 
 // Hook of one tile: for each of the lane's columns, the smallest live
-// neighbour u < v (or -1), stored as one 16-byte write.  Returns whether the
-// tile has any candidate edge (tmask bit) and whether some column has two or
-// more live smaller neighbours (lmask bit).
+// neighbour u < v (or -1), stored as one 16-byte write when the tile has a
+// candidate edge at all; otherwise v is a singleton in every column of the
+// tile and nothing is written (readers consult tmask first).  Returns
+// whether the tile has any candidate edge (tmask bit) and whether some
+// column has two or more live smaller neighbours (lmask bit).
 template <bool PER_EDGE>
 __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t v, uint32_t beg, uint32_t end,
                                  uint32_t split, uint32_t lane, bool inreg, uint32_t rcol, uint32_t rh,
@@ -70,7 +72,7 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
   // streaming store: the row is not read again before the next kernel
   typedef int int4v __attribute__((ext_vector_type(4)));
   const int4v ov = {out.x, out.y, out.z, out.w};
-  __builtin_nontemporal_store(ov, reinterpret_cast<int4v*>(row + tc.q0));
+  if (any) __builtin_nontemporal_store(ov, reinterpret_cast<int4v*>(row + tc.q0));
   need = __ballot(cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1) != 0;
 }
 

@@ -109,7 +109,7 @@ __device__ void commit_block(const CelfView& c, uint64_t k) {
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       const uint32_t q = qb + b * blockDim.x + threadIdx.x;
-      vals[b] = q < m.R ? m.M[(uint64_t)id * m.Rs + q] : 0;
+      vals[b] = q < m.R ? memo_entry(m, id, q) : 0;
     }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {

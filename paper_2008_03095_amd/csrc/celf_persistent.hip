@@ -257,16 +257,23 @@ __device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t
 // This lane's share of gain(u | S) over tile t: the sizes of u's components
 // in the lane's four columns that hold no seed.  `last` is the most recent
 // seed (or kInvalid), whose coverage bits may not be visible yet: its
-// component is tested directly.  The row is read without consulting tmask
-// (a tile without its bit holds -1, a singleton, in every column), which
-// saves a dependent load on this latency-bound path.
+// component is tested directly.  The rows and their tmask words are loaded
+// together; a row word of a tile without its tmask bit is stale and reads
+// as -1 (a singleton), which saves a dependent load on this latency-bound
+// path.
 __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
                                        uint32_t last) {
   const MemoView& m = c.m;
   const uint32_t q0 = t * kTile + lane * kPerLane;
   const bool has_last = last != kInvalid;
-  const p_i4 cur = ldg4(m.M + (uint64_t)u * m.Rs + q0);
-  const p_i4 sl = ldg4(m.M + (uint64_t)(has_last ? last : u) * m.Rs + q0);
+  const uint32_t lu = has_last ? last : u;
+  const uint32_t ub = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
+  const uint32_t lb = ldg(m.tmask + (uint64_t)lu * m.mwords + (t >> 5));
+  const p_i4 ru = ldg4(m.M + (uint64_t)u * m.Rs + q0);
+  const p_i4 rl = ldg4(m.M + (uint64_t)lu * m.Rs + q0);
+  const p_i4 none = p_i4{-1, -1, -1, -1};
+  const p_i4 cur = ((ub >> (t & 31)) & 1u) ? ru : none;
+  const p_i4 sl = ((lb >> (t & 31)) & 1u) ? rl : none;
   // every load below has a valid address, so none waits behind a branch:
   // a member reads its root's entry, a root or singleton its own
   int32_t raw[4];
@@ -295,14 +302,16 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
 // Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
 // dividing 32; `bits` is u's tmask word shifted down to tile t0).  Tiles
 // without their bit, or past the row, read as singletons (-1) without a load.
-// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B).
-// Tiles past the row re-read the last tile (p_sum_tiles skips them), so the
-// number of loads in flight never depends on the data.  The row is read
-// whole: a tile without its tmask bit holds -1 (a singleton) in every
-// column, and almost every tile of a vertex worth re-evaluating has it.
+// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
+// dividing 32) and u's tmask word for them.  Every load is issued whatever
+// the mask says (tiles past the row re-read the last tile, which
+// p_sum_tiles skips), so the number of loads in flight never depends on the
+// data; p_sum_tiles reads a tile without its tmask bit as singletons.
 template <int B>
-__device__ inline void p_load_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane, p_i4 (&cur)[B]) {
+__device__ inline void p_load_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane, p_i4 (&cur)[B],
+                                    uint32_t& bits) {
   const MemoView& m = c.m;
+  bits = ldg(m.tmask + (uint64_t)u * m.mwords + (t0 >> 5));
 #pragma unroll
   for (int b = 0; b < B; ++b)
     cur[b] = ldg4(m.M + (uint64_t)u * m.Rs + min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane);
@@ -314,10 +323,13 @@ __device__ inline void p_load_tiles(const CelfView& c, uint32_t u, uint32_t t0, 
 // its root's entries, anything else its own), so they issue together.
 template <int B>
 __device__ inline uint64_t p_sum_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane,
-                                       const p_i4 (&cur)[B]) {
+                                       const p_i4 (&row)[B], uint32_t bits) {
   const MemoView& m = c.m;
   int32_t raw[B][4];
   uint32_t word[B][4];
+  p_i4 cur[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) cur[b] = ((bits >> ((t0 + b) & 31)) & 1u) ? row[b] : p_i4{-1, -1, -1, -1};
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const uint32_t q0 = min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane;
@@ -746,7 +758,8 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
     const uint32_t ids = ld32(&a.blist[min(base + lane * nw, cnt - 1)]);
     uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane(ids);
     p_i4 nxt[kB];
-    p_load_tiles<kB>(c, v, 0, lane, nxt);
+    uint32_t nbits;
+    p_load_tiles<kB>(c, v, 0, lane, nxt, nbits);
     for (uint32_t j = 0; j < nloc; ++j) {
       const uint32_t vn = (uint32_t)__builtin_amdgcn_readlane(ids, (int)min(j + 1, nloc - 1));
       uint64_t sum = 0;
@@ -754,9 +767,10 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
         p_i4 cur[kB];
 #pragma unroll
         for (int b = 0; b < kB; ++b) cur[b] = nxt[b];
+        const uint32_t bits = nbits;
         const bool more = t + kB < ntiles;
-        p_load_tiles<kB>(c, more ? v : vn, more ? t + kB : 0, lane, nxt);
-        sum += p_sum_tiles<kB>(c, v, t, lane, cur);
+        p_load_tiles<kB>(c, more ? v : vn, more ? t + kB : 0, lane, nxt, nbits);
+        sum += p_sum_tiles<kB>(c, v, t, lane, cur, bits);
       }
       sum = p_wsum(sum);
       if (lane == 0) {
@@ -801,7 +815,9 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       const uint32_t per = (c.m.R + G.nb - 1) / G.nb;
       const uint32_t q_lo = min(G.bi * per, c.m.R), q_hi = min(q_lo + per, c.m.R);
       for (uint32_t q = q_lo + threadIdx.x; q < q_hi; q += kPBlock) {
-        const int32_t val = ldg(c.m.M + (uint64_t)id * c.m.Rs + q);
+        const uint32_t t = q / kTile;
+        const int32_t raw = ldg(c.m.M + (uint64_t)id * c.m.Rs + q);
+        const int32_t val = ((ldg(c.m.tmask + (uint64_t)id * c.m.mwords + (t >> 5)) >> (t & 31)) & 1u) ? raw : -1;
         const uint32_t root = val < 0 ? id : (uint32_t)val;
         g_or(&c.cov[(uint64_t)root * c.cwords + (q >> 5)], 1u << (q & 31));
       }

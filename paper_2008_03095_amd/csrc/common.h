@@ -80,8 +80,10 @@ struct MemoView {
   uint32_t never_live;  // uniform mode with T = 0
   const uint2* edges;   // [nnz] {neighbour, h_e}
   const uint32_t* xs;   // [Rs] X of column q (ascending for q < R)
-  int32_t* M;           // [n][Rs]
+  int32_t* M;           // [n][Rs]; only tiles with their tmask bit are written
   uint32_t* tmask;      // [n][mwords]  tile may hold a non-singleton column
+                        //              (clear: v is a singleton in every column
+                        //              of the tile and its M words are stale)
   uint32_t* lmask;      // [n][mwords]  tile has a column with two or more
                         //              live smaller neighbours (needs k_link)
   int64_t* g0;          // [n]
@@ -94,6 +96,16 @@ struct MemoView {
   uint32_t* counts;     // [2 * j] = |tlist_j|, [2 * j + 1] = |llist_j|
   uint32_t list_cap;
 };
+
+// Memo entry of v in column q (see MemoView::M): -1 where v's tile has no
+// candidate edge, without trusting the unwritten word.  The row word is
+// loaded unconditionally so both loads issue together.
+__device__ inline int32_t memo_entry(const MemoView& m, uint32_t v, uint32_t q) {
+  const uint32_t t = q / kTile;
+  const int32_t val = m.M[(uint64_t)v * m.Rs + q];
+  const bool on = (m.tmask[(uint64_t)v * m.mwords + (t >> 5)] >> (t & 31)) & 1u;
+  return on ? val : -1;
+}
 
 constexpr uint32_t kHubPiece = 256;  // smaller neighbours of a hub per union wavefront
 constexpr uint32_t kSubLists = 256;

@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(64) k_sigma_pair(MemoView m, const uint32_t* S
   if (q < m.R) {
     for (uint32_t j = 0; j < len; ++j) {
       const uint32_t s = S[j];
-      const int32_t val = m.M[(uint64_t)s * m.Rs + q];
+      const int32_t val = memo_entry(m, s, q);
       const uint32_t root = val < 0 ? s : (uint32_t)val;
       const int32_t size = val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q];
       bool dup = false;
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(256) k_sigma_bitmap(MemoView m, const uint32_t
        i += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t j = (uint32_t)(i / m.R), q = (uint32_t)(i % m.R);
     const uint32_t s = S[j];
-    const int32_t val = m.M[(uint64_t)s * m.Rs + q];
+    const int32_t val = memo_entry(m, s, q);
     const uint32_t root = val < 0 ? s : (uint32_t)val;
     const uint32_t bit = 1u << (q & 31);
     const uint32_t old = atomicOr(&bm[(uint64_t)root * cwords + (q >> 5)], bit);
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) k_export(MemoView m, const uint32_t* pos,
     const uint32_t vv = (uint32_t)(i / cnt), k = (uint32_t)(i % cnt);
     const uint32_t v = v0 + vv;
     const uint32_t q = pos[r0 + k];
-    const int32_t val = m.M[(uint64_t)v * m.Rs + q];
+    const int32_t val = memo_entry(m, v, q);
     int32_t res;
     if (mode == 0) res = val < 0 ? (int32_t)v : val;
     else res = val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q];
