@@ -77,10 +77,13 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
 }
 
 // k_hook_rows: one wavefront per vertex with at most kWave neighbours (the
-// neighbour list sits in registers) writes the vertex's whole row, tile by
-// tile; the X values of the next tile are loaded before the current tile is
-// processed, so the wave waits on loads, not on its stores.  The wave owns
-// the vertex's mask words and stores them directly.
+// neighbour list sits in registers).  Per 32 tiles, the lanes first read the
+// X bounds of one tile each and the wavefront tests every tile's bounds
+// against all its edges (two lane reads, a compare and a ballot per tile):
+// the tiles with a candidate edge form the tmask word.  Only those tiles are
+// then hooked and written, the X values of the next one loaded before the
+// current one is processed.  The wave owns the vertex's mask words and
+// stores them directly.
 template <bool PER_EDGE>
 __global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
   const uint32_t v = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -89,33 +92,53 @@ __global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
   const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
   if (end - beg > (uint32_t)kWave) return;  // k_hook_hubs
   const uint32_t split = uni(g.split[v]);
+  const bool has = beg + lane < end;
   uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
-  if (beg + lane < end) {
+  if (has) {
     const uint2 e = m.edges[beg + lane];
     rcol = e.x;
     rh = e.y;
     if (PER_EDGE) rtm1 = g.tm1[beg + lane];
   }
+  const uint32_t kb = PER_EDGE ? bitlen32(rtm1) : m.kshift;
+  const uint32_t hk = (uint32_t)((uint64_t)rh >> kb);
   int32_t* row = m.M + (uint64_t)v * m.Rs;
   uint32_t* tw = m.tmask + (uint64_t)v * m.mwords;
   uint32_t* lw = m.lmask + (uint64_t)v * m.mwords;
-  uint4 xn = load_tile_x(m, 0, lane);
-  uint32_t tbits = 0, lbits = 0;
-  for (uint32_t t = 0; t < m.ntiles; ++t) {
-    const uint4 xc = xn;
-    if (t + 1 < m.ntiles) xn = load_tile_x(m, t + 1, lane);
-    TileCtx tc;
-    tile_from_x(m, t, lane, xc, m.kshift, tc, PER_EDGE);
-    bool any, need;
-    hook_tile<PER_EDGE>(g, m, v, beg, end, split, lane, true, rcol, rh, rtm1, tc, row, any, need);
-    tbits |= (any ? 1u : 0u) << (t & 31);
-    lbits |= (need ? 1u : 0u) << (t & 31);
-    if ((t & 31) == 31 || t + 1 == m.ntiles) {
-      if (lane == 0) {
-        tw[t >> 5] = tbits;
-        lw[t >> 5] = lbits;
+  for (uint32_t w = 0; w < m.mwords; ++w) {
+    const uint32_t t0 = w * 32, nt = min(32u, m.ntiles - t0);
+    // X of the first and of the last used column of tile t0 + lane
+    uint32_t xlo = 0, xhi = 0;
+    if (lane < nt) {
+      const uint32_t t = t0 + lane;
+      xlo = m.xs[t * kTile];
+      xhi = m.xs[min(t * kTile + kTile - 1, m.R - 1)];
+    }
+    uint32_t cm = 0;
+    if (!m.never_live) {
+      for (uint32_t i = 0; i < nt; ++i) {
+        const uint32_t lo = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)xlo, (int)i) >> kb);
+        const uint32_t hi = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)xhi, (int)i) >> kb);
+        cm |= (__ballot(has && hk - lo <= hi - lo) != 0 ? 1u : 0u) << i;
       }
-      tbits = lbits = 0;
+    }
+    uint32_t lbits = 0;
+    uint32_t rem = cm;
+    uint4 xn = load_tile_x(m, t0 + (rem ? (uint32_t)__builtin_ctz(rem) : 0u), lane);
+    while (rem) {
+      const uint32_t t = t0 + (uint32_t)__builtin_ctz(rem);
+      rem &= rem - 1;
+      const uint4 xc = xn;
+      xn = load_tile_x(m, t0 + (rem ? (uint32_t)__builtin_ctz(rem) : 0u), lane);
+      TileCtx tc;
+      tile_from_x(m, t, lane, xc, m.kshift, tc, PER_EDGE);
+      bool any, need;
+      hook_tile<PER_EDGE>(g, m, v, beg, end, split, lane, true, rcol, rh, rtm1, tc, row, any, need);
+      lbits |= (need ? 1u : 0u) << (t & 31);
+    }
+    if (lane == 0) {
+      tw[w] = cm;
+      lw[w] = lbits;
     }
   }
 }
