@@ -330,6 +330,24 @@ __device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, in
   return it;
 }
 
+// A wavefront's entries of a work list, 64 at a time: the entries of the
+// wavefront are first + k * stride (k = 0, 1, ...); lane l resolves entry
+// k0 + l of them.  `count` receives how many of the 64 exist (a prefix of
+// the lanes).  One load brings 64 entries, so the per-entry work that
+// follows does not wait for the list.
+__device__ inline uint32_t list_chunk(const ListIter& it, uint32_t k0, uint32_t lane, uint32_t& count) {
+  const uint64_t idx = (uint64_t)it.first + (uint64_t)(k0 + lane) * it.stride;
+  const bool ok = idx < it.total;
+  count = (uint32_t)__popcll(__ballot(ok));
+  return ok ? it.at((uint32_t)idx) : 0u;
+}
+
+// Row words of entry e (vertex e / ntiles, tile e % ntiles) for this lane.
+__device__ inline int4 list_row(const MemoView& m, uint32_t e, uint32_t lane) {
+  const uint32_t v = e / m.ntiles, t = e % m.ntiles;
+  return *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + t * kTile + lane * kPerLane);
+}
+
 template <bool PER_EDGE>
 __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
   const uint32_t lane = threadIdx.x & 63;
@@ -425,39 +443,48 @@ __global__ void __launch_bounds__(256) k_flatten(MemoView m) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
   const ListIter it = list_iter(m, m.tlist, 0, pre);
-  for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
-    const uint32_t e = uni(it.at(idx));
-    const uint32_t v = e / m.ntiles, t = e % m.ntiles;
-    int32_t* row = m.M + (uint64_t)v * m.Rs;
-    const uint32_t q0 = t * kTile + lane * kPerLane;
-    const int4 cur = *reinterpret_cast<const int4*>(row + q0);
-    int4 out = cur;
-    int32_t* o = &out.x;
-    uint32_t c[4];
-    bool act[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      act[i] = q0 + i < m.R && o[i] >= 0;
-      c[i] = act[i] ? (uint32_t)o[i] : 0u;
-    }
-    while (act[0] || act[1] || act[2] || act[3]) {
-      int32_t p[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) p[i] = act[i] ? m.M[(uint64_t)c[i] * m.Rs + q0 + i] : -1;
+  for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
+    uint32_t cnt;
+    const uint32_t ent = list_chunk(it, k0, lane, cnt);
+    // the next entry's row is requested before the current one is walked
+    uint32_t e = uni(__builtin_amdgcn_readfirstlane(ent));
+    int4 nrow = list_row(m, e, lane);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t ec = e;
+      const int4 cur = nrow;
+      e = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(j + 1, cnt - 1));
+      nrow = list_row(m, e, lane);
+      const uint32_t v = ec / m.ntiles, t = ec % m.ntiles;
+      int32_t* row = m.M + (uint64_t)v * m.Rs;
+      const uint32_t q0 = t * kTile + lane * kPerLane;
+      int4 out = cur;
+      int32_t* o = &out.x;
+      uint32_t c[4];
+      bool act[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        if (act[i] && p[i] >= 0) c[i] = (uint32_t)p[i];
-        else act[i] = false;
+        act[i] = q0 + i < m.R && o[i] >= 0;
+        c[i] = act[i] ? (uint32_t)o[i] : 0u;
       }
-    }
-    bool changed = false;
+      while (act[0] || act[1] || act[2] || act[3]) {
+        int32_t p[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (q0 + i < m.R && o[i] >= 0 && c[i] != (uint32_t)o[i]) {
-        o[i] = (int32_t)c[i];
-        changed = true;
+        for (int i = 0; i < 4; ++i) p[i] = act[i] ? m.M[(uint64_t)c[i] * m.Rs + q0 + i] : -1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (act[i] && p[i] >= 0) c[i] = (uint32_t)p[i];
+          else act[i] = false;
+        }
       }
-    if (changed) *reinterpret_cast<int4*>(row + q0) = out;
+      bool changed = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (q0 + i < m.R && o[i] >= 0 && c[i] != (uint32_t)o[i]) {
+          o[i] = (int32_t)c[i];
+          changed = true;
+        }
+      if (changed) *reinterpret_cast<int4*>(row + q0) = out;
+    }
   }
 }
 
@@ -528,21 +555,34 @@ __global__ void __launch_bounds__(256) k_gain0(MemoView m) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
   const ListIter it = list_iter(m, m.tlist, 0, pre);
-  for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
-    const uint32_t e = uni(it.at(idx));
-    const uint32_t v = e / m.ntiles, t = e % m.ntiles;
-    const uint32_t q0 = t * kTile + lane * kPerLane;
-    const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + q0);
-    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
-    int32_t sz[4];
+  for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
+    uint32_t cnt;
+    const uint32_t ent = list_chunk(it, k0, lane, cnt);
+    // the next entry's row is requested before the current one's root
+    // sizes are gathered; every gather has a valid address (a root or a
+    // singleton reads its own entry), so none waits behind a branch
+    uint32_t e = uni(__builtin_amdgcn_readfirstlane(ent));
+    int4 nrow = list_row(m, e, lane);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t ec = e;
+      const int4 cur = nrow;
+      e = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(j + 1, cnt - 1));
+      nrow = list_row(m, e, lane);
+      const uint32_t v = ec / m.ntiles, t = ec % m.ntiles;
+      const uint32_t q0 = t * kTile + lane * kPerLane;
+      const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+      int32_t raw[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int32_t val = vals[i];
-      sz[i] = (q0 + i >= m.R) ? 1 : (val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q0 + i]);
+      for (int i = 0; i < 4; ++i) raw[i] = m.M[(uint64_t)(vals[i] >= 0 ? (uint32_t)vals[i] : v) * m.Rs + q0 + i];
+      uint64_t sum = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t sz = vals[i] < 0 ? -vals[i] : -raw[i];
+        sum += (q0 + i < m.R) ? (uint64_t)(sz - 1) : 0;
+      }
+      sum = wave_sum_u64(sum);
+      if (lane == 0 && sum) atomicAdd((unsigned long long*)&m.g0[v], (unsigned long long)sum);
     }
-    uint64_t sum = (uint64_t)(sz[0] - 1) + (uint64_t)(sz[1] - 1) + (uint64_t)(sz[2] - 1) + (uint64_t)(sz[3] - 1);
-    sum = wave_sum_u64(sum);
-    if (lane == 0 && sum) atomicAdd((unsigned long long*)&m.g0[v], (unsigned long long)sum);
   }
 }
 
