@@ -392,14 +392,14 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = g.m * R * args.steps / dt
     # roofline kernel: the persistent CELF kernel (one launch per step, the
-    # largest share of the step).  Each evaluation of a candidate reads its
-    # label in all R samples (4 bytes each), and so does each commit; the
-    # component-size and coverage lookups that follow are gathers served
-    # mostly from cache and are not counted.
+    # largest share of the step).  Per evaluation of a candidate (and per
+    # commit) the method reads the vertex's label in all R samples, gathers
+    # the size of each labelled component and reads one coverage bit per
+    # sample: 4R + 4R + R/8 bytes.
     roof_n, roof_ms = ctx.kernel_stats("celf")
     roof_avg = roof_ms / roof_n if roof_n else None
     evals = G.celf_evals()
-    alg_bytes = 4 * R * (evals + K)
+    alg_bytes = (8 * R + R // 8) * (evals + K)
     achieved = alg_bytes / (roof_avg * 1e-3) / 1e9 if roof_avg else None
     traffic = read_traffic()
     phases /= args.steps

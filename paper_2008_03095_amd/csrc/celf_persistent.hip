@@ -302,37 +302,58 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
 // Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
 // dividing 32; `bits` is u's tmask word shifted down to tile t0).  Tiles
 // without their bit, or past the row, read as singletons (-1) without a load.
-// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
-// dividing 32) and u's tmask word for them.  Every load is issued whatever
-// the mask says (tiles past the row re-read the last tile, which
-// p_sum_tiles skips), so the number of loads in flight never depends on the
-// data; p_sum_tiles reads a tile without its tmask bit as singletons.
-template <int B>
-__device__ inline void p_load_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane, p_i4 (&cur)[B],
-                                    uint32_t& bits) {
-  const MemoView& m = c.m;
-  bits = ldg(m.tmask + (uint64_t)u * m.mwords + (t0 >> 5));
+// The bulk pass visits a candidate's tiles in batches of kBulkB.  With one
+// mask word per vertex (Rs <= 8192) only the tiles with their tmask bit are
+// visited and the others (singletons only) are counted in closed form;
+// otherwise every tile is visited.  tl[b] == kInvalid marks an empty slot.
+constexpr int kBulkB = 4;
+__device__ inline uint32_t p_tile_or0(uint32_t t) { return t == kInvalid ? 0u : t; }
+
+// Takes the next kBulkB tiles of a candidate: the lowest set bits of `rem`
+// (sparse) or the tiles pos, pos + 1, ... (dense).  Scalar work only.
+__device__ inline void p_take_tiles(bool sparse, uint32_t ntiles, uint32_t& rem, uint32_t& pos,
+                                    uint32_t (&tl)[kBulkB]) {
 #pragma unroll
-  for (int b = 0; b < B; ++b)
-    cur[b] = ldg4(m.M + (uint64_t)u * m.Rs + min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane);
+  for (int b = 0; b < kBulkB; ++b) {
+    if (sparse) {
+      tl[b] = rem ? (uint32_t)__builtin_ctz(rem) : kInvalid;
+      rem &= rem - 1;
+    } else {
+      tl[b] = pos < ntiles ? pos : kInvalid;
+      ++pos;
+    }
+  }
 }
 
-// This lane's share of gain(u | S) over the B tiles at t0 whose row words
-// p_load_tiles fetched.  Coverage is read from the bitmap only, so every
-// commit must be visible.  All loads have valid addresses (a member reads
-// its root's entries, anything else its own), so they issue together.
-template <int B>
-__device__ inline uint64_t p_sum_tiles(const CelfView& c, uint32_t u, uint32_t t0, uint32_t lane,
-                                       const p_i4 (&row)[B], uint32_t bits) {
+// Row words of u for the tiles tl and u's tmask word for them (the tiles of
+// a batch share one word).  Every load is issued whatever the tiles are, so
+// the number of loads in flight never depends on the data.
+__device__ inline void p_load_list(const CelfView& c, uint32_t u, const uint32_t (&tl)[kBulkB], uint32_t lane,
+                                   p_i4 (&cur)[kBulkB], uint32_t& word) {
   const MemoView& m = c.m;
-  int32_t raw[B][4];
-  uint32_t word[B][4];
-  p_i4 cur[B];
+  word = ldg(m.tmask + (uint64_t)u * m.mwords + (p_tile_or0(tl[0]) >> 5));
 #pragma unroll
-  for (int b = 0; b < B; ++b) cur[b] = ((bits >> ((t0 + b) & 31)) & 1u) ? row[b] : p_i4{-1, -1, -1, -1};
+  for (int b = 0; b < kBulkB; ++b)
+    cur[b] = ldg4(m.M + (uint64_t)u * m.Rs + p_tile_or0(tl[b]) * kTile + lane * kPerLane);
+}
+
+// This lane's share of gain(u | S) over the tiles tl whose row words
+// p_load_list fetched; a tile without its tmask bit reads as singletons.
+// Coverage is read from the bitmap only, so every commit must be visible.
+// All loads have valid addresses (a member reads its root's entries,
+// anything else its own), so they issue together.
+__device__ inline uint64_t p_sum_list(const CelfView& c, uint32_t u, const uint32_t (&tl)[kBulkB], uint32_t lane,
+                                      const p_i4 (&row)[kBulkB], uint32_t tword) {
+  const MemoView& m = c.m;
+  int32_t raw[kBulkB][4];
+  uint32_t word[kBulkB][4];
+  p_i4 cur[kBulkB];
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const uint32_t q0 = min(t0 + b, m.ntiles - 1) * kTile + lane * kPerLane;
+  for (int b = 0; b < kBulkB; ++b)
+    cur[b] = (tl[b] != kInvalid && ((tword >> (tl[b] & 31)) & 1u)) ? row[b] : p_i4{-1, -1, -1, -1};
+#pragma unroll
+  for (int b = 0; b < kBulkB; ++b) {
+    const uint32_t q0 = p_tile_or0(tl[b]) * kTile + lane * kPerLane;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int32_t val = cur[b][i];
@@ -343,9 +364,9 @@ __device__ inline uint64_t p_sum_tiles(const CelfView& c, uint32_t u, uint32_t t
   }
   uint64_t sum = 0;
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const uint32_t q0 = (t0 + b) * kTile + lane * kPerLane;
-    if (t0 + b >= m.ntiles) continue;
+  for (int b = 0; b < kBulkB; ++b) {
+    if (tl[b] == kInvalid) continue;
+    const uint32_t q0 = tl[b] * kTile + lane * kPerLane;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t q = q0 + i;
@@ -752,32 +773,61 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
   // the next 64.  The row words of the next batch (the next candidate's
   // first batch after the last one) are requested before the gathers of
   // the current batch, so a batch costs one memory latency, not two.
-  constexpr int kB = 4;
+  const MemoView& m = c.m;
+  const bool sparse = m.mwords == 1;
   for (uint32_t base = gw; base < cnt; base += 64 * nw) {
     const uint32_t nloc = min(64u, (cnt - base + nw - 1) / nw);
     const uint32_t ids = ld32(&a.blist[min(base + lane * nw, cnt - 1)]);
+    const uint32_t tws = ldg(m.tmask + (uint64_t)ids * m.mwords);  // word 0 of each lane's candidate
     uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane(ids);
-    p_i4 nxt[kB];
-    uint32_t nbits;
-    p_load_tiles<kB>(c, v, 0, lane, nxt, nbits);
+    uint32_t vb = (uint32_t)__builtin_amdgcn_readfirstlane(tws);
+    uint32_t rem = vb, pos = 0;
+    uint32_t nt[kBulkB];
+    p_i4 nxt[kBulkB];
+    uint32_t nword;
+    p_take_tiles(sparse, ntiles, rem, pos, nt);
+    p_load_list(c, v, nt, lane, nxt, nword);
     for (uint32_t j = 0; j < nloc; ++j) {
-      const uint32_t vn = (uint32_t)__builtin_amdgcn_readlane(ids, (int)min(j + 1, nloc - 1));
-      uint64_t sum = 0;
-      for (uint32_t t = 0; t < ntiles; t += kB) {
-        p_i4 cur[kB];
-#pragma unroll
-        for (int b = 0; b < kB; ++b) cur[b] = nxt[b];
-        const uint32_t bits = nbits;
-        const bool more = t + kB < ntiles;
-        p_load_tiles<kB>(c, more ? v : vn, more ? t + kB : 0, lane, nxt, nbits);
-        sum += p_sum_tiles<kB>(c, v, t, lane, cur, bits);
+      const int jn = (int)min(j + 1, nloc - 1);
+      const uint32_t vn = (uint32_t)__builtin_amdgcn_readlane(ids, jn);
+      const uint32_t vnb = (uint32_t)__builtin_amdgcn_readlane(tws, jn);
+      // batches of v; in the sparse case its unvisited tiles hold R minus the
+      // visited tiles' columns of singletons, each of gain 1
+      const uint32_t nbat = sparse ? max(1u, ((uint32_t)__builtin_popcount(vb) + kBulkB - 1) / kBulkB)
+                                   : (ntiles + kBulkB - 1) / kBulkB;
+      uint64_t singles = 0;
+      if (sparse) {
+        const uint32_t lastpad = ((vb >> (ntiles - 1)) & 1u) ? ntiles * kTile - m.R : 0u;
+        singles = (uint64_t)(m.R - ((uint32_t)__builtin_popcount(vb) * kTile - lastpad));
       }
-      sum = p_wsum(sum);
+      uint32_t nrem = vnb, npos = 0;
+      uint64_t sum = 0;
+      for (uint32_t i = 0; i < nbat; ++i) {
+        uint32_t ct[kBulkB];
+        p_i4 cur[kBulkB];
+#pragma unroll
+        for (int b = 0; b < kBulkB; ++b) {
+          ct[b] = nt[b];
+          cur[b] = nxt[b];
+        }
+        const uint32_t cword = nword;
+        const bool more = i + 1 < nbat;
+        if (more)
+          p_take_tiles(sparse, ntiles, rem, pos, nt);
+        else
+          p_take_tiles(sparse, ntiles, nrem, npos, nt);
+        p_load_list(c, more ? v : vn, nt, lane, nxt, nword);
+        sum += p_sum_list(c, v, ct, lane, cur, cword);
+      }
+      sum = p_wsum(sum) + singles;
       if (lane == 0) {
         st64(&c.key[v], p_make_key(c, sum, v));
         st32(&c.iter[v], s);
       }
       v = vn;
+      vb = vnb;
+      rem = nrem;
+      pos = npos;
     }
   }
   evals += cnt;
