@@ -410,7 +410,7 @@ def main():
              "celf_topw", "celf_eval", "celf_bulk"]
     if args.profile_celf:
         names += ["celf.barrier", "celf.eval", "celf.commit", "celf.restale", "celf.prep", "celf.post",
-                  "celf.rebuild", "celf.bulk", "celf.sort", "celf.move"]
+                  "celf.rebuild", "celf.bulk", "celf.sort", "celf.move", "celf.lookahead_commits"]
     stats = {k: ctx.kernel_stats(k) for k in names}
     rec = {
         "metric": METRIC,

@@ -40,6 +40,7 @@ constexpr uint32_t kPool = 2048;               // pool entries per workgroup
 constexpr uint32_t kPBlock = 256;              // threads per workgroup
 constexpr uint32_t kPer = kPool / kPBlock;     // pool entries per thread
 constexpr uint32_t kMaxCand = 1024;            // evaluations per round
+constexpr uint32_t kAheadMax = 64;             // largest round that also measures overlaps with its lead
 constexpr uint32_t kGroups = 16;               // barrier arrival groups
 constexpr uint32_t kDigitBits = 11;
 constexpr uint32_t kBins = 1u << kDigitBits;
@@ -59,7 +60,7 @@ struct PCelfScratch {
   alignas(128) uint32_t arrive[kGroups][32];  // one 128-byte line per group
   uint32_t top[32];
   uint32_t release[kGroups][32];
-  uint64_t gains[3][kMaxCand];        // per-round candidate gains, rotated
+  uint64_t gains[3][2 * kMaxCand];    // per-round candidate gains, then overlaps with the lead; rotated
   uint32_t hist[kBins];
   uint32_t pool_id[kPool];
   uint64_t pool_key[kPool];
@@ -145,11 +146,11 @@ struct PClock {
          kSort = 8, kMove = 9, kPhases = 10 };
   uint64_t acc[kPhases];
   uint64_t mark;
-  uint32_t barriers, rounds, rebuilds, bulks;
+  uint32_t barriers, rounds, rebuilds, bulks, ahead;
   bool on;
   __device__ void start(bool enable) {
     for (int i = 0; i < kPhases; ++i) acc[i] = 0;
-    barriers = rounds = rebuilds = bulks = 0;
+    barriers = rounds = rebuilds = bulks = ahead = 0;
     on = enable;
     mark = on ? __builtin_amdgcn_s_memrealtime() : 0;
   }
@@ -170,6 +171,8 @@ struct PoolLds {
   uint64_t wmax[kPBlock / 64];
   uint32_t hist[kBins];
   uint32_t cg[64];               // restale of a small F: S entries above each F entry
+  uint64_t fnext[kAheadMax];     // look-ahead: key of F entry i once lead is a seed
+  uint32_t lead;                 // look-ahead: leading candidate of the last round, or kInvalid
   uint32_t ns, head, nf, fbest;  // S size, S front, F size, index of max F
   uint64_t out_bound;
   uint64_t prefix;
@@ -257,23 +260,32 @@ __device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t
 // This lane's share of gain(u | S) over tile t: the sizes of u's components
 // in the lane's four columns that hold no seed.  `last` is the most recent
 // seed (or kInvalid), whose coverage bits may not be visible yet: its
-// component is tested directly.  The rows and their tmask words are loaded
+// component is tested directly, and so is prev's, the seed before it, when
+// no grid barrier has passed since its commit (kInvalid otherwise).  `overlap` receives the part of the share
+// that lies in components of `lead` (the round's leading candidate): what
+// u would lose if lead became the next seed.  The rows and their tmask words are loaded
 // together; a row word of a tile without its tmask bit is stale and reads
 // as -1 (a singleton), which saves a dependent load on this latency-bound
 // path.
 __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
-                                       uint32_t last) {
+                                       uint32_t last, uint32_t prev, uint32_t lead, uint64_t& overlap) {
   const MemoView& m = c.m;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  const bool has_last = last != kInvalid;
-  const uint32_t lu = has_last ? last : u;
+  const bool has_last = last != kInvalid, has_prev = prev != kInvalid;
+  const uint32_t lu = has_last ? last : u, pu = has_prev ? prev : u;
   const uint32_t ub = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
   const uint32_t lb = ldg(m.tmask + (uint64_t)lu * m.mwords + (t >> 5));
+  const uint32_t pb = ldg(m.tmask + (uint64_t)pu * m.mwords + (t >> 5));
+  const uint32_t db = ldg(m.tmask + (uint64_t)lead * m.mwords + (t >> 5));
   const p_i4 ru = ldg4(m.M + (uint64_t)u * m.Rs + q0);
   const p_i4 rl = ldg4(m.M + (uint64_t)lu * m.Rs + q0);
+  const p_i4 rp = ldg4(m.M + (uint64_t)pu * m.Rs + q0);
+  const p_i4 rd = ldg4(m.M + (uint64_t)lead * m.Rs + q0);
   const p_i4 none = p_i4{-1, -1, -1, -1};
   const p_i4 cur = ((ub >> (t & 31)) & 1u) ? ru : none;
   const p_i4 sl = ((lb >> (t & 31)) & 1u) ? rl : none;
+  const p_i4 sp = ((pb >> (t & 31)) & 1u) ? rp : none;
+  const p_i4 sd = ((db >> (t & 31)) & 1u) ? rd : none;
   // every load below has a valid address, so none waits behind a branch:
   // a member reads its root's entry, a root or singleton its own
   int32_t raw[4];
@@ -285,23 +297,26 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
     raw[i] = ldg(m.M + (uint64_t)root[i] * m.Rs + q0 + i);
     word[i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
   }
-  uint64_t sum = 0;
+  uint64_t sum = 0, ov = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t q = q0 + i;
     const int32_t val = cur[i];
     const uint32_t lroot = sl[i] < 0 ? last : (uint32_t)sl[i];
+    const uint32_t proot = sp[i] < 0 ? prev : (uint32_t)sp[i];
+    const uint32_t droot = sd[i] < 0 ? lead : (uint32_t)sd[i];
     const bool shared = val != -1;  // a singleton holds no seed
-    const bool covered = shared && (((word[i] >> (q & 31)) & 1u) || (has_last && lroot == root[i]));
+    const bool covered = shared && (((word[i] >> (q & 31)) & 1u) || (has_last && lroot == root[i]) ||
+                                    (has_prev && proot == root[i]));
     const uint64_t size = (uint64_t)(uint32_t)(-(val < 0 ? val : raw[i]));
-    sum += (q < m.R && !covered) ? size : 0;
+    const bool counted = q < m.R && !covered;
+    sum += counted ? size : 0;
+    ov += (counted && shared && droot == root[i]) ? size : 0;
   }
+  overlap = ov;
   return sum;
 }
 
-// Row words of u for the B tiles t0 .. t0 + B - 1 (t0 a multiple of B, B
-// dividing 32; `bits` is u's tmask word shifted down to tile t0).  Tiles
-// without their bit, or past the row, read as singletons (-1) without a load.
 // The bulk pass visits a candidate's tiles in batches of kBulkB.  With one
 // mask word per vertex (Rs <= 8192) only the tiles with their tmask bit are
 // visited and the others (singletons only) are counted in closed form;
@@ -843,11 +858,13 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   const uint32_t nw = G.nb * (kPBlock / 64);
   const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   const uint32_t ntiles = c.m.ntiles;
-  uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, step_rebuilds = 0;
+  uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, prev = kInvalid, step_rebuilds = 0;
+  bool synced = true;  // a grid barrier has passed since the last commit
   uint64_t evals = 0;
   PClock clk;
   clk.start(a.prof != 0);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  if (threadIdx.x == 0) L.lead = kInvalid;
   if (!pool_rebuild(a, G, L, s, gen, clk)) return;
   bool just_rebuilt = true;
   while (s < c.K) {
@@ -876,17 +893,39 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         *gp(c.marginal + s) = (int64_t)(fbest >> c.B);
         st64(&c.key[id], 0ull);
       }
+      // look-ahead: every F entry came from the round led by id, which
+      // measured each one's overlap with id
+      const bool ahead = L.lead == id;
       clk.lap(PClock::kCommit);
       __syncthreads();
       if (threadIdx.x == 0) {  // drop the seed from F
         const uint32_t b = L.fbest;
         L.fkey[b] = L.fkey[nf - 1];
         L.fid[b] = L.fid[nf - 1];
+        if (ahead) L.fnext[b] = L.fnext[nf - 1];  // nf <= kAheadMax here
         L.nf = nf - 1;
+        L.lead = kInvalid;
       }
       __syncthreads();
-      pool_restale(L, clk);
+      if (ahead) {
+        // the keys for the next step are exact: F stays fresh, S unchanged
+        for (uint32_t i = threadIdx.x; i + 1 < nf; i += kPBlock) {
+          const uint64_t k = L.fnext[i];
+          L.fkey[i] = k;
+          if (G.bi == 0) {
+            st64(&c.key[L.fid[i]], k);
+            st32(&c.iter[L.fid[i]], s + 1);
+          }
+        }
+        __syncthreads();
+        f_best(L);
+        ++clk.ahead;
+      } else {
+        pool_restale(L, clk);
+      }
+      prev = synced ? kInvalid : last;  // a look-ahead commit follows the last one without a barrier
       last = id;
+      synced = false;
       ++s;
       rounds = 0;
       step_rebuilds = 0;
@@ -900,25 +939,37 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       uint32_t nc = min(want, ns - head);
       if (fbest) nc = min(nc, count_greater(L.skey + head, nc, fbest));
       nc = min(nc, kPool - nf);
+      // look-ahead when F is empty: the round also measures each candidate's
+      // overlap with the leading (largest stale) candidate, so that if the
+      // lead wins, the others' keys for the next step are known exactly
+      const bool ahead = nf == 0 && nc <= kAheadMax;
+      const uint32_t lead = L.sid[head];
       uint64_t* g = x->gains[ev_round % 3];
       if (G.bi == 0) {
         uint64_t* nxt = x->gains[(ev_round + 1) % 3];
-        for (uint32_t i = threadIdx.x; i < kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
+        for (uint32_t i = threadIdx.x; i < 2 * kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
       }
       clk.lap(PClock::kPrep);
       const uint32_t items = nc * ntiles;
       for (uint32_t it = gw; it < items; it += nw) {
         const uint32_t w = it / ntiles, t = it - w * ntiles;
-        const uint64_t part = p_wsum(p_eval_tile(c, L.sid[head + w], t, lane, last));
+        const uint32_t u = L.sid[head + w];
+        uint64_t ov;
+        const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, ahead ? lead : u, ov));
+        ov = ahead ? p_wsum(ov) : 0;
         if (lane == 0 && part) g_add64(&g[w], part);
+        if (lane == 0 && ov) g_add64(&g[kMaxCand + w], ov);
       }
       if (!grid_sync(x, G, gen, clk, PClock::kEval)) return;
+      synced = true;  // every commit so far is visible in the coverage bitmap
       // move the evaluated entries from S to F
       for (uint32_t w = threadIdx.x; w < nc; w += kPBlock) {
         const uint32_t v = L.sid[head + w];
-        const uint64_t k = p_make_key(c, ld64(&g[w]), v);
+        const uint64_t gain = ld64(&g[w]);
+        const uint64_t k = p_make_key(c, gain, v);
         L.fkey[nf + w] = k;
         L.fid[nf + w] = v;
+        if (ahead) L.fnext[w] = p_make_key(c, gain - ld64(&g[kMaxCand + w]), v);
         if (G.bi == 0) {
           st64(&c.key[v], k);
           st32(&c.iter[v], s);
@@ -928,6 +979,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       if (threadIdx.x == 0) {
         L.head = head + nc;
         L.nf = nf + nc;
+        L.lead = ahead ? lead : kInvalid;
       }
       __syncthreads();
       f_best(L);
@@ -948,7 +1000,9 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     }
     if (nf && step_rebuilds > 0)
       if (!bulk_eval(a, G, s, fbest, gen, clk, evals)) return;
+    if (threadIdx.x == 0) L.lead = kInvalid;  // the rebuilt F did not come from one round
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
+    synced = true;
     ++step_rebuilds;
     if (L.ns == 0 && L.nf == 0) {  // no unselected vertex: cannot happen for K <= n
       if (G.bi == 0 && threadIdx.x == 0) g_or(&x->err, 2u);
@@ -964,6 +1018,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     x->prof[12] = clk.barriers;
     x->prof[13] = clk.rounds;
     x->prof[14] = ((uint64_t)clk.bulks << 32) | clk.rebuilds;
+    x->prof[15] = clk.ahead;
   }
 }
 

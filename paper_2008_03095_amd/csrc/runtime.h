@@ -142,6 +142,10 @@ struct im_ctx {
   hipEvent_t coop_done = nullptr;
   bool coop_pending = false;
   hipStream_t coop_stream = nullptr;
+  // streams of this context besides stream, aux and bstreams (a server's
+  // slots): a persistent launch is fenced against every one of them
+  std::vector<hipStream_t> peers;
+  std::vector<hipEvent_t> fence_ev;  // one per fenced stream, reused
 };
 
 struct im_graph {

@@ -511,9 +511,32 @@ void celf_prepare(CelfBuffers* cb, hipStream_t st) {
 // Returns false when the device cannot run it.
 bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_t group_blocks,
                             const uint32_t* first, hipStream_t st) {
-  // one persistent kernel at a time per context: two partly resident
-  // cooperative grids could each wait for the other's workgroups
+  // The grid waits at barriers for all of its workgroups, so all of them must
+  // become resident: no other kernel of this context may hold the device's
+  // resources meanwhile (a server's slots keep feeding kernels; a late
+  // workgroup could wait behind them until the barrier gives up).  The
+  // launch waits for the work already enqueued on every other stream of the
+  // context, and their later work waits for the launch.  This also keeps
+  // two persistent grids apart.
   std::lock_guard<std::recursive_mutex> lk(c->mu);
+  std::vector<hipStream_t> others;
+  auto add = [&](hipStream_t o) {
+    if (o && o != st && std::find(others.begin(), others.end(), o) == others.end()) others.push_back(o);
+  };
+  add(c->stream);
+  add(c->aux);
+  for (hipStream_t o : c->bstreams) add(o);
+  for (hipStream_t o : c->peers) add(o);
+  while (c->fence_ev.size() < others.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+    c->fence_ev.push_back(e);
+  }
+  for (size_t i = 0; i < others.size(); ++i) {
+    if (hipEventRecord(c->fence_ev[i], others[i]) != hipSuccess ||
+        hipStreamWaitEvent(st, c->fence_ev[i], 0) != hipSuccess)
+      return false;
+  }
   if (c->coop_pending && c->coop_stream != st) (void)hipStreamWaitEvent(st, c->coop_done, 0);
   hipError_t e;
   {
@@ -525,6 +548,7 @@ bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_
     return false;
   }
   (void)hipEventRecord(c->coop_done, st);
+  for (hipStream_t o : others) (void)hipStreamWaitEvent(o, c->coop_done, 0);
   c->coop_pending = true;
   c->coop_stream = st;
   return true;
@@ -632,7 +656,7 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
   if (perr) return fail(IM_ERR_DEVICE, "persistent CELF kernel aborted (code %u)", perr);
   if (cb->persistent && c->profiling >= 2) {
     // phase clock of the persistent kernel: ticks of 10 ns per phase
-    uint64_t pr[15];
+    uint64_t pr[16];
     if (hipMemcpy(pr, static_cast<char*>(cb->pscratch) + pcelf_prof_offset(), sizeof(pr),
                   hipMemcpyDeviceToHost) == hipSuccess) {
       std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -645,6 +669,7 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
         e.first += counts[i];
         e.second += pr[i] * 1e-5;
       }
+      c->kstats["celf.lookahead_commits"].first += pr[15];  // steps decided without a round
     }
   }
   if (hs.s != v.K) return fail(IM_ERR_DEVICE, "CELF committed %u of %u seeds", hs.s, v.K);
@@ -720,6 +745,7 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
     (void)hipStreamDestroy(c->aux);
   }
   if (c->coop_done) (void)hipEventDestroy(c->coop_done);
+  for (hipEvent_t e : c->fence_ev) (void)hipEventDestroy(e);
   delete c;
 }
 

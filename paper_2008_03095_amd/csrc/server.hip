@@ -10,6 +10,7 @@
 // queries run (their memos are pinned); with nothing running it is rejected.
 // Queries that arrive while others run are admitted as soon as a slot and
 // memory free up, so their kernels overlap on the device.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -316,6 +317,7 @@ extern "C" im_status im_server_create(im_ctx* c, const im_server_config* cfg, im
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     c->memo_demand = memo_demand;
     c->memo_demand_user = sv;
+    for (Slot& s : sv->slots) c->peers.push_back(s.stream);  // fenced by persistent launches
   }
   sv->worker = std::thread(worker_main, sv);
   *out = sv;
@@ -423,6 +425,8 @@ extern "C" void im_server_destroy(im_server* sv) {
       sv->ctx->memo_demand = nullptr;
       sv->ctx->memo_demand_user = nullptr;
     }
+    auto& pe = sv->ctx->peers;
+    for (Slot& s : sv->slots) pe.erase(std::remove(pe.begin(), pe.end(), s.stream), pe.end());
   }
   for (Slot& s : sv->slots) {
     if (s.host) (void)hipHostFree(s.host);
