@@ -515,22 +515,38 @@ __global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts)
   __syncthreads();
   const uint32_t word = t >> 5, bit = t & 31;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  // 64 vertices' mask words per load; the wave then visits the flagged ones
+  // 64 vertices' mask words per load; the wave then visits the flagged ones,
+  // four rows requested together
+  constexpr int kRows = 4;
   for (uint32_t vb = v0 + wv * 64; vb < v1; vb += 4 * 64) {
     const uint32_t vl = vb + lane;
     const bool flagged = vl < v1 && ((m.tmask[(uint64_t)vl * m.mwords + word] >> bit) & 1u);
-    for (uint64_t fm = __ballot(flagged); fm; fm &= fm - 1) {
-    const uint32_t v = vb + (uint32_t)__builtin_ctzll(fm);
-    const int4 cur = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + q0);
-    const int32_t vals[4] = {cur.x, cur.y, cur.z, cur.w};
+    uint64_t fm = __ballot(flagged);
+    while (fm) {
+      uint32_t vv[kRows];
+      bool on[kRows];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t q = q0 + i;
-      const int32_t c = vals[i];
-      if (q >= m.R || c < 0) continue;
-      if ((uint32_t)c < kHotRoots) atomicAdd(&hot[c][lane * kPerLane + i], 1u);
-      else atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
-    }
+      for (int r = 0; r < kRows; ++r) {
+        on[r] = fm != 0;
+        vv[r] = on[r] ? vb + (uint32_t)__builtin_ctzll(fm) : vb + (uint32_t)__builtin_ctzll(__ballot(flagged));
+        fm &= fm - 1;
+      }
+      int4 rows[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) rows[r] = *reinterpret_cast<const int4*>(m.M + (uint64_t)vv[r] * m.Rs + q0);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        if (!on[r]) continue;
+        const int32_t vals[4] = {rows[r].x, rows[r].y, rows[r].z, rows[r].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t q = q0 + i;
+          const int32_t c = vals[i];
+          if (q >= m.R || c < 0) continue;
+          if ((uint32_t)c < kHotRoots) atomicAdd(&hot[c][lane * kPerLane + i], 1u);
+          else atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+        }
+      }
     }
   }
   __syncthreads();
