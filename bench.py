@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--queries", type=int, default=300, help="serving workload: queries of the trace")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: concurrent query slots")
     ap.add_argument("--hbm-budget-gib", type=float, default=224.0, help="serving workload: memo budget")
-    ap.add_argument("--cpu-samples", type=int, default=1536)
+    ap.add_argument("--cpu-samples", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--weights", default="const", choices=["const", "uniform", "normal"],
