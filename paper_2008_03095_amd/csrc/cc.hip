@@ -77,10 +77,10 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
 }
 
 // k_hook_rows: one wavefront per vertex with at most kWave neighbours (the
-// neighbour list sits in registers).  Per 32 tiles, the lanes first read the
-// X bounds of one tile each and the wavefront tests every tile's bounds
-// against all its edges (two lane reads, a compare and a ballot per tile):
-// the tiles with a candidate edge form the tmask word.  Only those tiles are
+// neighbour list sits in registers).  Per 32 tiles, lane i reads the X
+// bounds of tile i and tests them against every edge of the vertex (one lane
+// read and a compare per edge): the tiles with a candidate edge form the
+// tmask word.  Only those tiles are
 // then hooked and written, the X values of the next one loaded before the
 // current one is processed.  The wave owns the vertex's mask words and
 // stores them directly.
@@ -100,8 +100,7 @@ __global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
     rh = e.y;
     if (PER_EDGE) rtm1 = g.tm1[beg + lane];
   }
-  const uint32_t kb = PER_EDGE ? bitlen32(rtm1) : m.kshift;
-  const uint32_t hk = (uint32_t)((uint64_t)rh >> kb);
+  const uint32_t kb = m.kshift;  // uniform mode
   int32_t* row = m.M + (uint64_t)v * m.Rs;
   uint32_t* tw = m.tmask + (uint64_t)v * m.mwords;
   uint32_t* lw = m.lmask + (uint64_t)v * m.mwords;
@@ -114,14 +113,26 @@ __global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
       xlo = m.xs[t * kTile];
       xhi = m.xs[min(t * kTile + kTile - 1, m.R - 1)];
     }
-    uint32_t cm = 0;
+    // lane i tests tile t0 + i against every edge (one lane read per edge)
+    bool hit = false;
     if (!m.never_live) {
-      for (uint32_t i = 0; i < nt; ++i) {
-        const uint32_t lo = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)xlo, (int)i) >> kb);
-        const uint32_t hi = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)xhi, (int)i) >> kb);
-        cm |= (__ballot(has && hk - lo <= hi - lo) != 0 ? 1u : 0u) << i;
+      const uint32_t deg = end - beg;
+      if (PER_EDGE) {
+        for (uint32_t j = 0; j < deg; ++j) {
+          const uint32_t kj = bitlen32((uint32_t)__builtin_amdgcn_readlane((int)rtm1, (int)j));
+          const uint32_t hj = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rh, (int)j) >> kj);
+          const uint32_t lo = (uint32_t)((uint64_t)xlo >> kj), hi = (uint32_t)((uint64_t)xhi >> kj);
+          hit = hit || hj - lo <= hi - lo;
+        }
+      } else {
+        const uint32_t lo = (uint32_t)((uint64_t)xlo >> kb), hi = (uint32_t)((uint64_t)xhi >> kb);
+        for (uint32_t j = 0; j < deg; ++j) {
+          const uint32_t hj = (uint32_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rh, (int)j) >> kb);
+          hit = hit || hj - lo <= hi - lo;
+        }
       }
     }
+    const uint32_t cm = (uint32_t)__ballot(hit && lane < nt);
     uint32_t lbits = 0;
     uint32_t rem = cm;
     uint4 xn = load_tile_x(m, t0 + (rem ? (uint32_t)__builtin_ctz(rem) : 0u), lane);
