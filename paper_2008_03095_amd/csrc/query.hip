@@ -15,27 +15,74 @@ __device__ inline uint64_t wave_sum_u64q(uint64_t x) {
   return x;
 }
 
-// One thread per column: a seed's component counts unless an earlier seed
-// of the list has the same label in that column.
-__global__ void __launch_bounds__(64) k_sigma_pair(MemoView m, const uint32_t* S, uint32_t len,
-                                                   unsigned long long* out) {
+// A workgroup per 64 columns; its four wavefronts split the seeds.  First
+// each (seed, column) gets its label and component size, the loads of a
+// wavefront's seeds issued together; then a seed's component counts unless
+// an earlier seed of the list has the same label in that column.  S holds
+// distinct ids (the callers deduplicate it), so a singleton seed shares its
+// component with no other seed; a shared label is usually met early, since
+// the seeds of one large component share its root.
+constexpr int kSigmaBatch = 8;
+__global__ void __launch_bounds__(256) k_sigma_pair(MemoView m, const uint32_t* S, uint32_t len,
+                                                    unsigned long long* out) {
   __shared__ uint32_t roots[kSigmaPairMax][64];
-  const uint32_t q = blockIdx.x * 64 + threadIdx.x;
+  __shared__ int32_t sizes[kSigmaPairMax][64];
+  __shared__ unsigned long long part[4];
+  const uint32_t c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t q = blockIdx.x * 64 + c;
+  const uint32_t qq = q < m.R ? q : m.R - 1;  // in range; the count skips q >= R
+  const uint32_t t = qq / kTile;
+  for (uint32_t j0 = w * kSigmaBatch; j0 < len; j0 += 4 * kSigmaBatch) {
+    uint32_t s[kSigmaBatch];
+    int32_t raw[kSigmaBatch];
+    uint32_t tw[kSigmaBatch];
+#pragma unroll
+    for (int k = 0; k < kSigmaBatch; ++k) {
+      s[k] = S[min(j0 + k, len - 1)];
+      raw[k] = m.M[(uint64_t)s[k] * m.Rs + qq];
+      tw[k] = m.tmask[(uint64_t)s[k] * m.mwords + (t >> 5)];
+    }
+    int32_t val[kSigmaBatch], gsz[kSigmaBatch];
+#pragma unroll
+    for (int k = 0; k < kSigmaBatch; ++k) {
+      val[k] = ((tw[k] >> (t & 31)) & 1u) ? raw[k] : -1;
+      gsz[k] = m.M[(uint64_t)(val[k] < 0 ? s[k] : (uint32_t)val[k]) * m.Rs + qq];  // issued for every seed
+    }
+#pragma unroll
+    for (int k = 0; k < kSigmaBatch; ++k) {
+      const uint32_t j = j0 + k;
+      if (j < len) {
+        roots[j][c] = val[k] < 0 ? s[k] : (uint32_t)val[k];
+        sizes[j][c] = val[k] == -1 ? 0 : (val[k] < 0 ? -val[k] : -gsz[k]);  // 0 marks a singleton
+      }
+    }
+  }
+  __syncthreads();
   uint64_t cnt = 0;
   if (q < m.R) {
-    for (uint32_t j = 0; j < len; ++j) {
-      const uint32_t s = S[j];
-      const int32_t val = memo_entry(m, s, q);
-      const uint32_t root = val < 0 ? s : (uint32_t)val;
-      const int32_t size = val < 0 ? -val : -m.M[(uint64_t)val * m.Rs + q];
+    for (uint32_t j = w; j < len; j += 4) {
+      const int32_t sz = sizes[j][c];
+      if (sz == 0) {  // a singleton seed: its own component, of size 1
+        cnt += 1;
+        continue;
+      }
+      const uint32_t r = roots[j][c];
       bool dup = false;
-      for (uint32_t i = 0; i < j; ++i) dup = dup || roots[i][threadIdx.x] == root;
-      roots[j][threadIdx.x] = root;
-      cnt += dup ? 0 : (uint64_t)size;
+      for (uint32_t i = 0; i < j; ++i)
+        if (roots[i][c] == r) {
+          dup = true;
+          break;
+        }
+      cnt += dup ? 0 : (uint64_t)sz;
     }
   }
   cnt = wave_sum_u64q(cnt);
-  if (threadIdx.x == 0 && cnt) atomicAdd(out, (unsigned long long)cnt);
+  if (c == 0) part[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
+    if (tot) atomicAdd(out, tot);
+  }
 }
 
 // Any |S|: the first seed to set its component's bit in a zeroed
@@ -82,7 +129,7 @@ uint32_t sigma_pair_max() { return kSigmaPairMax; }
 
 void launch_sigma_pair(const MemoView& m, const uint32_t* S, uint32_t len, unsigned long long* out,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_sigma_pair, dim3((m.R + 63) / 64), dim3(64), 0, st, m, S, len, out);
+  hipLaunchKernelGGL(k_sigma_pair, dim3((m.R + 63) / 64), dim3(256), 0, st, m, S, len, out);
 }
 
 void launch_sigma_bitmap(const MemoView& m, const uint32_t* S, uint32_t len, uint32_t* bm,
