@@ -72,6 +72,12 @@ def _load():
     lib.orc_celf.restype = C.c_int
     lib.orc_celf_memo.argtypes = [u32, u32, vp, vp, vp, u32, vp, vp, vp, vp]
     lib.orc_celf_memo.restype = C.c_int
+    lib.orc_arc_key.argtypes = [u32, u32, u32]
+    lib.orc_arc_key.restype = u32
+    lib.orc_arc_hash.argtypes = [u32, u32, u32, u32]
+    lib.orc_arc_hash.restype = u32
+    lib.orc_sigma_count_arcs.argtypes = [u32, vp, vp, dbl, vp, u32, u32, vp, u32, C.c_int]
+    lib.orc_sigma_count_arcs.restype = i64
     _lib = lib
     return lib
 
@@ -167,10 +173,32 @@ def label_range(g, s: Sampler, r0: int, cnt: int) -> np.ndarray:
     return out
 
 
+def arc_key(u: int, v: int, n: int) -> int:
+    return _load().orc_arc_key(u, v, n)
+
+
+def arc_hash(seed: int, u: int, v: int, n: int) -> int:
+    return _load().orc_arc_hash(seed & 0xFFFFFFFF, u, v, n)
+
+
 def sigma_count(g, s: Sampler, S, threads: int = 1) -> int:
+    """sum_r |vertices reachable from S in sample r|.  On a directed graph
+    (g.directed) reachability follows the out-arcs, each arc hashed from its
+    ordered pair (hash sampling only)."""
     lib = _load()
-    keep, a = _args(g, s)
     S = np.ascontiguousarray(np.asarray(S, dtype=np.uint32))
+    if getattr(g, "directed", False):
+        if s.mode != MODE_HASH:
+            raise ValueError("directed graphs use hash sampling")
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.uint64)
+        col = np.ascontiguousarray(g.col, dtype=np.uint32)
+        p_slot = s.p_slot if s.p_slot is not None else (
+            None if g.p_slot is None else np.ascontiguousarray(g.p_slot, np.float64))
+        r = lib.orc_sigma_count_arcs(g.n, _ptr(rp), _ptr(col), s.p, _ptr(p_slot), s.R, s.seed, _ptr(S),
+                                     int(S.size), int(threads))
+        del rp, col, p_slot
+        return int(r)
+    keep, a = _args(g, s)
     r = lib.orc_sigma_count(*a, _ptr(S), int(S.size), int(threads))
     del keep
     return int(r)

@@ -22,7 +22,9 @@
  *     re-evaluated RandCas-style (Algorithm 4) on the same R samples, with
  *     ties broken by the smaller vertex id;
  *   - sigma(S) counts: sum over samples of the number of vertices reachable
- *     from S (Algorithm 4 without the division by R).
+ *     from S (Algorithm 4 without the division by R);
+ *   - the same count on a digraph, where an arc is hashed from the ordered
+ *     pair and reachability follows the arcs (orc_sigma_count_arcs).
  *
  * Every count is an exact integer (int64).  sigma = count / R is formed only
  * by callers.
@@ -68,6 +70,17 @@ uint32_t orc_edge_hash(uint32_t seed, uint32_t u, uint32_t v, uint32_t n) {
 
 /* X_r of Eq. 2: one 32-bit value per simulation r = 0..R-1. */
 uint32_t orc_sample_value(uint32_t seed, uint32_t r) { return orc_fmix32(seed + r); }
+
+/* Directed graphs (the paper leaves them to future work): an arc u -> v is
+ * its own edge, hashed from the ordered pair, i.e. the 64-bit key u*n + v
+ * folded the same way.  For u < v it equals the undirected key. */
+uint32_t orc_arc_key(uint32_t u, uint32_t v, uint32_t n) {
+    uint64_t key = (uint64_t)u * (uint64_t)n + (uint64_t)v;
+    return (uint32_t)key ^ orc_fmix32((uint32_t)(key >> 32));
+}
+uint32_t orc_arc_hash(uint32_t seed, uint32_t u, uint32_t v, uint32_t n) {
+    return orc_fmix32(seed ^ orc_arc_key(u, v, n));
+}
 
 /* Threshold floor(p * 2^32) held in 64 bits so that p = 1 keeps every edge.
  * Scaling a double by 2^32 is exact, so the floor is exactly determined. */
@@ -397,6 +410,28 @@ int64_t orc_sigma_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col
                         const uint8_t *table, const uint32_t *S, uint32_t s_len, int threads) {
     orc_graph g;
     if (graph_init(&g, n, row_ptr, col, mode, p, p_slot, R, seed, table)) return -1;
+    orc_job jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.g = &g;
+    jb.task = 2;
+    jb.S = S;
+    jb.s_len = s_len;
+    run_jobs(&jb, threads);
+    graph_free(&g);
+    return (int64_t)jb.acc;
+}
+
+/* sigma count of S on a digraph (out-arc CSR): sum_r |vertices reachable
+ * from S over the live arcs of sample r|, the independent-cascade spread of
+ * Algorithm 4 with directed reachability.  Arc liveness follows Eq. 2 with
+ * the arc hash above (hash sampling only). */
+int64_t orc_sigma_count_arcs(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, double p,
+                             const double *p_slot, uint32_t R, uint32_t seed, const uint32_t *S,
+                             uint32_t s_len, int threads) {
+    orc_graph g;
+    if (graph_init(&g, n, row_ptr, col, ORC_MODE_HASH, p, p_slot, R, seed, NULL)) return -1;
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) g.h_slot[j] = orc_arc_hash(seed, u, col[j], n);
     orc_job jb;
     memset(&jb, 0, sizeof(jb));
     jb.g = &g;

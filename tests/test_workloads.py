@@ -33,3 +33,32 @@ def test_normal_weights():
     assert abs(ps.mean() - 0.05021) < 0.001
     assert 0.022 < ps.std() < 0.0255
     assert 0.015 < (ps == 0.0).mean() < 0.032
+
+
+def test_rmat_directed_is_a_simple_digraph():
+    from workloads import rmat_directed
+
+    g = rmat_directed(10, 6, 0.57, 0.19, 0.19, 5)
+    assert g.directed and g.m == g.nnz
+    rp = g.row_ptr.astype(np.int64)
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    assert np.all(rows != g.col)  # no self-loops
+    for u in range(g.n):
+        row = g.col[rp[u]:rp[u + 1]]
+        assert np.all(np.diff(row.astype(np.int64)) > 0)  # sorted, no duplicate arcs
+    # not symmetrised: some arc has no reverse
+    fwd = set(zip(rows.tolist(), g.col.tolist()))
+    assert any((v, u) not in fwd for (u, v) in fwd)
+    assert g.nnz <= 6 * g.n
+
+
+def test_wc_weights_sum_to_one_into_each_vertex():
+    from workloads import random_small_digraph, wc_p
+
+    g = random_small_digraph(50, 300, 2)
+    p = wc_p(g)
+    into = np.zeros(g.n)
+    np.add.at(into, g.col.astype(np.int64), p)
+    indeg = np.bincount(g.col.astype(np.int64), minlength=g.n)
+    assert np.allclose(into[indeg > 0], 1.0) and np.all(into[indeg == 0] == 0)
+    assert np.all((p > 0) & (p <= 1))

@@ -21,5 +21,9 @@ from .graphs import (  # noqa: F401
     star_graph,
     path_graph,
     random_small_graph,
+    from_arc_list,
+    rmat_directed,
+    wc_p,
+    random_small_digraph,
 )
 from .configs import CONFIGS, Query, make_config, config_graphs, serving_trace  # noqa: F401

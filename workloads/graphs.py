@@ -47,14 +47,16 @@ def uniform01(seed: int, start: int, count: int) -> np.ndarray:
 
 @dataclass
 class Graph:
-    """Undirected graph in symmetric CSR form."""
+    """Graph in CSR form: symmetric (undirected, both orientations of every
+    edge) or, with directed=True, the out-arcs of every vertex."""
 
     n: int
     row_ptr: np.ndarray  # uint64 [n+1]
-    col: np.ndarray  # uint32 [2m]
-    p_slot: Optional[np.ndarray] = None  # float64 [2m] or None (uniform p)
+    col: np.ndarray  # uint32 [2m] (undirected) or [m] (directed)
+    p_slot: Optional[np.ndarray] = None  # float64 per slot or None (uniform p)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    directed: bool = False
 
     @property
     def nnz(self) -> int:
@@ -62,7 +64,8 @@ class Graph:
 
     @property
     def m(self) -> int:
-        return self.nnz // 2
+        """Edges (undirected) or arcs (directed)."""
+        return self.nnz if self.directed else self.nnz // 2
 
     def degrees(self) -> np.ndarray:
         return np.diff(self.row_ptr.astype(np.int64))
@@ -105,6 +108,20 @@ def from_edge_list(n: int, u: np.ndarray, v: np.ndarray, name: str = "",
     if pk is not None:
         p_slot = np.concatenate([pk, pk])[order]
     return Graph(n=n, row_ptr=row_ptr, col=dst.astype(np.uint32), p_slot=p_slot, name=name)
+
+
+def from_arc_list(n: int, u: np.ndarray, v: np.ndarray, name: str = "") -> Graph:
+    """Directed CSR (out-arcs, rows sorted) from arcs u -> v; duplicate arcs
+    and self-loops are dropped."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    key = np.unique(u * n + v)
+    src, dst = key // n, key % n
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    return Graph(n=n, row_ptr=row_ptr, col=dst.astype(np.uint32), name=name, directed=True)
 
 
 def chung_lu(n: int, m: int, gamma: float, seed: int, stream_offset: int = 0,
@@ -175,6 +192,49 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
     g = from_edge_list(n, u, v, name=name or f"rmat(scale={scale},ef={edge_factor},seed={seed})")
     g.meta.update(kind="rmat", scale=scale, edge_factor=edge_factor, seed=seed)
     return g
+
+
+def rmat_directed(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+                  name: str = "", chunk: int = 1 << 21) -> Graph:
+    """R-MAT digraph: the draws of rmat() taken as arcs row -> column (not
+    symmetrised), deduplicated, self-loops dropped."""
+    n = 1 << scale
+    draws = edge_factor * n
+    us, vs = [], []
+    pos = 0
+    t_ab, t_abc = a + b, a + b + c
+    for start in range(0, draws, chunk):
+        cnt = min(chunk, draws - start)
+        uu = uniform01(seed, pos, cnt * scale).reshape(cnt, scale)
+        pos += cnt * scale
+        row_bit = (uu >= t_ab).astype(np.int64)
+        col_bit = (((uu >= a) & (uu < t_ab)) | (uu >= t_abc)).astype(np.int64)
+        weights = (1 << np.arange(scale - 1, -1, -1, dtype=np.int64))
+        us.append(row_bit @ weights)
+        vs.append(col_bit @ weights)
+    g = from_arc_list(n, np.concatenate(us), np.concatenate(vs),
+                      name=name or f"rmat_dir(scale={scale},ef={edge_factor},seed={seed})")
+    g.meta.update(kind="rmat_directed", scale=scale, edge_factor=edge_factor, seed=seed)
+    return g
+
+
+def wc_p(g: Graph) -> np.ndarray:
+    """Weighted-cascade probabilities of a digraph: arc u -> v gets
+    1 / in-degree(v), so the arcs into a vertex sum to one."""
+    if not g.directed:
+        raise ValueError("the weighted cascade is defined on arcs")
+    indeg = np.bincount(g.col.astype(np.int64), minlength=g.n)
+    return 1.0 / indeg[g.col.astype(np.int64)].astype(np.float64)
+
+
+def random_small_digraph(n: int, m: int, seed: int) -> Graph:
+    """Uniform random simple digraph with n vertices and m arcs (m <= n(n-1))."""
+    arcs = [(i, j) for i in range(n) for j in range(n) if i != j]
+    if m > len(arcs):
+        raise ValueError("too many arcs")
+    keys = splitmix64_stream(seed, 0, len(arcs))
+    sel = np.array([arcs[i] for i in sorted(np.argsort(keys, kind="stable")[:m])], dtype=np.int64).reshape(-1, 2)
+    return from_arc_list(n, sel[:, 0], sel[:, 1], name=f"drand({n},{m},{seed})")
 
 
 def trivalency_p(g: Graph, graph_seed: int, values=(0.1, 0.01, 0.001)) -> np.ndarray:
