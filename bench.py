@@ -219,6 +219,76 @@ def serve_bench(args):
     print(json.dumps(rec), flush=True)
 
 
+def directed_bench(args):
+    """Directed graphs (a widening of the paper's undirected method): the
+    spread of a seed set on a directed R-MAT (scale 18, edge factor 5, arcs
+    not symmetrised, seed 3) under the weighted cascade (p(u -> v) =
+    1 / in-degree(v)), R = 8,192, S = the 100 vertices of largest out-degree.
+    One step = the memo-free search (sampler set-up, level-synchronous
+    reachability over all samples, count); value = arcs * R / step time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2008_03095_amd as P
+    from workloads import rmat_directed, wc_p
+
+    g = rmat_directed(18, 5, 0.57, 0.19, 0.19, 3)
+    g.p_slot = wc_p(g)
+    R, seed = 8192, 3
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    S = [int(v) for v in np.argsort(-deg, kind="stable")[:100]]
+    ctx = P.Context(device=0)
+    G = P.Graph.from_csr(ctx, g)
+    G.set_params(0.0, R, seed)
+    for _ in range(args.warmup):
+        cnt, _, levels = G.estimate_sigma_direct(S)
+    ctx.set_profiling(1)
+    ctx.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cnt, _, levels = G.estimate_sigma_direct(S)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    ms = dt * 1e3 / args.steps
+    names = ["edge_hash", "x_sort", "sigma_direct"]
+    stats = {k: ctx.kernel_stats(k) for k in names}
+    rec = {
+        "metric": "arc-samples/s (arcs·R / spread time), directed spread under the weighted cascade",
+        "value": g.nnz * R / (ms * 1e-3),
+        "unit": "arc-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 bitsets",
+        "data": "synthetic",
+        "config": {"workload": "d1: directed R-MAT scale 18, edge factor 5, seed 3, weighted cascade; R=8192, "
+                               "|S|=100 (largest out-degree)", "n": g.n, "arcs": g.nnz, "R": R},
+        "count": cnt,
+        "levels": levels,
+        "kernel_total_ms_per_step": {k: v[1] / args.steps for k, v in stats.items()},
+    }
+    G.free()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        # the oracle on the first samples of the same spread
+        samples = min(args.cpu_samples, R)
+        threads = len(os.sched_getaffinity(0))
+        t = time.perf_counter()
+        oracle.sigma_count(g, oracle.Sampler("hash", R=samples, seed=seed), S, threads=threads)
+        dt_c = time.perf_counter() - t
+        rec["cpu_baseline"] = {"value": g.nnz * samples / dt_c, "unit": "arc-samples/s", "cores": threads,
+                               "kind": "oracle", "sample": f"same graph and S, first {samples} of {R} samples "
+                               f"({dt_c:.2f} s)"}
+    print(json.dumps(rec), flush=True)
+
+
 def batch_bench(args):
     """Batching workload: 64 Chung-Lu graphs (seeds 100..163, n log-uniform in
     [1,000, 40,000], m uniform in [2n, 10n], per-edge trivalency p), R = 1,024,
@@ -313,7 +383,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c3", "c5"])
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c3", "c5", "d1"])
     ap.add_argument("--queries", type=int, default=300, help="serving workload: queries of the trace")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: concurrent query slots")
     ap.add_argument("--hbm-budget-gib", type=float, default=224.0, help="serving workload: memo budget")
@@ -344,6 +414,9 @@ def main():
         return
     if args.workload == "c3":
         batch_bench(args)
+        return
+    if args.workload == "d1":
+        directed_bench(args)
         return
 
     import numpy as np

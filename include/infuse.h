@@ -101,6 +101,18 @@ uint64_t im_ctx_bytes_in_use(const im_ctx *ctx);
  * Errors: IM_ERR_INVALID_GRAPH for malformed input, IM_ERR_OUT_OF_MEMORY. */
 im_status im_graph_load_csr(im_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
                             const uint32_t *col_idx, const double *p_slot, im_graph **out);
+/* Loads a directed graph (not a method of the paper, which leaves directed
+ * graphs to future work; the spread follows its Algorithm 4 with directed
+ * reachability).  row_ptr/col_idx give the out-arcs of every vertex in the
+ * layout of im_graph_load_csr, without the symmetry requirement: arc u -> v
+ * is an edge of its own, hashed from the ordered pair (key u*n + v, folded
+ * like the undirected key) and live in sample r when (h ^ X_r) < T.
+ * p_slot (nullable) gives a probability per arc, e.g. the weighted cascade
+ * p(u -> v) = 1 / in-degree(v).  Only im_set_params and
+ * im_estimate_sigma_direct (reachability from S over the live arcs) apply:
+ * every memo call returns IM_ERR_INVALID_ARG.  Errors as im_graph_load_csr. */
+im_status im_graph_load_arcs(im_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
+                             const uint32_t *col_idx, const double *p_slot, im_graph **out);
 void im_graph_free(im_graph *g);
 
 /* Sets the uniform edge probability p (Section IV-B weight settings), the

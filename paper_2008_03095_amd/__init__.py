@@ -155,10 +155,11 @@ class Context:
 
 
 class Graph:
-    """An undirected CSR graph resident on the device (im_graph_load_csr)."""
+    """A CSR graph resident on the device: undirected (im_graph_load_csr) or,
+    with directed=True, the out-arcs of every vertex (im_graph_load_arcs)."""
 
     def __init__(self, ctx: Context, n: int, row_ptr: np.ndarray, col: np.ndarray,
-                 p_slot: Optional[np.ndarray] = None):
+                 p_slot: Optional[np.ndarray] = None, directed: bool = False):
         self._lib = ctx._lib
         self.ctx = ctx
         self.n = int(n)
@@ -166,8 +167,10 @@ class Graph:
         cl = np.ascontiguousarray(col, dtype=np.uint32)
         ps = None if p_slot is None else np.ascontiguousarray(p_slot, dtype=np.float64)
         out = C.c_void_p()
-        check(self._lib.im_graph_load_csr(ctx.handle, self.n, int(rp[-1]) if rp.size else 0,
-                                          _ptr(rp), _ptr(cl), _ptr(ps), C.byref(out)))
+        load = self._lib.im_graph_load_arcs if directed else self._lib.im_graph_load_csr
+        check(load(ctx.handle, self.n, int(rp[-1]) if rp.size else 0, _ptr(rp), _ptr(cl), _ptr(ps),
+                   C.byref(out)))
+        self.directed = bool(directed)
         self.handle = out
         self.R = 0
         self.nnz = int(rp[-1]) if rp.size else 0
@@ -175,8 +178,9 @@ class Graph:
 
     @classmethod
     def from_csr(cls, ctx: Context, g) -> "Graph":
-        """From any object with n, row_ptr, col and optional p_slot."""
-        return cls(ctx, g.n, g.row_ptr, g.col, getattr(g, "p_slot", None))
+        """From any object with n, row_ptr, col and optional p_slot and
+        directed."""
+        return cls(ctx, g.n, g.row_ptr, g.col, getattr(g, "p_slot", None), bool(getattr(g, "directed", False)))
 
     def free(self):
         if getattr(self, "handle", None):

@@ -60,6 +60,7 @@ SIGNATURES = {
     "im_ctx_destroy": (None, [vp]),
     "im_ctx_bytes_in_use": (u64, [vp]),
     "im_graph_load_csr": (C.c_int, [vp, u32, u64, vp, vp, vp, P(vp)]),
+    "im_graph_load_arcs": (C.c_int, [vp, u32, u64, vp, vp, vp, P(vp)]),
     "im_graph_free": (None, [vp]),
     "im_set_params": (C.c_int, [vp, dbl, u32, u32]),
     "im_build_memo": (C.c_int, [vp]),

@@ -14,6 +14,7 @@ using namespace infuse;
 extern "C" im_status im_autotune(im_graph* g, uint32_t K, uint32_t reps, im_tuning* best) {
   if (!g || !best) return fail(IM_ERR_INVALID_ARG, "NULL argument");
   if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  if (g->directed) return fail(IM_ERR_INVALID_ARG, "directed graph: no memo selection to tune");
   if (K == 0 || K > g->n) return fail(IM_ERR_INVALID_ARG, "K must be in 1..n");
   if (reps == 0) reps = 1;
   im_ctx* c = g->ctx;

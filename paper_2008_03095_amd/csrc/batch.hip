@@ -35,6 +35,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     if (!graphs[i] || graphs[i]->ctx != c) return fail(IM_ERR_INVALID_ARG, "graph %u is not of this context", i);
     if (K[i] > graphs[i]->n) return fail(IM_ERR_INVALID_ARG, "K[%u] exceeds n", i);
     if (!graphs[i]->params_set) return fail(IM_ERR_INVALID_ARG, "graph %u has no parameters", i);
+    if (graphs[i]->directed) return fail(IM_ERR_INVALID_ARG, "graph %u is directed: no memo selection", i);
   }
   std::vector<Memo*> memos(ng, nullptr);
   std::vector<CelfBuffers> cbs(ng);

@@ -43,6 +43,13 @@ __host__ __device__ inline uint32_t edge_key32(uint32_t u, uint32_t v, uint32_t 
   return (uint32_t)key ^ fmix32((uint32_t)(key >> 32));
 }
 
+// Key of the arc u -> v of a directed graph (an arc is its own edge): the
+// ordered pair u * n + v, folded like edge_key32 (equal to it when u < v).
+__host__ __device__ inline uint32_t arc_key32(uint32_t u, uint32_t v, uint32_t n) {
+  const uint64_t key = (uint64_t)u * n + v;
+  return (uint32_t)key ^ fmix32((uint32_t)(key >> 32));
+}
+
 // Bit length of t (0 for t = 0): the smallest k with t < 2^k.  With
 // tm1 = T - 1 a live edge needs (h ^ X) <= tm1, hence (h ^ X) >> k == 0.
 __host__ __device__ inline uint32_t bitlen32(uint32_t t) {
@@ -66,6 +73,7 @@ struct GraphView {
                             // piece of a hub's smaller neighbours
   uint32_t nhubs;
   uint32_t hub_pieces;      // entries of hub_piece
+  uint32_t directed;        // 1: col holds out-arcs, each hashed from its ordered pair
 };
 
 // Per-memo device view.

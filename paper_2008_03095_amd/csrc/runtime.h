@@ -154,6 +154,7 @@ struct im_graph {
   uint64_t nnz_in = 0;  // slots given by the caller
   uint32_t nnz = 0;     // slots on the device (per-slot p: T = 0 slots dropped)
   bool per_edge = false;
+  bool directed = false;  // out-arc CSR: only the memo-free spread applies
   void* gbuf = nullptr;
   uint32_t* row_ptr = nullptr;
   uint32_t* col = nullptr;

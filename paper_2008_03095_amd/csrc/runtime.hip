@@ -29,6 +29,7 @@ infuse::GraphView im_graph::view() const {
   v.hub_piece = hub_piece;
   v.nhubs = nhubs;
   v.hub_pieces = hub_pieces;
+  v.directed = directed ? 1u : 0u;
   return v;
 }
 
@@ -263,6 +264,9 @@ Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
 
 // Allocates the memo and enqueues its construction on `st`.
 im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out) {
+  if (g->directed)
+    return fail(IM_ERR_INVALID_ARG,
+                "directed graph: components do not give reachability; use im_estimate_sigma_direct");
   im_ctx* c = g->ctx;
   Memo* m = new Memo();
   m->tkey = g->per_edge ? 0 : thr_of(p);
@@ -814,7 +818,7 @@ extern "C" im_status im_kernel_stats(im_ctx* c, const char* kernel, uint64_t* la
 // ---------------------------------------------------------------------------
 
 static im_status validate_csr(uint32_t n, uint64_t nnz, const uint64_t* rp, const uint32_t* col,
-                              const double* p_slot) {
+                              const double* p_slot, bool directed) {
   if (n == 0) return fail(IM_ERR_INVALID_GRAPH, "n must be >= 1");
   if (n >= (1u << 31)) return fail(IM_ERR_INVALID_GRAPH, "n must be < 2^31");
   if (nnz >= (1ull << 32)) return fail(IM_ERR_INVALID_GRAPH, "nnz must be < 2^32");
@@ -830,6 +834,7 @@ static im_status validate_csr(uint32_t n, uint64_t nnz, const uint64_t* rp, cons
         return fail(IM_ERR_INVALID_GRAPH, "row %u is not strictly increasing", u);
       if (p_slot && (!(p_slot[j] >= 0.0) || !(p_slot[j] <= 1.0)))
         return fail(IM_ERR_INVALID_GRAPH, "p_slot[%llu] outside [0,1]", (unsigned long long)j);
+      if (directed) continue;
       // symmetric: (v, u) must exist with the same probability
       const uint32_t* b = col + rp[v];
       const uint32_t* e = col + rp[v + 1];
@@ -842,11 +847,11 @@ static im_status validate_csr(uint32_t n, uint64_t nnz, const uint64_t* rp, cons
   return IM_OK;
 }
 
-extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
-                                       const uint32_t* col_idx, const double* p_slot, im_graph** out) {
+static im_status load_graph(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                            const uint32_t* col_idx, const double* p_slot, bool directed, im_graph** out) {
   if (!c || !out) return fail(IM_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  im_status s = validate_csr(n, nnz, row_ptr, col_idx, p_slot);
+  im_status s = validate_csr(n, nnz, row_ptr, col_idx, p_slot, directed);
   if (s != IM_OK) return s;
   // device CSR: with per-slot p, slots with T = 0 are never live and are
   // dropped; the rest keep T - 1 per slot
@@ -879,6 +884,7 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   g->nnz_in = nnz;
   g->nnz = rp[n];
   g->per_edge = p_slot != nullptr;
+  g->directed = directed;
   const size_t b_rp = align256((size_t)(n + 1) * 4), b_col = align256((size_t)g->nnz * 4 + 4);
   const size_t b_split = align256((size_t)n * 4), b_tm1 = p_slot ? align256((size_t)g->nnz * 4 + 4) : 0;
   const size_t b_hubs = align256((size_t)hubs.size() * 4 + 4);
@@ -923,6 +929,16 @@ extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, cons
   }
   *out = g;
   return IM_OK;
+}
+
+extern "C" im_status im_graph_load_csr(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                       const uint32_t* col_idx, const double* p_slot, im_graph** out) {
+  return load_graph(c, n, nnz, row_ptr, col_idx, p_slot, false, out);
+}
+
+extern "C" im_status im_graph_load_arcs(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                        const uint32_t* col_idx, const double* p_slot, im_graph** out) {
+  return load_graph(c, n, nnz, row_ptr, col_idx, p_slot, true, out);
 }
 
 extern "C" void im_graph_free(im_graph* g) {

@@ -1,6 +1,7 @@
 // Hash edge sampler set-up (Section III-A, Eq. 1-2).
 //
-// k_edge_hash   h_e = fmix32(s ^ key32(u, v)) for every CSR slot, stored
+// k_edge_hash   h_e = fmix32(s ^ key32(u, v)) for every CSR slot (the key of
+//               the ordered pair for an arc of a directed graph), stored
 //               beside the neighbour id ({v, h_e}, 8 bytes per slot), since
 //               the paper precomputes the m hashes once instead of hashing
 //               during traversal.
@@ -20,7 +21,7 @@ __global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, u
     const uint32_t beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     for (uint32_t j = beg + lane; j < end; j += kWave) {
       const uint32_t v = g.col[j];
-      edges[j] = make_uint2(v, fmix32(seed ^ edge_key32(u, v, g.n)));
+      edges[j] = make_uint2(v, fmix32(seed ^ (g.directed ? arc_key32(u, v, g.n) : edge_key32(u, v, g.n))));
     }
   }
 }

@@ -328,6 +328,7 @@ extern "C" im_status im_server_submit(im_server* sv, im_graph* g, const im_query
   if (!sv || !g || !q || !ticket) return fail(IM_ERR_INVALID_ARG, "NULL argument");
   if (g->ctx != sv->ctx) return fail(IM_ERR_INVALID_ARG, "graph belongs to another context");
   if (q->kind != 0 && q->kind != 1) return fail(IM_ERR_INVALID_ARG, "unknown query kind %d", q->kind);
+  if (g->directed) return fail(IM_ERR_INVALID_ARG, "directed graph: the server answers from memos");
   im_status st = check_params(g, q->p, q->R);
   if (st != IM_OK) return st;
   auto t = std::make_unique<Ticket>();

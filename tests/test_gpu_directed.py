@@ -1,0 +1,85 @@
+"""Directed graphs: the memo-free spread (reachability over hashed arcs) on
+the device equals the oracle's count, sample for sample in total; memo calls
+are refused.  Integers, so the comparison is exact."""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2008_03095_amd as P
+from tests.conftest import announce
+from workloads import from_arc_list, random_small_digraph, rmat_directed, wc_p
+
+pytestmark = pytest.mark.gpu
+
+
+def _seed_sets(g, rng):
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    top = list(np.argsort(-deg, kind="stable")[:min(20, g.n)])
+    return [[0], list(rng.choice(g.n, min(5, g.n), replace=False)), top, list(range(g.n))[:200]]
+
+
+CASES = {
+    "drand12": (lambda: random_small_digraph(12, 40, 1), 0.3, 64, 1, False),
+    "drand300_ragged": (lambda: random_small_digraph(60, 900, 2), 0.05, 300, 2, False),
+    "rmat12_p01": (lambda: rmat_directed(12, 8, 0.57, 0.19, 0.19, 4), 0.01, 1024, 4, False),
+    "rmat12_wc": (lambda: rmat_directed(12, 8, 0.57, 0.19, 0.19, 5), 0.0, 512, 5, True),
+    "rmat14_wc_R257": (lambda: rmat_directed(14, 6, 0.57, 0.19, 0.19, 6), 0.0, 257, 6, True),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_directed_spread_matches_oracle(gpu_ctx, case):
+    make, p, R, seed, wc = CASES[case]
+    g = make()
+    if wc:
+        g.p_slot = wc_p(g)
+    announce(f"directed spread {case}: n={g.n} arcs={g.nnz} R={R}")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(p, R, seed)
+        s = oracle.Sampler("hash", p=p, R=R, seed=seed)
+        for S in _seed_sets(g, np.random.default_rng(seed)):
+            cnt, sig, _ = G.estimate_sigma_direct(S)
+            assert cnt == oracle.sigma_count(g, s, S, threads=8), S[:5]
+            assert sig == pytest.approx(cnt / R)
+    finally:
+        G.free()
+
+
+def test_directed_forced_live_path_and_no_live_arcs(gpu_ctx):
+    k = 300
+    a = np.arange(k - 1)
+    g = from_arc_list(k, a, a + 1)
+    announce("directed path, p = 1 and p = 0")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(1.0, 128, 3)
+        for i in (0, 17, k - 1):
+            assert G.estimate_sigma_direct([i])[0] == 128 * (k - i)
+        G.set_params(0.0, 128, 3)
+        assert G.estimate_sigma_direct([0, 5, 9])[0] == 128 * 3
+    finally:
+        G.free()
+
+
+def test_directed_graph_refuses_memo_calls(gpu_ctx):
+    g = random_small_digraph(20, 60, 3)
+    announce("directed graph memo refusal")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(0.1, 64, 1)
+        for call in (G.build_memo, lambda: G.select_seeds(2), lambda: G.estimate_sigma([1])):
+            with pytest.raises(P.InfuseError) as e:
+                call()
+            assert e.value.status == 1  # IM_ERR_INVALID_ARG
+        assert G.estimate_sigma_direct([1])[0] == oracle.sigma_count(g, oracle.Sampler("hash", p=0.1, R=64, seed=1), [1])
+    finally:
+        G.free()
+
+
+def test_arc_loader_rejects_malformed_rows(gpu_ctx):
+    with pytest.raises(P.InfuseError):
+        P.Graph(gpu_ctx, 3, np.array([0, 2, 2, 2], np.uint64), np.array([2, 1], np.uint32), directed=True)
+    with pytest.raises(P.InfuseError):
+        P.Graph(gpu_ctx, 3, np.array([0, 1, 1, 1], np.uint64), np.array([0], np.uint32), directed=True)
