@@ -508,10 +508,11 @@ __global__ void __launch_bounds__(256) k_flatten(MemoView m) {
 constexpr uint32_t kHotRoots = 8;
 constexpr uint32_t kCountMaxBlockVerts = 4096;
 
-// Vertices per workgroup of k_count: enough workgroups to fill the device
-// (about 2048), multiples of 256, at most kCountMaxBlockVerts.
+// Vertices per workgroup of k_count: many workgroups (about 32768, so that
+// the row loads of many wavefronts are in flight), multiples of 256, at most
+// kCountMaxBlockVerts.
 static uint32_t count_block_verts(const MemoView& m) {
-  const uint64_t want = ((uint64_t)m.n * m.ntiles + 2047) / 2048;
+  const uint64_t want = ((uint64_t)m.n * m.ntiles + 32767) / 32768;
   const uint64_t vb = (want + 255) / 256 * 256;
   return (uint32_t)std::min<uint64_t>(kCountMaxBlockVerts, std::max<uint64_t>(256, vb));
 }
