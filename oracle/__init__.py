@@ -78,6 +78,8 @@ def _load():
     lib.orc_arc_hash.restype = u32
     lib.orc_sigma_count_arcs.argtypes = [u32, vp, vp, dbl, vp, u32, u32, vp, u32, C.c_int]
     lib.orc_sigma_count_arcs.restype = i64
+    lib.orc_celf_arcs.argtypes = [u32, vp, vp, dbl, vp, u32, u32, u32, vp, vp, vp, vp]
+    lib.orc_celf_arcs.restype = C.c_int
     _lib = lib
     return lib
 
@@ -202,6 +204,29 @@ def sigma_count(g, s: Sampler, S, threads: int = 1) -> int:
     r = lib.orc_sigma_count(*a, _ptr(S), int(S.size), int(threads))
     del keep
     return int(r)
+
+
+def celf_arcs(g, s: Sampler, K: int) -> dict:
+    """Lazy greedy on a digraph (hash sampling): seeds, marginal counts,
+    cover count and the number of evaluations."""
+    if not getattr(g, "directed", False) or s.mode != MODE_HASH:
+        raise ValueError("celf_arcs takes a digraph and hash sampling")
+    lib = _load()
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(g.col, dtype=np.uint32)
+    p_slot = s.p_slot if s.p_slot is not None else (
+        None if g.p_slot is None else np.ascontiguousarray(g.p_slot, np.float64))
+    seeds = np.zeros(max(K, 1), dtype=np.uint32)
+    marg = np.zeros(max(K, 1), dtype=np.int64)
+    cover = C.c_int64()
+    evals = C.c_uint64()
+    rc = lib.orc_celf_arcs(g.n, _ptr(rp), _ptr(col), s.p, _ptr(p_slot), s.R, s.seed, int(K), _ptr(seeds),
+                           _ptr(marg), C.byref(cover), C.byref(evals))
+    if rc == -2:
+        raise ValueError("K > n")
+    if rc != 0:
+        raise RuntimeError("oracle: allocation failure")
+    return {"seeds": seeds[:K], "marginal": marg[:K], "cover": int(cover.value), "evals": int(evals.value)}
 
 
 def gain(g, s: Sampler, u: int, seed_set=(), threads: int = 1) -> int:

@@ -24,7 +24,9 @@
  *   - sigma(S) counts: sum over samples of the number of vertices reachable
  *     from S (Algorithm 4 without the division by R);
  *   - the same count on a digraph, where an arc is hashed from the ordered
- *     pair and reachability follows the arcs (orc_sigma_count_arcs).
+ *     pair and reachability follows the arcs (orc_sigma_count_arcs), and lazy
+ *     greedy on it with gains over uncovered reachable vertices
+ *     (orc_celf_arcs).
  *
  * Every count is an exact integer (int64).  sigma = count / R is formed only
  * by callers.
@@ -441,6 +443,107 @@ int64_t orc_sigma_count_arcs(uint32_t n, const uint64_t *row_ptr, const uint32_t
     run_jobs(&jb, threads);
     graph_free(&g);
     return (int64_t)jb.acc;
+}
+
+/* Greedy seed selection on a digraph by lazy evaluation (Algorithm 3 with the
+ * spread of orc_sigma_count_arcs): gain(u | S) = sum_r |R_r(u) \ R_r(S)|,
+ * the vertices reachable from u over live arcs of sample r and not from S.
+ * Lazy queue as orc_celf: the largest stale gain is re-evaluated unless it
+ * was computed for the current |S|, ties to the smaller id; every gain starts
+ * unevaluated (+infinity).  R_r(S) is kept as one bit per (sample, vertex). */
+int orc_celf_arcs(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, double p, const double *p_slot,
+                  uint32_t R, uint32_t seed, uint32_t K, uint32_t *seeds, int64_t *marginal,
+                  int64_t *cover_count, uint64_t *n_evals) {
+    if (K > n) return -2;
+    orc_graph g;
+    if (graph_init(&g, n, row_ptr, col, ORC_MODE_HASH, p, p_slot, R, seed, NULL)) return -1;
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) g.h_slot[j] = orc_arc_hash(seed, u, col[j], n);
+    const uint64_t words = ((uint64_t)n + 63) / 64;
+    const uint64_t cov_words = words * R;
+    uint64_t *cov = (uint64_t *)calloc((size_t)(cov_words ? cov_words : 1), sizeof(uint64_t));
+    int64_t *mg = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t *iter = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    uint8_t *is_seed = (uint8_t *)calloc(n ? n : 1, 1);
+    uint32_t *queue = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint32_t *mark = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+    if (!cov || !mg || !iter || !is_seed || !queue || !mark) return -1;
+    for (uint32_t v = 0; v < n; ++v) {
+        mg[v] = INT64_MAX;
+        iter[v] = -1;
+    }
+    uint32_t stamp = 0, s_size = 0;
+    int64_t cover = 0;
+    uint64_t evals = 0;
+    while (s_size < K) {
+        int64_t best = -1;
+        uint32_t top = 0;
+        for (uint32_t v = 0; v < n; ++v)
+            if (!is_seed[v] && mg[v] > best) {
+                best = mg[v];
+                top = v;
+            }
+        if (iter[top] == (int64_t)s_size) {
+            /* commit: add R_r(top) to the covered sets */
+            for (uint32_t r = 0; r < R; ++r) {
+                uint64_t *cr = cov + (uint64_t)r * words;
+                if ((cr[top >> 6] >> (top & 63)) & 1u) continue;
+                uint32_t head = 0, tail = 0;
+                cr[top >> 6] |= 1ull << (top & 63);
+                queue[tail++] = top;
+                while (head < tail) {
+                    uint32_t u = queue[head++];
+                    for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+                        uint32_t w = col[j];
+                        if (!((cr[w >> 6] >> (w & 63)) & 1u) && slot_live(&g, j, r)) {
+                            cr[w >> 6] |= 1ull << (w & 63);
+                            queue[tail++] = w;
+                        }
+                    }
+                }
+            }
+            seeds[s_size] = top;
+            marginal[s_size] = mg[top];
+            cover += mg[top];
+            is_seed[top] = 1;
+            ++s_size;
+        } else {
+            /* gain: vertices reachable from top and not covered, per sample */
+            int64_t gsum = 0;
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint64_t *cr = cov + (uint64_t)r * words;
+                if ((cr[top >> 6] >> (top & 63)) & 1u) continue;
+                ++stamp;
+                uint32_t head = 0, tail = 0;
+                mark[top] = stamp;
+                queue[tail++] = top;
+                while (head < tail) {
+                    uint32_t u = queue[head++];
+                    for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+                        uint32_t w = col[j];
+                        if (mark[w] != stamp && !((cr[w >> 6] >> (w & 63)) & 1u) && slot_live(&g, j, r)) {
+                            mark[w] = stamp;
+                            queue[tail++] = w;
+                        }
+                    }
+                }
+                gsum += tail;
+            }
+            mg[top] = gsum;
+            iter[top] = s_size;
+            ++evals;
+        }
+    }
+    *cover_count = cover;
+    if (n_evals) *n_evals = evals;
+    free(cov);
+    free(mg);
+    free(iter);
+    free(is_seed);
+    free(queue);
+    free(mark);
+    graph_free(&g);
+    return 0;
 }
 
 /* Marginal gain of u given the seed set marked in is_seed (may be NULL for

@@ -121,3 +121,45 @@ def test_weighted_cascade_matches_scipy():
     S = [1, 7, 20]
     want = sum(_reach_scipy(g, live[:, r], S) for r in range(R))
     assert oracle.sigma_count(g, oracle.Sampler("hash", R=R, seed=seed), S, threads=3) == want
+
+
+def _greedy_scipy(g, live, K):
+    """Plain greedy by exhaustive evaluation: per step every unselected vertex's
+    spread with the current seeds, via scipy reachability; ties to the smaller id."""
+    R = live.shape[1]
+    S, marg = [], []
+    base = 0
+    for _ in range(K):
+        best, arg = -1, None
+        for u in range(g.n):
+            if u in S:
+                continue
+            tot = sum(_reach_scipy(g, live[:, r], S + [u]) for r in range(R))
+            if tot - base > best:
+                best, arg = tot - base, u
+        S.append(arg)
+        marg.append(best)
+        base += best
+    return S, marg
+
+
+@pytest.mark.parametrize("n,m,p,R,K,seed", [(10, 25, 0.35, 8, 4, 1), (14, 40, 0.2, 6, 5, 2), (9, 30, 0.6, 5, 9, 3)])
+def test_directed_lazy_greedy_equals_plain_greedy(n, m, p, R, K, seed):
+    g = random_small_digraph(n, m, seed)
+    live = _live(g, np.full(g.nnz, p), R, seed)
+    want_s, want_m = _greedy_scipy(g, live, K)
+    got = oracle.celf_arcs(g, oracle.Sampler("hash", p=p, R=R, seed=seed), K)
+    assert list(got["seeds"]) == want_s
+    assert list(got["marginal"]) == want_m
+    assert got["cover"] == sum(want_m)
+    assert got["cover"] == oracle.sigma_count(g, oracle.Sampler("hash", p=p, R=R, seed=seed), want_s)
+
+
+def test_directed_greedy_marginals_do_not_increase_and_k_over_n_fails():
+    g = random_small_digraph(30, 120, 9)
+    g.p_slot = wc_p(g)
+    r = oracle.celf_arcs(g, oracle.Sampler("hash", R=32, seed=9), 30)
+    assert np.all(np.diff(r["marginal"]) <= 0)
+    assert r["cover"] == 32 * 30  # every vertex reached once all are seeds
+    with pytest.raises(ValueError):
+        oracle.celf_arcs(g, oracle.Sampler("hash", R=4, seed=9), 31)
