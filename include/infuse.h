@@ -159,6 +159,19 @@ im_status im_estimate_sigma(im_graph *g, const uint32_t *S, uint32_t s_len, int6
 im_status im_estimate_sigma_direct(im_graph *g, const uint32_t *S, uint32_t s_len, int64_t *count,
                                    double *sigma, uint32_t *levels);
 
+/* Greedy selection of K seeds without a memo, for graphs whose memo would
+ * not fit and for directed graphs (whose spread is reachability, not
+ * connectivity; the paper leaves them to future work): the marginal gain of
+ * u is sum_r |R_r(u) \ R_r(S)|, the vertices reachable from u over the live
+ * edges (arcs) of sample r and not from the seeds, computed by searches of
+ * all samples at once, many candidates side by side.  Same queue and
+ * tie-breaking as im_select_seeds (on an undirected graph the result is the
+ * same), same outputs and errors.  Needs about 3 n R / 8 bytes per
+ * candidate searched side by side (up to 256, within 4 GiB) plus the
+ * sampler state; meant for graphs of up to about 10^5 vertices. */
+im_status im_select_seeds_direct(im_graph *g, uint32_t K, uint32_t *seeds, int64_t *marginal,
+                                 int64_t *cover_count);
+
 /* Copies component labels of simulations first_sample .. first_sample +
  * n_samples - 1 for every vertex into host[n][n_samples] (vertex-major).
  * Errors: IM_ERR_INVALID_ARG when the range exceeds R. */

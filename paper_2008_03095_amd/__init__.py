@@ -212,6 +212,15 @@ class Graph:
                                           C.byref(cnt), C.byref(sig)))
         return int(cnt.value), float(sig.value)
 
+    def select_seeds_direct(self, K: int):
+        """Greedy selection without a memo (im_select_seeds_direct), also for
+        directed graphs: (seeds, marginal, cover)."""
+        seeds = np.zeros(max(K, 1), dtype=np.uint32)
+        marg = np.zeros(max(K, 1), dtype=np.int64)
+        cover = C.c_int64()
+        check(self._lib.im_select_seeds_direct(self.handle, int(K), _ptr(seeds), _ptr(marg), C.byref(cover)))
+        return seeds[:K], marg[:K], int(cover.value)
+
     def estimate_sigma_direct(self, S: Sequence[int]):
         """sigma(S) without a memo (im_estimate_sigma_direct): (count, sigma, levels)."""
         arr = np.ascontiguousarray(np.asarray(S, dtype=np.uint32))

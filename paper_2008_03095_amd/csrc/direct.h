@@ -5,8 +5,12 @@
 
 namespace infuse {
 
+// Several searches can run side by side as copies of the graph: virtual
+// vertex c * gn + v is vertex v of copy c (gn = the graph's n); n counts the
+// virtual vertices.  A copy's arrays are those of one search.
 struct BfsView {
   uint32_t n, ntiles;
+  uint32_t gn;          // vertices of the graph (n / copies)
   uint64_t* V;          // [n][ntiles][4] visited columns (ballot layout)
   const uint64_t* F;    // frontier of this level
   uint64_t* N;          // frontier of the next level
@@ -21,5 +25,10 @@ void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, u
                       hipStream_t st);
 void launch_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t ntiles, hipStream_t st);
 void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st);
+// Set bits of each copy's words: out[c] += popcount(V[c * words .. (c + 1) * words)).
+void launch_bfs_count_copies(const uint64_t* V, uint64_t words, uint32_t copies, unsigned long long* out,
+                             hipStream_t st);
+// V[c * words + i] = src[i] for every copy c < copies.
+void launch_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words, uint32_t copies, hipStream_t st);
 
 }  // namespace infuse

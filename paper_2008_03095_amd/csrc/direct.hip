@@ -28,15 +28,18 @@ __device__ inline uint64_t valid_word(uint32_t R, uint32_t t, uint32_t i) {
   return w;
 }
 
-// Seeds: every sample column of every tile is visited and in the frontier.
+// Seeds (virtual ids): every sample column of every tile is visited; the
+// columns where the seed was not visited before join the frontier (V may
+// start from a covered set, whose vertices add nothing).
 __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t len) {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (uint64_t)len * m.ntiles * 4) return;
   const uint32_t s = (uint32_t)(k / (m.ntiles * 4)), r = (uint32_t)(k % (m.ntiles * 4));
   const uint32_t v = S[s], t = r / 4, i = r % 4;
   const uint64_t w = valid_word(m.R, t, i);
-  b.V[((uint64_t)v * m.ntiles + t) * 4 + i] = w;
-  b.N[((uint64_t)v * m.ntiles + t) * 4 + i] = w;
+  const uint64_t old = b.V[((uint64_t)v * m.ntiles + t) * 4 + i];
+  b.V[((uint64_t)v * m.ntiles + t) * 4 + i] = old | w;
+  b.N[((uint64_t)v * m.ntiles + t) * 4 + i] = w & ~old;
   if (r == 0) {
     b.stamp[v] = 1;
     b.next[s] = v;
@@ -50,8 +53,9 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint64_t items = (uint64_t)ncur * m.ntiles;
   for (uint64_t it = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += nw) {
-    const uint32_t v = uni(b.cur[it / m.ntiles]), t = (uint32_t)(it % m.ntiles);
-    const uint64_t* fw = b.F + ((uint64_t)v * m.ntiles + t) * 4;
+    const uint32_t vv = uni(b.cur[it / m.ntiles]), t = (uint32_t)(it % m.ntiles);
+    const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
+    const uint64_t* fw = b.F + ((uint64_t)vv * m.ntiles + t) * 4;
     const uint64_t f0 = fw[0], f1 = fw[1], f2 = fw[2], f3 = fw[3];
     if (!(f0 | f1 | f2 | f3)) continue;
     uint32_t fb[4];
@@ -80,7 +84,8 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
             any = any || lb[i];
           }
           if (!__ballot(any)) return;
-          uint64_t* vw = b.V + ((uint64_t)u * m.ntiles + t) * 4;
+          const uint32_t uv = cb + u;  // virtual id of the neighbour
+          uint64_t* vw = b.V + ((uint64_t)uv * m.ntiles + t) * 4;
           const uint64_t v0 = vw[0], v1 = vw[1], v2 = vw[2], v3 = vw[3];
           const uint64_t n0 = __ballot(lb[0] && !((v0 >> lane) & 1u));
           const uint64_t n1 = __ballot(lb[1] && !((v1 >> lane) & 1u));
@@ -88,14 +93,14 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
           const uint64_t n3 = __ballot(lb[3] && !((v3 >> lane) & 1u));
           if (!(n0 | n1 | n2 | n3)) return;
           if (lane == 0) {
-            uint64_t* nw4 = b.N + ((uint64_t)u * m.ntiles + t) * 4;
+            uint64_t* nw4 = b.N + ((uint64_t)uv * m.ntiles + t) * 4;
             const uint64_t nn[4] = {n0, n1, n2, n3};
             for (int i = 0; i < 4; ++i)
               if (nn[i]) {
                 atomicOr((unsigned long long*)&vw[i], (unsigned long long)nn[i]);
                 atomicOr((unsigned long long*)&nw4[i], (unsigned long long)nn[i]);
               }
-            if (atomicMax(&b.stamp[u], level + 1) < level + 1) b.next[atomicAdd(b.ncount, 1u)] = u;
+            if (atomicMax(&b.stamp[uv], level + 1) < level + 1) b.next[atomicAdd(b.ncount, 1u)] = uv;
           }
         });
   }
@@ -116,6 +121,24 @@ __global__ void k_bfs_count(const uint64_t* V, uint64_t words, unsigned long lon
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+// Per-copy counts: block (x, c) sums a stretch of copy c's words.
+__global__ void k_bfs_count_copies(const uint64_t* V, uint64_t words, unsigned long long* out) {
+  const uint32_t c = blockIdx.y;
+  const uint64_t* p = V + (uint64_t)c * words;
+  uint64_t cnt = 0;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (uint64_t)gridDim.x * blockDim.x)
+    cnt += (uint64_t)__popcll(p[k]);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&out[c], (unsigned long long)cnt);
+}
+
+__global__ void k_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words) {
+  const uint32_t c = blockIdx.y;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (uint64_t)gridDim.x * blockDim.x)
+    V[(uint64_t)c * words + k] = src[k];
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -143,6 +166,19 @@ void launch_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t 
 void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st) {
   const uint32_t blocks = (uint32_t)std::min<uint64_t>(8192, (words + 255) / 256);
   hipLaunchKernelGGL(k_bfs_count, dim3(std::max(1u, blocks)), dim3(256), 0, st, V, words, out);
+}
+
+void launch_bfs_count_copies(const uint64_t* V, uint64_t words, uint32_t copies, unsigned long long* out,
+                             hipStream_t st) {
+  if (!copies) return;
+  const uint32_t bx = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (words + 255) / 256));
+  hipLaunchKernelGGL(k_bfs_count_copies, dim3(bx, copies), dim3(256), 0, st, V, words, out);
+}
+
+void launch_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words, uint32_t copies, hipStream_t st) {
+  if (!copies || !words) return;
+  const uint32_t bx = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (words + 255) / 256));
+  hipLaunchKernelGGL(k_bfs_replicate, dim3(bx, copies), dim3(256), 0, st, src, V, words);
 }
 
 }  // namespace infuse

@@ -1204,6 +1204,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   hipError_t e = hipMemcpyAsync(dS, set.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
   BfsView bv;
   bv.n = n;
+  bv.gn = n;
   bv.ntiles = ntiles;
   bv.V = V;
   bv.F = nullptr;
@@ -1242,6 +1243,167 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   if (count) *count = (int64_t)h;
   if (sigma) *sigma = (double)h / (double)R;
   if (levels) *levels = level - 1;
+  return IM_OK;
+}
+
+// Greedy selection without a memo.  The gains are spreads over uncovered
+// vertices, computed by the level-synchronous search: a batch of candidates
+// is searched side by side as copies of the graph, each copy's visited set
+// starting from the covered set R_r(S) of every sample, so a copy's new bits
+// are the candidate's gain.  The lazy queue (on the host) commits the largest
+// key when it is fresh, ties to the smaller id, and otherwise re-evaluates
+// the largest stale keys, as many as fit side by side; every key starts
+// unevaluated.  A commit grows the covered set by one more search.
+extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* seeds, int64_t* marginal,
+                                            int64_t* cover_count) {
+  if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  if (K > g->n) return fail(IM_ERR_INVALID_ARG, "K = %u exceeds n = %u", K, g->n);
+  if (K && (!seeds || !marginal)) return fail(IM_ERR_INVALID_ARG, "NULL output array");
+  if (cover_count) *cover_count = 0;
+  if (K == 0) return IM_OK;
+  im_ctx* c = g->ctx;
+  hipStream_t st = c->stream;
+  const uint32_t n = g->n, R = g->R, Rs = round_up(R, kTile), ntiles = Rs / kTile;
+  const uint64_t T = thr_of(g->p);
+  const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
+  const uint64_t per_copy = 3 * words * 8 + 3 * (uint64_t)n * 4;
+  const uint64_t copy_budget = 4ull << 30;
+  const uint32_t copies = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({256, n, copy_budget / per_copy}));
+  const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
+  const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
+  const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
+  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256((size_t)(copies + 8) * 8);
+  const size_t b_S = align256((size_t)copies * 4);
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 3 * b_list + b_cnt + b_S;
+  void* base = nullptr;
+  im_status s = ctx_alloc(c, total, &base);
+  if (s != IM_OK) return s;
+  char* p8 = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* r = p8;
+    p8 += bytes;
+    return r;
+  };
+  MemoView mv = {};
+  mv.n = n;
+  mv.R = R;
+  mv.Rs = Rs;
+  mv.ntiles = ntiles;
+  mv.never_live = (!g->per_edge && T == 0) ? 1u : 0u;
+  mv.tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
+  mv.kshift = bitlen32(mv.tm1);
+  uint2* edges = reinterpret_cast<uint2*>(take(b_edges));
+  uint32_t* xs = reinterpret_cast<uint32_t*>(take(b_x));
+  uint32_t* inv = reinterpret_cast<uint32_t*>(take(b_x));
+  uint32_t* pos = reinterpret_cast<uint32_t*>(take(b_pos));
+  uint64_t* scr = reinterpret_cast<uint64_t*>(take(b_scr));
+  uint64_t* Vs = reinterpret_cast<uint64_t*>(take(b_one));  // covered: R_r(S), one copy
+  uint64_t* V = reinterpret_cast<uint64_t*>(take(b_many));
+  uint64_t* A = reinterpret_cast<uint64_t*>(take(b_many));
+  uint64_t* B = reinterpret_cast<uint64_t*>(take(b_many));
+  uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
+  uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
+  uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(take(b_cnt));  // [0] list size, [8..] counts
+  uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
+  mv.edges = edges;
+  mv.xs = xs;
+  const GraphView gv = g->view();
+  launch_edge_hash(gv, g->seed, edges, st);
+  launch_x_sort(g->seed, R, Rs, scr, xs, inv, pos, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(Vs), words * 2, 0u, st);
+  hipError_t e = hipSuccess;
+  std::vector<uint32_t> hsrc(copies);
+  std::vector<unsigned long long> hcnt(copies);
+  // searches from the sources src[c] of copies 0 .. nc-1, each over the
+  // visited set Vv (nc copies); the frontier sets start zero
+  auto search = [&](uint64_t* Vv, uint32_t nc) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(A), words * 2 * nc, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(B), words * 2 * nc, 0u, st);
+    launch_fill_u32(stamp, (uint64_t)n * nc, 0u, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dS, hsrc.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st);
+    BfsView bv;
+    bv.n = n * nc;
+    bv.gn = n;
+    bv.ntiles = ntiles;
+    bv.V = Vv;
+    bv.F = nullptr;
+    bv.N = A;
+    bv.cur = nullptr;
+    bv.next = L0;
+    bv.ncount = reinterpret_cast<uint32_t*>(cnt);
+    bv.stamp = stamp;
+    launch_bfs_seed(mv, bv, dS, nc, st);
+    uint64_t* fa = A;
+    uint64_t* fb = B;
+    uint32_t* la = L0;
+    uint32_t* lb = L1;
+    uint32_t ncur = nc, level = 1;
+    while (e == hipSuccess && ncur) {
+      bv.F = fa;
+      bv.N = fb;
+      bv.cur = la;
+      bv.next = lb;
+      launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 1, 0u, st);
+      launch_bfs_level(gv, mv, bv, ncur, level, st);
+      uint32_t nnext = 0;
+      e = hipMemcpyAsync(&nnext, cnt, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      launch_bfs_clear(fa, la, ncur, ntiles, st);
+      std::swap(fa, fb);
+      std::swap(la, lb);
+      ncur = nnext;
+      ++level;
+    }
+  };
+  std::vector<int64_t> key(n, INT64_MAX), when(n, -1);
+  std::vector<uint8_t> chosen(n, 0);
+  std::vector<uint32_t> order;
+  int64_t cover = 0;
+  uint64_t evals = 0;
+  {
+    KTimer t(c, "select_direct", st);
+    uint32_t step = 0;
+    auto before = [&](uint32_t a, uint32_t b) { return key[a] != key[b] ? key[a] > key[b] : a < b; };
+    while (e == hipSuccess && step < K) {
+      uint32_t top = kInvalid;
+      for (uint32_t v = 0; v < n; ++v)
+        if (!chosen[v] && (top == kInvalid || before(v, top))) top = v;
+      if (when[top] == (int64_t)step) {  // fresh: the exact maximiser
+        hsrc[0] = top;
+        search(Vs, 1);
+        seeds[step] = top;
+        marginal[step] = key[top];
+        cover += key[top];
+        chosen[top] = 1;
+        ++step;
+        continue;
+      }
+      // the largest stale keys, as many as fit side by side
+      order.clear();
+      for (uint32_t v = 0; v < n; ++v)
+        if (!chosen[v] && when[v] != (int64_t)step) order.push_back(v);
+      const uint32_t nc = std::min<uint32_t>(copies, (uint32_t)order.size());
+      std::partial_sort(order.begin(), order.begin() + nc, order.end(), before);
+      for (uint32_t i = 0; i < nc; ++i) hsrc[i] = i * n + order[i];
+      launch_bfs_replicate(Vs, V, words, nc, st);
+      search(V, nc);
+      launch_fill_u32(reinterpret_cast<uint32_t*>(cnt + 8), (uint64_t)nc * 2, 0u, st);
+      launch_bfs_count_copies(V, words, nc, cnt + 8, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(hcnt.data(), cnt + 8, (size_t)nc * 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      for (uint32_t i = 0; i < nc; ++i) {
+        key[order[i]] = (int64_t)hcnt[i] - cover;  // bits of the copy beyond the covered set
+        when[order[i]] = step;
+      }
+      evals += nc;
+    }
+  }
+  ctx_free(c, base);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free selection failed: %s", hipGetErrorString(e));
+  if (cover_count) *cover_count = cover;
+  g->last_evals = evals;
   return IM_OK;
 }
 
