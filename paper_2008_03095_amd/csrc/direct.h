@@ -18,12 +18,15 @@ struct BfsView {
   uint32_t* next;       // frontier vertices of the next level
   uint32_t* ncount;     // |next|
   uint32_t* stamp;      // [n] last level a vertex joined a frontier list
+  uint32_t* levels;     // largest level with a non-empty frontier
 };
 
 void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st);
-void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t ncur, uint32_t level,
-                      hipStream_t st);
-void launch_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t ntiles, hipStream_t st);
+// The frontier size is read on the device (*ncur), so levels can be
+// enqueued without waiting for the host; an empty frontier makes both no-ops.
+void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, const uint32_t* ncur,
+                      uint32_t level, hipStream_t st);
+void launch_bfs_clear(uint64_t* F, const uint32_t* cur, const uint32_t* ncur, uint32_t ntiles, hipStream_t st);
 void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st);
 // Set bits of each copy's words: out[c] += popcount(V[c * words .. (c + 1) * words)).
 void launch_bfs_count_copies(const uint64_t* V, uint64_t words, uint32_t copies, unsigned long long* out,

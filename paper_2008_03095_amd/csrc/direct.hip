@@ -47,8 +47,11 @@ __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t le
 }
 
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsView b, uint32_t ncur,
+__global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsView b, const uint32_t* ncur_p,
                                                    uint32_t level) {
+  const uint32_t ncur = *ncur_p;
+  if (ncur == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(b.levels, level);
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint64_t items = (uint64_t)ncur * m.ntiles;
@@ -107,11 +110,12 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
 }
 
 // Clears the frontier words of this level's vertices.
-__global__ void k_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t ntiles) {
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (uint64_t)ncur * ntiles * 4) return;
-  const uint32_t v = cur[k / (ntiles * 4)];
-  F[(uint64_t)v * ntiles * 4 + k % (ntiles * 4)] = 0;
+__global__ void k_bfs_clear(uint64_t* F, const uint32_t* cur, const uint32_t* ncur_p, uint32_t ntiles) {
+  const uint64_t total = (uint64_t)(*ncur_p) * ntiles * 4;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = cur[k / (ntiles * 4)];
+    F[(uint64_t)v * ntiles * 4 + k % (ntiles * 4)] = 0;
+  }
 }
 
 __global__ void k_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out) {
@@ -148,19 +152,19 @@ void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uin
   if (k) hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, m, b, S, len);
 }
 
-void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t ncur, uint32_t level,
-                      hipStream_t st) {
-  const uint64_t waves = (uint64_t)ncur * m.ntiles;
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(65536, (waves + 3) / 4);
+// Fixed grids (the frontier size is known only on the device): enough
+// wavefronts to fill the device, striding over the (vertex, tile) items.
+void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, const uint32_t* ncur,
+                      uint32_t level, hipStream_t st) {
+  constexpr uint32_t kBlocks = 16384;
   if (g.tm1)
-    hipLaunchKernelGGL(k_bfs_level<true>, dim3(blocks), dim3(256), 0, st, g, m, b, ncur, level);
+    hipLaunchKernelGGL(k_bfs_level<true>, dim3(kBlocks), dim3(256), 0, st, g, m, b, ncur, level);
   else
-    hipLaunchKernelGGL(k_bfs_level<false>, dim3(blocks), dim3(256), 0, st, g, m, b, ncur, level);
+    hipLaunchKernelGGL(k_bfs_level<false>, dim3(kBlocks), dim3(256), 0, st, g, m, b, ncur, level);
 }
 
-void launch_bfs_clear(uint64_t* F, const uint32_t* cur, uint32_t ncur, uint32_t ntiles, hipStream_t st) {
-  const uint64_t k = (uint64_t)ncur * ntiles * 4;
-  if (k) hipLaunchKernelGGL(k_bfs_clear, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, F, cur, ncur, ntiles);
+void launch_bfs_clear(uint64_t* F, const uint32_t* cur, const uint32_t* ncur, uint32_t ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_bfs_clear, dim3(1024), dim3(256), 0, st, F, cur, ncur, ntiles);
 }
 
 void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st) {

@@ -1139,6 +1139,44 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   return s;
 }
 
+// Runs a level-synchronous search whose first frontier (list la, its size in
+// cnt[0]) is in place: cnt[1] must be 0.  Levels are enqueued eight at a time
+// and the host looks at the frontier size only between groups (levels past
+// the last are no-ops).  *levels receives the number of non-empty levels.
+static hipError_t bfs_levels(const GraphView& gv, const MemoView& mv, BfsView bv, uint64_t* fa, uint64_t* fb,
+                             uint32_t* la, uint32_t* lb, uint32_t* cnt, hipStream_t st, uint32_t* levels) {
+  constexpr int kGroup = 8;
+  uint32_t* ca = cnt;
+  uint32_t* cb = cnt + 1;
+  bv.levels = cnt + 2;
+  launch_fill_u32(cnt + 2, 1, 0u, st);
+  hipError_t e = hipSuccess;
+  for (uint32_t level = 1;;) {
+    for (int k = 0; k < kGroup; ++k, ++level) {
+      bv.F = fa;
+      bv.N = fb;
+      bv.cur = la;
+      bv.next = lb;
+      bv.ncount = cb;
+      launch_bfs_level(gv, mv, bv, ca, level, st);
+      launch_bfs_clear(fa, la, ca, mv.ntiles, st);  // fa is all zero again
+      launch_fill_u32(ca, 1, 0u, st);               // becomes the next level's next count
+      std::swap(fa, fb);
+      std::swap(la, lb);
+      std::swap(ca, cb);
+    }
+    uint32_t h = 0;
+    e = hipMemcpyAsync(&h, ca, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess || h == 0) break;
+  }
+  uint32_t lv = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&lv, cnt + 2, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (levels) *levels = lv;
+  return e;
+}
+
 extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, uint32_t s_len, int64_t* count,
                                               double* sigma, uint32_t* levels) {
   if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
@@ -1193,7 +1231,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0] next-list size, [2..3] result
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..1] list sizes, [2] levels, [4..5] result
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
   mv.edges = edges;
   mv.xs = xs;
@@ -1214,35 +1252,21 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   bv.ncount = cnt;
   bv.stamp = stamp;
   launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
-  uint32_t ncur = len, level = 1;
+  launch_fill_u32(cnt, 1, len, st);
+  uint32_t nlev = 0;
   {
     KTimer t(c, "sigma_direct", st);
-    while (e == hipSuccess && ncur) {
-      bv.F = A;
-      bv.N = B;
-      bv.cur = L0;
-      bv.next = L1;
-      launch_fill_u32(cnt, 1, 0u, st);
-      launch_bfs_level(gv, mv, bv, ncur, level, st);
-      uint32_t nnext = 0;
-      e = hipMemcpyAsync(&nnext, cnt, 4, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      launch_bfs_clear(A, L0, ncur, ntiles, st);  // A is all zero again
-      std::swap(A, B);
-      std::swap(L0, L1);
-      ncur = nnext;
-      ++level;
-    }
-    if (e == hipSuccess) launch_bfs_count(V, words, reinterpret_cast<unsigned long long*>(cnt + 2), st);
+    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, cnt, st, &nlev);
+    if (e == hipSuccess) launch_bfs_count(V, words, reinterpret_cast<unsigned long long*>(cnt + 4), st);
   }
   unsigned long long h = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt + 2, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt + 4, 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free sigma failed: %s", hipGetErrorString(e));
   if (count) *count = (int64_t)h;
   if (sigma) *sigma = (double)h / (double)R;
-  if (levels) *levels = level - 1;
+  if (levels) *levels = nlev;
   return IM_OK;
 }
 
@@ -1305,7 +1329,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
-  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(take(b_cnt));  // [0] list size, [8..] counts
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(take(b_cnt));  // [0..1] level state, [8..] counts
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
   mv.edges = edges;
   mv.xs = xs;
@@ -1334,28 +1358,12 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
     bv.next = L0;
     bv.ncount = reinterpret_cast<uint32_t*>(cnt);
     bv.stamp = stamp;
+    bv.levels = nullptr;
     launch_bfs_seed(mv, bv, dS, nc, st);
-    uint64_t* fa = A;
-    uint64_t* fb = B;
-    uint32_t* la = L0;
-    uint32_t* lb = L1;
-    uint32_t ncur = nc, level = 1;
-    while (e == hipSuccess && ncur) {
-      bv.F = fa;
-      bv.N = fb;
-      bv.cur = la;
-      bv.next = lb;
-      launch_fill_u32(reinterpret_cast<uint32_t*>(cnt), 1, 0u, st);
-      launch_bfs_level(gv, mv, bv, ncur, level, st);
-      uint32_t nnext = 0;
-      e = hipMemcpyAsync(&nnext, cnt, 4, hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      launch_bfs_clear(fa, la, ncur, ntiles, st);
-      std::swap(fa, fb);
-      std::swap(la, lb);
-      ncur = nnext;
-      ++level;
-    }
+    uint32_t* c3 = reinterpret_cast<uint32_t*>(cnt);
+    launch_fill_u32(c3, 1, nc, st);
+    launch_fill_u32(c3 + 1, 1, 0u, st);
+    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, c3, st, nullptr);
   };
   std::vector<int64_t> key(n, INT64_MAX), when(n, -1);
   std::vector<uint8_t> chosen(n, 0);
