@@ -9,10 +9,13 @@
 // its frontier is not empty, the candidate edges of the tile (tile
 // prefilter), and ors the columns where the edge is live and the vertex is
 // in the frontier into V and the next frontier N of the neighbour; a
-// neighbour that gains columns joins the next frontier list once (level
-// stamp).  V and N are written only by atomics while a level runs (stale
-// reads of V only cause redundant atomics); F is read-only.  The count is
-// the number of set bits of V: sum over samples of |R_r(S)|, seeds included.
+// neighbour that gains columns is marked in a bitmap, which a second kernel
+// turns into the next frontier list (in vertex order).  V and N are written only by atomics while a level runs (stale
+// reads of V only cause redundant atomics); F is only read, then cleared by
+// the wavefront that owns the item, so both frontier sets are all zero again
+// once a search ends.  The count is the number of bits the search sets in V,
+// summed from the atomics' old values: sum over samples of |R_r(S)|, seeds
+// included (beyond the set V starts from).
 #include <algorithm>
 
 #include "common.h"
@@ -28,39 +31,74 @@ __device__ inline uint64_t valid_word(uint32_t R, uint32_t t, uint32_t i) {
   return w;
 }
 
+// New bits of a copy's count: summed over the wavefront, one atomic add by
+// lane 0 into one of the copy's slots.
+__device__ inline void add_count(const BfsView& b, uint32_t copy, uint32_t pc) {
+  uint32_t c = pc;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0 && c)
+    atomicAdd(&b.counts[(uint64_t)copy * kCountSlots + blockIdx.x % kCountSlots], (unsigned long long)c);
+}
+
 // Seeds (virtual ids): every sample column of every tile is visited; the
-// columns where the seed was not visited before join the frontier (V may
-// start from a covered set, whose vertices add nothing).
+// columns where the seed was not visited before join the frontier and the
+// count (V may start from a covered set, whose vertices add nothing).
+// Thread 0 also sets the list sizes of the first level (the seed list is
+// level 1's frontier, level 2's list starts empty) and the level count.
 __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t len) {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    b.lcount[1] = len;
+    b.lcount[2] = 0;
+    *b.levels = 0;
+  }
   if (k >= (uint64_t)len * m.ntiles * 4) return;
   const uint32_t s = (uint32_t)(k / (m.ntiles * 4)), r = (uint32_t)(k % (m.ntiles * 4));
   const uint32_t v = S[s], t = r / 4, i = r % 4;
   const uint64_t w = valid_word(m.R, t, i);
-  const uint64_t old = b.V[((uint64_t)v * m.ntiles + t) * 4 + i];
-  b.V[((uint64_t)v * m.ntiles + t) * 4 + i] = old | w;
-  b.N[((uint64_t)v * m.ntiles + t) * 4 + i] = w & ~old;
-  if (r == 0) {
-    b.stamp[v] = 1;
-    b.next[s] = v;
+  const uint64_t at = ((uint64_t)v * m.ntiles + t) * 4 + i;
+  const uint64_t nb = w & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)w);
+  if (nb) {
+    atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
+    atomicAdd(&b.counts[(uint64_t)(v / b.gn) * kCountSlots + k % kCountSlots], (unsigned long long)__popcll(nb));
   }
+  if (r == 0) b.next[s] = v;
 }
 
+// One level.  A wavefront takes (frontier vertex, tile) items; for each
+// candidate edge of the tile it forms the 256-bit set of columns where the
+// edge is live and the vertex is in the frontier, and parks it in four lanes
+// (lane 4j + i holds word i of the j-th pending target).  Sixteen targets
+// are then updated at once: each lane reads its word of V, ors the unseen
+// columns in (the atomic's old value decides which bits are new, so every
+// bit is counted once), adds the new ones to N, and one lane per target
+// that gained columns marks it in the next frontier's bitmap.  The item's
+// frontier words are cleared once read: each (vertex, tile) is one item of
+// the level.
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsView b, const uint32_t* ncur_p,
-                                                   uint32_t level) {
-  const uint32_t ncur = *ncur_p;
+__global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsView b, uint32_t level) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.lcount[(level + 2) % 3] = 0;  // the next level's next list
+  const uint32_t ncur = b.lcount[level % 3];
   if (ncur == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(b.levels, level);
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63, wsel = lane & 3, pslot = lane >> 2;
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint64_t items = (uint64_t)ncur * m.ntiles;
+  uint32_t pc = 0;        // new bits set by this lane for copy pcopy
+  uint32_t pcopy = 0;
   for (uint64_t it = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += nw) {
     const uint32_t vv = uni(b.cur[it / m.ntiles]), t = (uint32_t)(it % m.ntiles);
     const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
-    const uint64_t* fw = b.F + ((uint64_t)vv * m.ntiles + t) * 4;
+    if (cb / b.gn != pcopy) {  // counts are added when the copy changes, and at the end
+      if (__ballot(pc != 0)) add_count(b, pcopy, pc);
+      pc = 0;
+      pcopy = cb / b.gn;
+    }
+    uint64_t* fw = b.F + ((uint64_t)vv * m.ntiles + t) * 4;
     const uint64_t f0 = fw[0], f1 = fw[1], f2 = fw[2], f3 = fw[3];
     if (!(f0 | f1 | f2 | f3)) continue;
+    if (lane < 4) fw[lane] = 0;
     uint32_t fb[4];
     fb[0] = (uint32_t)(f0 >> lane) & 1u;
     fb[1] = (uint32_t)(f1 >> lane) & 1u;
@@ -77,66 +115,75 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
       rh = e.y;
       if (PER_EDGE) rtm1 = g.tm1[beg + lane];
     }
+    uint32_t pu = 0;   // this lane's pending target (graph id)
+    uint64_t pm = 0;   // word wsel of its live frontier columns
+    uint32_t np = 0;   // pending targets (uniform)
+    auto flush = [&]() {
+      uint64_t nb = 0;
+      if (pm) {
+        const uint64_t at = ((uint64_t)(cb + pu) * m.ntiles + t) * 4 + wsel;
+        const uint64_t want = pm & ~b.V[at];  // a stale word only costs an atomic
+        if (want) {
+          nb = want & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)want);
+          if (nb) atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
+        }
+      }
+      pc += (uint32_t)__popcll(nb);
+      const uint64_t hit = __ballot(nb != 0);
+      if (wsel == 0 && pslot < np && ((hit >> lane) & 0xFull)) {
+        const uint32_t uv = cb + pu;
+        atomicOr((unsigned long long*)&b.nbits[uv >> 6], 1ull << (uv & 63));
+      }
+      np = 0;
+      pm = 0;
+    };
     for_candidates<PER_EDGE, false>(
         g, m, v, beg, end, end, lane, inreg, rcol, rh, rtm1, tc, [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
           uint32_t lb[4];
-          bool any = false;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            lb[i] = (fb[i] && tc.valid[i] && (h ^ tc.x[i]) <= tt) ? 1u : 0u;
-            any = any || lb[i];
+          for (int i = 0; i < 4; ++i) lb[i] = (fb[i] && tc.valid[i] && (h ^ tc.x[i]) <= tt) ? 1u : 0u;
+          const uint64_t w0 = __ballot(lb[0]), w1 = __ballot(lb[1]), w2 = __ballot(lb[2]), w3 = __ballot(lb[3]);
+          if (!(w0 | w1 | w2 | w3)) return;
+          if (pslot == np) {
+            pu = u;
+            pm = wsel == 0 ? w0 : wsel == 1 ? w1 : wsel == 2 ? w2 : w3;
           }
-          if (!__ballot(any)) return;
-          const uint32_t uv = cb + u;  // virtual id of the neighbour
-          uint64_t* vw = b.V + ((uint64_t)uv * m.ntiles + t) * 4;
-          const uint64_t v0 = vw[0], v1 = vw[1], v2 = vw[2], v3 = vw[3];
-          const uint64_t n0 = __ballot(lb[0] && !((v0 >> lane) & 1u));
-          const uint64_t n1 = __ballot(lb[1] && !((v1 >> lane) & 1u));
-          const uint64_t n2 = __ballot(lb[2] && !((v2 >> lane) & 1u));
-          const uint64_t n3 = __ballot(lb[3] && !((v3 >> lane) & 1u));
-          if (!(n0 | n1 | n2 | n3)) return;
-          if (lane == 0) {
-            uint64_t* nw4 = b.N + ((uint64_t)uv * m.ntiles + t) * 4;
-            const uint64_t nn[4] = {n0, n1, n2, n3};
-            for (int i = 0; i < 4; ++i)
-              if (nn[i]) {
-                atomicOr((unsigned long long*)&vw[i], (unsigned long long)nn[i]);
-                atomicOr((unsigned long long*)&nw4[i], (unsigned long long)nn[i]);
-              }
-            if (atomicMax(&b.stamp[uv], level + 1) < level + 1) b.next[atomicAdd(b.ncount, 1u)] = uv;
-          }
+          if (++np == kWave / 4) flush();
         });
+    if (np) flush();
   }
+  if (__ballot(pc != 0)) add_count(b, pcopy, pc);
 }
 
-// Clears the frontier words of this level's vertices.
-__global__ void k_bfs_clear(uint64_t* F, const uint32_t* cur, const uint32_t* ncur_p, uint32_t ntiles) {
-  const uint64_t total = (uint64_t)(*ncur_p) * ntiles * 4;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t v = cur[k / (ntiles * 4)];
-    F[(uint64_t)v * ntiles * 4 + k % (ntiles * 4)] = 0;
+// The next frontier list from the bitmap left by level `level` (vertex
+// order; the bitmap is cleared): one bitmap word per lane, positions from a
+// scan over the wavefront and one atomic add per wavefront.
+__global__ void k_bfs_compact(BfsView b, uint32_t level) {
+  if (b.lcount[level % 3] == 0) return;  // an empty level marks nothing
+  const uint32_t words = (b.n + 63) / 64, lane = threadIdx.x & 63;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t w = 0;
+  if (i < words) {
+    w = b.nbits[i];
+    if (w) b.nbits[i] = 0;
   }
-}
-
-__global__ void k_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out) {
-  uint64_t c = 0;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (uint64_t)gridDim.x * blockDim.x)
-    c += (uint64_t)__popcll(V[k]);
+  const uint32_t c = (uint32_t)__popcll(w);
+  uint32_t incl = c;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, (unsigned long long)c);
-}
-
-// Per-copy counts: block (x, c) sums a stretch of copy c's words.
-__global__ void k_bfs_count_copies(const uint64_t* V, uint64_t words, unsigned long long* out) {
-  const uint32_t c = blockIdx.y;
-  const uint64_t* p = V + (uint64_t)c * words;
-  uint64_t cnt = 0;
-  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += (uint64_t)gridDim.x * blockDim.x)
-    cnt += (uint64_t)__popcll(p[k]);
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
-  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&out[c], (unsigned long long)cnt);
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= (uint32_t)off) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  if (!total) return;
+  uint32_t base = 0;
+  if (lane == 63) base = atomicAdd(&b.lcount[(level + 1) % 3], total);
+  base = __shfl(base, 63);
+  uint32_t pos = base + incl - c;
+  while (w) {
+    b.next[pos++] = i * 64 + (uint32_t)__builtin_ctzll(w);
+    w &= w - 1;
+  }
 }
 
 __global__ void k_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words) {
@@ -148,35 +195,20 @@ __global__ void k_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words
 // ---- launchers ---------------------------------------------------------------
 
 void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st) {
-  const uint64_t k = (uint64_t)len * m.ntiles * 4;
-  if (k) hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, m, b, S, len);
+  const uint64_t k = std::max<uint64_t>(1, (uint64_t)len * m.ntiles * 4);
+  hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, m, b, S, len);
 }
 
-// Fixed grids (the frontier size is known only on the device): enough
+// A fixed grid (the frontier size is known only on the device): enough
 // wavefronts to fill the device, striding over the (vertex, tile) items.
-void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, const uint32_t* ncur,
-                      uint32_t level, hipStream_t st) {
+void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t level, hipStream_t st) {
   constexpr uint32_t kBlocks = 16384;
   if (g.tm1)
-    hipLaunchKernelGGL(k_bfs_level<true>, dim3(kBlocks), dim3(256), 0, st, g, m, b, ncur, level);
+    hipLaunchKernelGGL(k_bfs_level<true>, dim3(kBlocks), dim3(256), 0, st, g, m, b, level);
   else
-    hipLaunchKernelGGL(k_bfs_level<false>, dim3(kBlocks), dim3(256), 0, st, g, m, b, ncur, level);
-}
-
-void launch_bfs_clear(uint64_t* F, const uint32_t* cur, const uint32_t* ncur, uint32_t ntiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_bfs_clear, dim3(1024), dim3(256), 0, st, F, cur, ncur, ntiles);
-}
-
-void launch_bfs_count(const uint64_t* V, uint64_t words, unsigned long long* out, hipStream_t st) {
-  const uint32_t blocks = (uint32_t)std::min<uint64_t>(8192, (words + 255) / 256);
-  hipLaunchKernelGGL(k_bfs_count, dim3(std::max(1u, blocks)), dim3(256), 0, st, V, words, out);
-}
-
-void launch_bfs_count_copies(const uint64_t* V, uint64_t words, uint32_t copies, unsigned long long* out,
-                             hipStream_t st) {
-  if (!copies) return;
-  const uint32_t bx = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (words + 255) / 256));
-  hipLaunchKernelGGL(k_bfs_count_copies, dim3(bx, copies), dim3(256), 0, st, V, words, out);
+    hipLaunchKernelGGL(k_bfs_level<false>, dim3(kBlocks), dim3(256), 0, st, g, m, b, level);
+  const uint32_t words = (b.n + 63) / 64;
+  hipLaunchKernelGGL(k_bfs_compact, dim3((words + 255) / 256), dim3(256), 0, st, b, level);
 }
 
 void launch_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words, uint32_t copies, hipStream_t st) {

@@ -1139,17 +1139,13 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   return s;
 }
 
-// Runs a level-synchronous search whose first frontier (list la, its size in
-// cnt[0]) is in place: cnt[1] must be 0.  Levels are enqueued eight at a time
-// and the host looks at the frontier size only between groups (levels past
-// the last are no-ops).  *levels receives the number of non-empty levels.
+// The levels of a search, enqueued eight at a time: each level reads its
+// frontier size on the device (an empty frontier makes the rest no-ops) and
+// the host looks at it once per group.  The seed kernel has set the list
+// sizes of level 1; frontier sets fa / fb and lists la / lb alternate.
 static hipError_t bfs_levels(const GraphView& gv, const MemoView& mv, BfsView bv, uint64_t* fa, uint64_t* fb,
-                             uint32_t* la, uint32_t* lb, uint32_t* cnt, hipStream_t st, uint32_t* levels) {
+                             uint32_t* la, uint32_t* lb, hipStream_t st, uint32_t* levels) {
   constexpr int kGroup = 8;
-  uint32_t* ca = cnt;
-  uint32_t* cb = cnt + 1;
-  bv.levels = cnt + 2;
-  launch_fill_u32(cnt + 2, 1, 0u, st);
   hipError_t e = hipSuccess;
   for (uint32_t level = 1;;) {
     for (int k = 0; k < kGroup; ++k, ++level) {
@@ -1157,21 +1153,17 @@ static hipError_t bfs_levels(const GraphView& gv, const MemoView& mv, BfsView bv
       bv.N = fb;
       bv.cur = la;
       bv.next = lb;
-      bv.ncount = cb;
-      launch_bfs_level(gv, mv, bv, ca, level, st);
-      launch_bfs_clear(fa, la, ca, mv.ntiles, st);  // fa is all zero again
-      launch_fill_u32(ca, 1, 0u, st);               // becomes the next level's next count
+      launch_bfs_level(gv, mv, bv, level, st);
       std::swap(fa, fb);
       std::swap(la, lb);
-      std::swap(ca, cb);
     }
     uint32_t h = 0;
-    e = hipMemcpyAsync(&h, ca, 4, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(&h, bv.lcount + level % 3, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess || h == 0) break;
   }
   uint32_t lv = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&lv, cnt + 2, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&lv, bv.levels, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (levels) *levels = lv;
   return e;
@@ -1197,12 +1189,13 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   const uint64_t T = thr_of(g->p);
   const uint64_t words = (uint64_t)n * ntiles * 4;
   // one allocation: sampler state, visited and two frontier bitsets, two
-  // frontier lists, level stamps, counters, S
+  // frontier lists, the next frontier's bitmap, counters, S
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
+  const size_t b_nb = align256(((size_t)n + 63) / 64 * 8);
   const size_t b_cnt = 256, b_S = align256((size_t)len * 4);
-  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 3 * b_list + b_cnt + b_S;
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
   s = ctx_alloc(c, total, &base);
   if (s != IM_OK) return s;
@@ -1230,40 +1223,41 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   uint64_t* B = reinterpret_cast<uint64_t*>(take(b_bits));
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
-  uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..1] list sizes, [2] levels, [4..5] result
+  uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..2] list sizes, [3] levels, [16..] counts
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(cnt + 16);
   mv.edges = edges;
   mv.xs = xs;
   const GraphView gv = g->view();
   launch_edge_hash(gv, g->seed, edges, st);
   launch_x_sort(g->seed, R, Rs, scr, xs, inv, pos, st);
-  launch_fill_u32(reinterpret_cast<uint32_t*>(V), (uint64_t)(3 * b_bits + 3 * b_list + b_cnt) / 4, 0u, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(V), (uint64_t)(3 * b_bits + 2 * b_list + b_nb + b_cnt) / 4, 0u, st);
   hipError_t e = hipMemcpyAsync(dS, set.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
-  BfsView bv;
+  BfsView bv = {};
   bv.n = n;
   bv.gn = n;
   bv.ntiles = ntiles;
   bv.V = V;
-  bv.F = nullptr;
   bv.N = A;
-  bv.cur = nullptr;
   bv.next = L0;
-  bv.ncount = cnt;
-  bv.stamp = stamp;
-  launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
-  launch_fill_u32(cnt, 1, len, st);
+  bv.lcount = cnt;
+  bv.levels = cnt + 3;
+  bv.nbits = nbits;
+  bv.counts = counts;
   uint32_t nlev = 0;
   {
     KTimer t(c, "sigma_direct", st);
-    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, cnt, st, &nlev);
-    if (e == hipSuccess) launch_bfs_count(V, words, reinterpret_cast<unsigned long long*>(cnt + 4), st);
+    launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
+    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, st, &nlev);
   }
-  unsigned long long h = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt + 4, 8, hipMemcpyDeviceToHost, st);
+  unsigned long long hc[kCountSlots] = {};
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free sigma failed: %s", hipGetErrorString(e));
+  unsigned long long h = 0;
+  for (unsigned long long x : hc) h += x;
   if (count) *count = (int64_t)h;
   if (sigma) *sigma = (double)h / (double)R;
   if (levels) *levels = nlev;
@@ -1291,15 +1285,15 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const uint32_t n = g->n, R = g->R, Rs = round_up(R, kTile), ntiles = Rs / kTile;
   const uint64_t T = thr_of(g->p);
   const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
-  const uint64_t per_copy = 3 * words * 8 + 3 * (uint64_t)n * 4;
+  const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * 4 + n / 8 + 1;
   const uint64_t copy_budget = 4ull << 30;
   const uint32_t copies = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({256, n, copy_budget / per_copy}));
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
-  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256((size_t)(copies + 8) * 8);
-  const size_t b_S = align256((size_t)copies * 4);
-  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 3 * b_list + b_cnt + b_S;
+  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(64 + (size_t)copies * kCountSlots * 8);
+  const size_t b_nb = align256(((size_t)n * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
   im_status s = ctx_alloc(c, total, &base);
   if (s != IM_OK) return s;
@@ -1328,8 +1322,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint64_t* B = reinterpret_cast<uint64_t*>(take(b_many));
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
-  uint32_t* stamp = reinterpret_cast<uint32_t*>(take(b_list));
-  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(take(b_cnt));  // [0..1] level state, [8..] counts
+  uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
+  uint32_t* lc = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..2] list sizes, [3] levels, [16..] counts
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(lc + 16);
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
   mv.edges = edges;
   mv.xs = xs;
@@ -1337,33 +1332,31 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   launch_edge_hash(gv, g->seed, edges, st);
   launch_x_sort(g->seed, R, Rs, scr, xs, inv, pos, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(Vs), words * 2, 0u, st);
+  // the frontier sets and the bitmap start zero and every search leaves them zero
+  launch_fill_u32(reinterpret_cast<uint32_t*>(A), words * 2 * copies, 0u, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(B), words * 2 * copies, 0u, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(nbits), b_nb / 4, 0u, st);
   hipError_t e = hipSuccess;
   std::vector<uint32_t> hsrc(copies);
-  std::vector<unsigned long long> hcnt(copies);
+  std::vector<unsigned long long> hcnt((size_t)copies * kCountSlots);
   // searches from the sources src[c] of copies 0 .. nc-1, each over the
-  // visited set Vv (nc copies); the frontier sets start zero
+  // visited set Vv (nc copies); counts[c] receives copy c's new bits
   auto search = [&](uint64_t* Vv, uint32_t nc) {
-    launch_fill_u32(reinterpret_cast<uint32_t*>(A), words * 2 * nc, 0u, st);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(B), words * 2 * nc, 0u, st);
-    launch_fill_u32(stamp, (uint64_t)n * nc, 0u, st);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(counts), (uint64_t)nc * kCountSlots * 2, 0u, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dS, hsrc.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st);
-    BfsView bv;
+    BfsView bv = {};
     bv.n = n * nc;
     bv.gn = n;
     bv.ntiles = ntiles;
     bv.V = Vv;
-    bv.F = nullptr;
     bv.N = A;
-    bv.cur = nullptr;
     bv.next = L0;
-    bv.ncount = reinterpret_cast<uint32_t*>(cnt);
-    bv.stamp = stamp;
-    bv.levels = nullptr;
+    bv.lcount = lc;
+    bv.levels = lc + 3;
+    bv.nbits = nbits;
+    bv.counts = counts;
     launch_bfs_seed(mv, bv, dS, nc, st);
-    uint32_t* c3 = reinterpret_cast<uint32_t*>(cnt);
-    launch_fill_u32(c3, 1, nc, st);
-    launch_fill_u32(c3 + 1, 1, 0u, st);
-    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, c3, st, nullptr);
+    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, st, nullptr);
   };
   std::vector<int64_t> key(n, INT64_MAX), when(n, -1);
   std::vector<uint8_t> chosen(n, 0);
@@ -1397,12 +1390,13 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
       for (uint32_t i = 0; i < nc; ++i) hsrc[i] = i * n + order[i];
       launch_bfs_replicate(Vs, V, words, nc, st);
       search(V, nc);
-      launch_fill_u32(reinterpret_cast<uint32_t*>(cnt + 8), (uint64_t)nc * 2, 0u, st);
-      launch_bfs_count_copies(V, words, nc, cnt + 8, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(hcnt.data(), cnt + 8, (size_t)nc * 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hcnt.data(), counts, (size_t)nc * kCountSlots * 8, hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
-      for (uint32_t i = 0; i < nc; ++i) {
-        key[order[i]] = (int64_t)hcnt[i] - cover;  // bits of the copy beyond the covered set
+      for (uint32_t i = 0; i < nc && e == hipSuccess; ++i) {
+        int64_t gain = 0;  // bits of the copy beyond the covered set
+        for (uint32_t k = 0; k < kCountSlots; ++k) gain += (int64_t)hcnt[(size_t)i * kCountSlots + k];
+        key[order[i]] = gain;
         when[order[i]] = step;
       }
       evals += nc;
