@@ -30,6 +30,10 @@ METRIC = "edge-samples/s (m·R/s), K-seed time; serving p50/p99 vs plain per-que
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "celf_persistent_c4_traffic.txt")
 ROOF_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("celf_persistent.hip", "common.h")]
+# the memo-free search (directed workload): level kernel and its sources
+BFS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_level_d1_traffic.txt")
+BFS_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f)
+               for f in ("direct.hip", "direct.h", "tile.h", "common.h")]
 
 WORKLOADS = {
     "c4": "R-MAT scale 18, edge factor 5, a/b/c/d=.57/.19/.19/.05, seed 3; p=0.01, R=8192, K=100",
@@ -38,27 +42,39 @@ WORKLOADS = {
 }
 
 
-def roof_source_hash() -> str:
+def roof_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in ROOF_SOURCES:
+    for p in sources or ROOF_SOURCES:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed counter
-    summary, or None when its source changed since the counters were taken."""
+def read_traffic(path=None, sources=None):
+    """HBM bytes of the roofline kernel from a committed counter summary, or
+    None when its sources changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("TRAFFIC_JSON "):
                     rec = json.loads(line[len("TRAFFIC_JSON "):])
-                    if rec.get("source_hash") == roof_source_hash():
+                    if rec.get("source_hash") == roof_source_hash(sources):
                         return rec
     except OSError:
         pass
     return None
+
+
+def bfs_algorithmic_bytes(stats: dict, per_arc_p: bool) -> int:
+    """Bytes the memo-free search moves by its definition, from its work
+    counts: per frontier item (vertex, 256-column tile) its four frontier
+    words read and cleared and its row bounds (72 B); per arc scanned the
+    target id and hash (8 B) and, with per-arc probabilities, the threshold
+    (4 B); per (arc, item) pair live in a frontier column the target's four
+    visited words read and or-ed and its four frontier words or-ed (96 B).
+    The 1 KiB of sample values of a tile is shared by every item and left
+    out."""
+    return 72 * stats["items"] + (12 if per_arc_p else 8) * stats["arcs"] + 96 * stats["live_pairs"]
 
 
 def cpu_baseline(workload, samples: int):
@@ -243,18 +259,28 @@ def directed_bench(args):
     G.set_params(0.0, R, seed)
     for _ in range(args.warmup):
         cnt, _, levels = G.estimate_sigma_direct(S)
-    ctx.set_profiling(1)
-    ctx.reset_kernel_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         cnt, _, levels = G.estimate_sigma_direct(S)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ctx.set_profiling(False)
     ms = dt * 1e3 / args.steps
-    names = ["edge_hash", "x_sort", "sigma_direct"]
+    # one more call, untimed, with the kernel clock and the search's work
+    # counts on (both perturb the kernels a little: the level times of this
+    # call are the roofline's)
+    ctx.set_profiling(1)
+    ctx.reset_kernel_stats()
+    G.estimate_sigma_direct(S)
+    torch.cuda.synchronize()
+    ctx.set_profiling(False)
+    names = ["edge_hash", "x_sort", "sigma_direct", "bfs_level"]
     stats = {k: ctx.kernel_stats(k) for k in names}
+    work = G.search_stats()
+    lv_n, level_ms = stats["bfs_level"]
+    alg = bfs_algorithmic_bytes(work, True)
+    achieved = alg / (level_ms * 1e-3) / 1e9 if level_ms > 0 else None
+    traffic = read_traffic(BFS_TRAFFIC_FILE, BFS_SOURCES)
     rec = {
         "metric": "arc-samples/s (arcs·R / spread time), directed spread under the weighted cascade",
         "value": g.nnz * R / (ms * 1e-3),
@@ -272,9 +298,28 @@ def directed_bench(args):
                                "|S|=100 (largest out-degree)", "n": g.n, "arcs": g.nnz, "R": R},
         "count": cnt,
         "levels": levels,
-        "kernel_total_ms_per_step": {k: v[1] / args.steps for k, v in stats.items()},
+        "kernel_ms_profiled_call": {k: v[1] for k, v in stats.items()},
+        "search_work": work,
+        # roofline of the level kernel over one step: the step's algorithmic
+        # bytes over the summed duration of its level launches
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_bfs_level",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic["bytes_per_step"] if traffic else None,
+            "algorithmic_bytes": alg,
+            "launches_per_step": lv_n,
+            "level_ms_per_step": level_ms,
+        },
     }
     G.free()
+    if args.no_selection:
+        ctx.close()
+        print(json.dumps(rec), flush=True)
+        return
     # greedy selection on a smaller digraph (memo-free, candidates searched
     # side by side): directed R-MAT scale 14, weighted cascade, R = 1,024, K = 50
     gs = rmat_directed(14, 5, 0.57, 0.19, 0.19, 4)
@@ -410,6 +455,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-selection", action="store_true", help="d1: the spread only")
     ap.add_argument("--weights", default="const", choices=["const", "uniform", "normal"],
                     help="edge probabilities: the workload's constant p, or per edge U[0,0.1] or "
                          "N(0.05,0.025) clipped (the paper's other weight settings)")

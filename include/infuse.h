@@ -244,6 +244,15 @@ im_status im_last_phase_ms(const im_graph *g, double *ms4);
 /* Number of CELF evaluations (vertex re-evaluations) of the last selection. */
 uint64_t im_last_celf_evals(const im_graph *g);
 
+/* Work counts of the last memo-free call on g (im_estimate_sigma_direct,
+ * or every search of im_select_seeds_direct summed): out4[0] non-empty
+ * levels, out4[1] frontier items (vertex, 256-column tile) visited, out4[2]
+ * arcs scanned in those items, out4[3] (arc, item) pairs live in at least
+ * one frontier column.  The counts are kept only while profiling is on
+ * (im_set_profiling level 1 or more; they cost atomics in every level),
+ * else they read zero.  Errors: NULL arguments. */
+im_status im_last_search_stats(const im_graph *g, uint64_t *out4);
+
 /* Work counts of the resident memo for the current parameters (built if
  * needed; waits for it): out[0] (vertex, 256-column tile) pairs that may
  * hold a non-singleton component, out[1] pairs with a column of two or more

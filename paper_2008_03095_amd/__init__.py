@@ -256,6 +256,12 @@ class Graph:
     def celf_evals(self) -> int:
         return int(self._lib.im_last_celf_evals(self.handle))
 
+    def search_stats(self) -> dict:
+        """Work counts of the last memo-free call on this graph."""
+        a = (C.c_uint64 * 4)()
+        check(self._lib.im_last_search_stats(self.handle, a))
+        return dict(levels=int(a[0]), items=int(a[1]), arcs=int(a[2]), live_pairs=int(a[3]))
+
     def memo_stats(self) -> dict:
         a = (C.c_uint64 * 4)()
         check(self._lib.im_memo_stats(self.handle, a))

@@ -82,6 +82,7 @@ SIGNATURES = {
     "im_kernel_stats": (C.c_int, [vp, C.c_char_p, P(u64), P(dbl)]),
     "im_last_phase_ms": (C.c_int, [vp, P(dbl)]),
     "im_last_celf_evals": (u64, [vp]),
+    "im_last_search_stats": (C.c_int, [vp, P(u64)]),
     "im_memo_stats": (C.c_int, [vp, P(u64)]),
     "im_batch_select": (C.c_int, [vp, u32, P(vp), P(u32), P(P(u32)), P(P(i64)), P(i64)]),
     "im_server_create": (C.c_int, [vp, P(im_server_config), P(vp)]),

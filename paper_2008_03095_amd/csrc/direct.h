@@ -24,15 +24,17 @@ struct BfsView {
   uint64_t* nbits;                // [ceil(n / 64)] vertices of the next frontier (zero between levels)
   uint32_t* levels;               // largest level with a non-empty frontier
   unsigned long long* counts;     // [copies][kCountSlots] new bits
+  unsigned long long* stats;      // [kCountSlots][3] work counts (items, arcs, live pairs), or nullptr
 };
 
 // Seeds S[i] (virtual ids) join the visited sets and the first frontier
 // (lists b.next / b.lcount[1]); their uncovered columns are counted.
 void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st);
-// One level and the listing of the next frontier: the frontier size is read
-// on the device, so levels can be enqueued without waiting for the host; an
-// empty frontier makes both kernels no-ops.
+// One level, then the listing of the next frontier: the frontier size is
+// read on the device, so levels can be enqueued without waiting for the
+// host; an empty frontier makes both kernels no-ops.
 void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t level, hipStream_t st);
+void launch_bfs_compact(const BfsView& b, uint32_t level, hipStream_t st);
 // V[c * words + i] = src[i] for every copy c < copies.
 void launch_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words, uint32_t copies, hipStream_t st);
 

@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   const uint64_t items = (uint64_t)ncur * m.ntiles;
   uint32_t pc = 0;        // new bits set by this lane for copy pcopy
   uint32_t pcopy = 0;
+  uint64_t s_items = 0, s_arcs = 0, s_live = 0;  // work counts of this wavefront (kept when b.stats)
   for (uint64_t it = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += nw) {
     const uint32_t vv = uni(b.cur[it / m.ntiles]), t = (uint32_t)(it % m.ntiles);
     const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
@@ -99,6 +100,7 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     const uint64_t f0 = fw[0], f1 = fw[1], f2 = fw[2], f3 = fw[3];
     if (!(f0 | f1 | f2 | f3)) continue;
     if (lane < 4) fw[lane] = 0;
+    ++s_items;
     uint32_t fb[4];
     fb[0] = (uint32_t)(f0 >> lane) & 1u;
     fb[1] = (uint32_t)(f1 >> lane) & 1u;
@@ -108,6 +110,7 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
     const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
     const bool inreg = end - beg <= (uint32_t)kWave;
+    s_arcs += end - beg;
     uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
     if (inreg && beg + lane < end) {
       const uint2 e = m.edges[beg + lane];
@@ -144,6 +147,7 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
           for (int i = 0; i < 4; ++i) lb[i] = (fb[i] && tc.valid[i] && (h ^ tc.x[i]) <= tt) ? 1u : 0u;
           const uint64_t w0 = __ballot(lb[0]), w1 = __ballot(lb[1]), w2 = __ballot(lb[2]), w3 = __ballot(lb[3]);
           if (!(w0 | w1 | w2 | w3)) return;
+          ++s_live;
           if (pslot == np) {
             pu = u;
             pm = wsel == 0 ? w0 : wsel == 1 ? w1 : wsel == 2 ? w2 : w3;
@@ -153,6 +157,18 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     if (np) flush();
   }
   if (__ballot(pc != 0)) add_count(b, pcopy, pc);
+  if (b.stats) {  // block sums in LDS, then one add per counter and block
+    __shared__ unsigned long long ws[3];
+    if (threadIdx.x < 3) ws[threadIdx.x] = 0;
+    __syncthreads();
+    if (lane == 0 && s_items) {
+      atomicAdd(&ws[0], (unsigned long long)s_items);
+      atomicAdd(&ws[1], (unsigned long long)s_arcs);
+      atomicAdd(&ws[2], (unsigned long long)s_live);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && ws[0]) atomicAdd(&b.stats[(blockIdx.x % kCountSlots) * 3 + threadIdx.x], ws[threadIdx.x]);
+  }
 }
 
 // The next frontier list from the bitmap left by level `level` (vertex
@@ -207,6 +223,9 @@ void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, u
     hipLaunchKernelGGL(k_bfs_level<true>, dim3(kBlocks), dim3(256), 0, st, g, m, b, level);
   else
     hipLaunchKernelGGL(k_bfs_level<false>, dim3(kBlocks), dim3(256), 0, st, g, m, b, level);
+}
+
+void launch_bfs_compact(const BfsView& b, uint32_t level, hipStream_t st) {
   const uint32_t words = (b.n + 63) / 64;
   hipLaunchKernelGGL(k_bfs_compact, dim3((words + 255) / 256), dim3(256), 0, st, b, level);
 }

@@ -174,5 +174,6 @@ struct im_graph {
   bool timed_build = false;
   double phase_ms[4] = {0, 0, 0, 0};
   uint64_t last_evals = 0;
+  uint64_t last_search[4] = {0, 0, 0, 0};  // memo-free searches: levels, items, arcs, live pairs
   infuse::GraphView view() const;
 };

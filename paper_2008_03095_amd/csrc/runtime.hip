@@ -1143,8 +1143,8 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
 // frontier size on the device (an empty frontier makes the rest no-ops) and
 // the host looks at it once per group.  The seed kernel has set the list
 // sizes of level 1; frontier sets fa / fb and lists la / lb alternate.
-static hipError_t bfs_levels(const GraphView& gv, const MemoView& mv, BfsView bv, uint64_t* fa, uint64_t* fb,
-                             uint32_t* la, uint32_t* lb, hipStream_t st, uint32_t* levels) {
+static hipError_t bfs_levels(im_ctx* c, const GraphView& gv, const MemoView& mv, BfsView bv, uint64_t* fa,
+                             uint64_t* fb, uint32_t* la, uint32_t* lb, hipStream_t st, uint32_t* levels) {
   constexpr int kGroup = 8;
   hipError_t e = hipSuccess;
   for (uint32_t level = 1;;) {
@@ -1153,7 +1153,11 @@ static hipError_t bfs_levels(const GraphView& gv, const MemoView& mv, BfsView bv
       bv.N = fb;
       bv.cur = la;
       bv.next = lb;
-      launch_bfs_level(gv, mv, bv, level, st);
+      {
+        KTimer t(c, "bfs_level", st);
+        launch_bfs_level(gv, mv, bv, level, st);
+      }
+      launch_bfs_compact(bv, level, st);
       std::swap(fa, fb);
       std::swap(la, lb);
     }
@@ -1194,7 +1198,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
   const size_t b_nb = align256(((size_t)n + 63) / 64 * 8);
-  const size_t b_cnt = 256, b_S = align256((size_t)len * 4);
+  const size_t b_cnt = 1024, b_S = align256((size_t)len * 4);
   const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
   s = ctx_alloc(c, total, &base);
@@ -1224,9 +1228,11 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
-  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..2] list sizes, [3] levels, [16..] counts
+  // cnt: [0..2] list sizes, [3] levels; bytes 64..191 the count slots, 256..639 work counts
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
-  unsigned long long* counts = reinterpret_cast<unsigned long long*>(cnt + 16);
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(cnt) + 8;
+  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(cnt) + 32;
   mv.edges = edges;
   mv.xs = xs;
   const GraphView gv = g->view();
@@ -1245,19 +1251,25 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   bv.levels = cnt + 3;
   bv.nbits = nbits;
   bv.counts = counts;
+  bv.stats = c->profiling >= 1 ? wstats : nullptr;  // work counts cost atomics: kept while profiling
   uint32_t nlev = 0;
   {
     KTimer t(c, "sigma_direct", st);
     launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
-    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, st, &nlev);
+    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &nlev);
   }
-  unsigned long long hc[kCountSlots] = {};
-  if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st);
+  unsigned long long hb[80] = {};  // bytes 0..639 of cnt
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, cnt, sizeof(hb), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  const unsigned long long* hc = hb + 8;
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free sigma failed: %s", hipGetErrorString(e));
   unsigned long long h = 0;
-  for (unsigned long long x : hc) h += x;
+  for (uint32_t k = 0; k < kCountSlots; ++k) h += hc[k];
+  g->last_search[0] = nlev;
+  for (int k = 1; k < 4; ++k) g->last_search[k] = 0;
+  for (uint32_t k = 0; k < kCountSlots; ++k)
+    for (int j = 0; j < 3; ++j) g->last_search[1 + j] += hb[32 + k * 3 + j];
   if (count) *count = (int64_t)h;
   if (sigma) *sigma = (double)h / (double)R;
   if (levels) *levels = nlev;
@@ -1291,7 +1303,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
-  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(64 + (size_t)copies * kCountSlots * 8);
+  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(512 + (size_t)copies * kCountSlots * 8);
   const size_t b_nb = align256(((size_t)n * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
   const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
@@ -1323,8 +1335,10 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
-  uint32_t* lc = reinterpret_cast<uint32_t*>(take(b_cnt));  // [0..2] list sizes, [3] levels, [16..] counts
-  unsigned long long* counts = reinterpret_cast<unsigned long long*>(lc + 16);
+  // lc: [0..2] list sizes, [3] levels; bytes 64..447 work counts, 512.. the count slots of each copy
+  uint32_t* lc = reinterpret_cast<uint32_t*>(take(b_cnt));
+  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(lc) + 8;
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(lc) + 64;
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
   mv.edges = edges;
   mv.xs = xs;
@@ -1336,6 +1350,8 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   launch_fill_u32(reinterpret_cast<uint32_t*>(A), words * 2 * copies, 0u, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(B), words * 2 * copies, 0u, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(nbits), b_nb / 4, 0u, st);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(wstats), kCountSlots * 3 * 2, 0u, st);
+  uint64_t total_levels = 0;
   hipError_t e = hipSuccess;
   std::vector<uint32_t> hsrc(copies);
   std::vector<unsigned long long> hcnt((size_t)copies * kCountSlots);
@@ -1355,8 +1371,11 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
     bv.levels = lc + 3;
     bv.nbits = nbits;
     bv.counts = counts;
+    bv.stats = c->profiling >= 1 ? wstats : nullptr;
     launch_bfs_seed(mv, bv, dS, nc, st);
-    if (e == hipSuccess) e = bfs_levels(gv, mv, bv, A, B, L0, L1, st, nullptr);
+    uint32_t lv = 0;
+    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &lv);
+    total_levels += lv;
   };
   std::vector<int64_t> key(n, INT64_MAX), when(n, -1);
   std::vector<uint8_t> chosen(n, 0);
@@ -1402,10 +1421,23 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
       evals += nc;
     }
   }
+  unsigned long long hw[kCountSlots * 3] = {};
+  if (e == hipSuccess) e = hipMemcpyAsync(hw, wstats, sizeof(hw), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free selection failed: %s", hipGetErrorString(e));
   if (cover_count) *cover_count = cover;
   g->last_evals = evals;
+  g->last_search[0] = total_levels;
+  for (int k = 1; k < 4; ++k) g->last_search[k] = 0;
+  for (uint32_t k = 0; k < kCountSlots; ++k)
+    for (int j = 0; j < 3; ++j) g->last_search[1 + j] += hw[k * 3 + j];
+  return IM_OK;
+}
+
+extern "C" im_status im_last_search_stats(const im_graph* g, uint64_t* out4) {
+  if (!g || !out4) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) out4[k] = g->last_search[k];
   return IM_OK;
 }
 
