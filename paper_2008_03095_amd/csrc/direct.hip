@@ -83,13 +83,15 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   if (ncur == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(b.levels, level);
   const uint32_t lane = threadIdx.x & 63, wsel = lane & 3, pslot = lane >> 2;
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  // item counts fit in 32 bits (n * ntiles < 2^32, checked by the host); the
+  // item index is wave-uniform, so its division by ntiles stays scalar
+  const uint64_t nw = gridDim.x * 4;
   const uint64_t items = (uint64_t)ncur * m.ntiles;
   uint32_t pc = 0;        // new bits set by this lane for copy pcopy
   uint32_t pcopy = 0;
   uint64_t s_items = 0, s_arcs = 0, s_live = 0;  // work counts of this wavefront (kept when b.stats)
-  for (uint64_t it = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); it < items; it += nw) {
-    const uint32_t vv = uni(b.cur[it / m.ntiles]), t = (uint32_t)(it % m.ntiles);
+  for (uint64_t it = blockIdx.x * 4 + uni(threadIdx.x >> 6); it < items; it += nw) {
+    const uint32_t vv = uni(b.cur[(uint32_t)it / m.ntiles]), t = (uint32_t)it % m.ntiles;
     const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
     if (cb / b.gn != pcopy) {  // counts are added when the copy changes, and at the end
       if (__ballot(pc != 0)) add_count(b, pcopy, pc);

@@ -1196,6 +1196,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   // frontier lists, the next frontier's bitmap, counters, S
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
+  if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
   const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
   const size_t b_nb = align256(((size_t)n + 63) / 64 * 8);
   const size_t b_cnt = 1024, b_S = align256((size_t)len * 4);
@@ -1299,7 +1300,10 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
   const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * 4 + n / 8 + 1;
   const uint64_t copy_budget = 4ull << 30;
-  const uint32_t copies = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({256, n, copy_budget / per_copy}));
+  if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
+  // copies * n * ntiles level items must fit in 32 bits
+  const uint32_t copies = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>({256, n, copy_budget / per_copy, (uint64_t)UINT32_MAX / ((uint64_t)n * ntiles)}));
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);

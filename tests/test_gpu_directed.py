@@ -129,3 +129,33 @@ def test_memo_free_selection_equals_memo_selection_undirected(gpu_ctx):
         assert list(s1) == list(s2) and list(m1) == list(m2) and c1 == c2
     finally:
         G.free()
+
+
+def test_search_work_counts_on_a_forced_live_path(gpu_ctx):
+    """Work counts of the memo-free search, exact on a path with every arc
+    live: from seed i the frontier is one vertex per level in one tile, each
+    frontier vertex but the last has one arc, live in every column."""
+    k = 300
+    a = np.arange(k - 1)
+    g = from_arc_list(k, a, a + 1)
+    announce("search work counts, directed path, p = 1")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(1.0, 128, 3)
+        gpu_ctx.set_profiling(1)
+        try:
+            for i in (0, 117, k - 1):
+                cnt, _, levels = G.estimate_sigma_direct([i])
+                assert cnt == 128 * (k - i) and levels == k - i
+                assert G.search_stats() == dict(levels=k - i, items=k - i, arcs=k - 1 - i, live_pairs=k - 1 - i)
+            # selection: every search's counts summed, consistent with the work done
+            G.select_seeds_direct(3)
+            st = G.search_stats()
+            assert st["levels"] > 0 and st["items"] >= st["levels"] and st["arcs"] >= st["live_pairs"] > 0
+        finally:
+            gpu_ctx.set_profiling(0)
+        # without profiling only the level count is kept
+        G.estimate_sigma_direct([5])
+        assert G.search_stats() == dict(levels=k - 5, items=0, arcs=0, live_pairs=0)
+    finally:
+        G.free()
