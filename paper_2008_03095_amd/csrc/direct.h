@@ -9,8 +9,9 @@ namespace infuse {
 // vertex c * gn + v is vertex v of copy c (gn = the graph's n); n counts the
 // virtual vertices.  A copy's arrays are those of one search.
 // Per copy, new bits are summed into kCountSlots counters (blocks spread
-// over them); the copy's count is the sum of its slots.
-constexpr uint32_t kCountSlots = 16;
+// over them; fewer slots made the adds of one level's wavefronts contend);
+// the copy's count is the sum of its slots.
+constexpr uint32_t kCountSlots = 128;
 
 struct BfsView {
   uint32_t n, ntiles;

@@ -217,10 +217,11 @@ void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uin
   hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, m, b, S, len);
 }
 
-// A fixed grid (the frontier size is known only on the device): enough
-// wavefronts to fill the device, striding over the (vertex, tile) items.
+// A fixed grid (the frontier size is known only on the device): four
+// rounds of resident wavefronts, striding over the (vertex, tile) items.
+// Larger grids pay per-wavefront set-up and count adds for nothing.
 void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, uint32_t level, hipStream_t st) {
-  constexpr uint32_t kBlocks = 16384;
+  constexpr uint32_t kBlocks = 8192;
   if (g.tm1)
     hipLaunchKernelGGL(k_bfs_level<true>, dim3(kBlocks), dim3(256), 0, st, g, m, b, level);
   else

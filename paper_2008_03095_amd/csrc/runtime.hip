@@ -1199,7 +1199,9 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
   const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
   const size_t b_nb = align256(((size_t)n + 63) / 64 * 8);
-  const size_t b_cnt = 1024, b_S = align256((size_t)len * 4);
+  // cnt: [0..2] list sizes, [3] levels; then the count slots and the work counts
+  const size_t o_counts = 64, o_stats = align256(o_counts + kCountSlots * 8);
+  const size_t b_cnt = align256(o_stats + kCountSlots * 24), b_S = align256((size_t)len * 4);
   const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
   s = ctx_alloc(c, total, &base);
@@ -1229,11 +1231,10 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
-  // cnt: [0..2] list sizes, [3] levels; bytes 64..191 the count slots, 256..639 work counts
   uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
-  unsigned long long* counts = reinterpret_cast<unsigned long long*>(cnt) + 8;
-  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(cnt) + 32;
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(cnt) + o_counts);
+  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(cnt) + o_stats);
   mv.edges = edges;
   mv.xs = xs;
   const GraphView gv = g->view();
@@ -1259,10 +1260,11 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
     launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
     if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &nlev);
   }
-  unsigned long long hb[80] = {};  // bytes 0..639 of cnt
-  if (e == hipSuccess) e = hipMemcpyAsync(hb, cnt, sizeof(hb), hipMemcpyDeviceToHost, st);
+  std::vector<unsigned long long> hb(b_cnt / 8);
+  if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), cnt, b_cnt, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  const unsigned long long* hc = hb + 8;
+  const unsigned long long* hc = hb.data() + o_counts / 8;
+  const unsigned long long* hs = hb.data() + o_stats / 8;
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free sigma failed: %s", hipGetErrorString(e));
   unsigned long long h = 0;
@@ -1270,7 +1272,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   g->last_search[0] = nlev;
   for (int k = 1; k < 4; ++k) g->last_search[k] = 0;
   for (uint32_t k = 0; k < kCountSlots; ++k)
-    for (int j = 0; j < 3; ++j) g->last_search[1 + j] += hb[32 + k * 3 + j];
+    for (int j = 0; j < 3; ++j) g->last_search[1 + j] += hs[k * 3 + j];
   if (count) *count = (int64_t)h;
   if (sigma) *sigma = (double)h / (double)R;
   if (levels) *levels = nlev;
@@ -1307,7 +1309,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
-  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(512 + (size_t)copies * kCountSlots * 8);
+  // lc: [0..2] list sizes, [3] levels; then the work counts and the count slots of each copy
+  const size_t o_stats = 64, o_counts = align256(o_stats + kCountSlots * 24);
+  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(o_counts + (size_t)copies * kCountSlots * 8);
   const size_t b_nb = align256(((size_t)n * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
   const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
@@ -1339,10 +1343,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint32_t* L0 = reinterpret_cast<uint32_t*>(take(b_list));
   uint32_t* L1 = reinterpret_cast<uint32_t*>(take(b_list));
   uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
-  // lc: [0..2] list sizes, [3] levels; bytes 64..447 work counts, 512.. the count slots of each copy
   uint32_t* lc = reinterpret_cast<uint32_t*>(take(b_cnt));
-  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(lc) + 8;
-  unsigned long long* counts = reinterpret_cast<unsigned long long*>(lc) + 64;
+  unsigned long long* wstats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lc) + o_stats);
+  unsigned long long* counts = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lc) + o_counts);
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
   mv.edges = edges;
   mv.xs = xs;
@@ -1425,8 +1428,8 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
       evals += nc;
     }
   }
-  unsigned long long hw[kCountSlots * 3] = {};
-  if (e == hipSuccess) e = hipMemcpyAsync(hw, wstats, sizeof(hw), hipMemcpyDeviceToHost, st);
+  std::vector<unsigned long long> hw(kCountSlots * 3);
+  if (e == hipSuccess) e = hipMemcpyAsync(hw.data(), wstats, hw.size() * 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   ctx_free(c, base);
   if (e != hipSuccess) return fail(IM_ERR_DEVICE, "memo-free selection failed: %s", hipGetErrorString(e));
