@@ -47,6 +47,29 @@ def test_directed_spread_matches_oracle(gpu_ctx, case):
         G.free()
 
 
+def test_directed_spread_full_size(gpu_ctx):
+    """The directed benchmark workload at full size: R-MAT scale 18, edge
+    factor 5, seed 3, weighted cascade, R = 8,192, S = the 100 vertices of
+    largest out-degree; the device count equals the oracle's over all
+    samples, in the launch configuration the benchmark times."""
+    import os
+
+    g = rmat_directed(18, 5, 0.57, 0.19, 0.19, 3)
+    g.p_slot = wc_p(g)
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    S = [int(v) for v in np.argsort(-deg, kind="stable")[:100]]
+    announce(f"directed spread full size: n={g.n} arcs={g.nnz} R=8192 |S|=100")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(0.0, 8192, 3)
+        cnt, _, levels = G.estimate_sigma_direct(S)
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        assert cnt == oracle.sigma_count(g, oracle.Sampler("hash", R=8192, seed=3), S, threads=threads)
+        assert levels > 1
+    finally:
+        G.free()
+
+
 def test_directed_forced_live_path_and_no_live_arcs(gpu_ctx):
     k = 300
     a = np.arange(k - 1)
@@ -90,6 +113,8 @@ SELECT_CASES = {
     "drand60_ragged": (lambda: random_small_digraph(60, 500, 2), 0.05, 300, 2, False, 10),
     "rmat11_wc": (lambda: rmat_directed(11, 6, 0.57, 0.19, 0.19, 5), 0.0, 256, 5, True, 15),
     "rmat12_p02": (lambda: rmat_directed(12, 5, 0.57, 0.19, 0.19, 7), 0.02, 128, 7, False, 8),
+    # the selection of the directed benchmark line, at its size
+    "rmat14_wc_K50": (lambda: rmat_directed(14, 5, 0.57, 0.19, 0.19, 4), 0.0, 1024, 4, True, 50),
 }
 
 
