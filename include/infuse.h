@@ -167,7 +167,7 @@ im_status im_estimate_sigma_direct(im_graph *g, const uint32_t *S, uint32_t s_le
  * all samples at once, many candidates side by side.  Same queue and
  * tie-breaking as im_select_seeds (on an undirected graph the result is the
  * same), same outputs and errors.  Needs about 3 n R / 8 bytes per
- * candidate searched side by side (up to 256, within 4 GiB) plus the
+ * candidate searched side by side (up to 1,024, within 8 GiB) plus the
  * sampler state; meant for graphs of up to about 10^5 vertices. */
 im_status im_select_seeds_direct(im_graph *g, uint32_t K, uint32_t *seeds, int64_t *marginal,
                                  int64_t *cover_count);

@@ -1285,7 +1285,8 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
 // starting from the covered set R_r(S) of every sample, so a copy's new bits
 // are the candidate's gain.  The lazy queue (on the host) commits the largest
 // key when it is fresh, ties to the smaller id, and otherwise re-evaluates
-// the largest stale keys, as many as fit side by side; every key starts
+// the largest stale keys that still rank above the best fresh one (no other
+// can win this step), as many as fit side by side; every key starts
 // unevaluated.  A commit grows the covered set by one more search.
 extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* seeds, int64_t* marginal,
                                             int64_t* cover_count) {
@@ -1301,11 +1302,11 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const uint64_t T = thr_of(g->p);
   const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
   const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * 4 + n / 8 + 1;
-  const uint64_t copy_budget = 4ull << 30;
+  const uint64_t copy_budget = 8ull << 30;
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
   // copies * n * ntiles level items must fit in 32 bits
   const uint32_t copies = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>({256, n, copy_budget / per_copy, (uint64_t)UINT32_MAX / ((uint64_t)n * ntiles)}));
+      1, std::min<uint64_t>({1024, n, copy_budget / per_copy, (uint64_t)UINT32_MAX / ((uint64_t)n * ntiles)}));
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
@@ -1391,7 +1392,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint64_t evals = 0;
   {
     KTimer t(c, "select_direct", st);
-    uint32_t step = 0;
+    uint32_t step = 0, rounds = 0;  // evaluation rounds of this step
     auto before = [&](uint32_t a, uint32_t b) { return key[a] != key[b] ? key[a] > key[b] : a < b; };
     while (e == hipSuccess && step < K) {
       uint32_t top = kInvalid;
@@ -1405,13 +1406,22 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
         cover += key[top];
         chosen[top] = 1;
         ++step;
+        rounds = 0;
         continue;
       }
-      // the largest stale keys, as many as fit side by side
+      // the largest stale keys above the best fresh one, as many as fit side by side
+      uint32_t best_fresh = kInvalid;
+      for (uint32_t v = 0; v < n; ++v)
+        if (!chosen[v] && when[v] == (int64_t)step && (best_fresh == kInvalid || before(v, best_fresh))) best_fresh = v;
       order.clear();
       for (uint32_t v = 0; v < n; ++v)
-        if (!chosen[v] && when[v] != (int64_t)step) order.push_back(v);
-      const uint32_t nc = std::min<uint32_t>(copies, (uint32_t)order.size());
+        if (!chosen[v] && when[v] != (int64_t)step && (best_fresh == kInvalid || before(v, best_fresh)))
+          order.push_back(v);
+      // never-evaluated keys fill whole batches; re-evaluations start at 64
+      // candidates per step and double with every further round
+      const uint32_t room = key[top] == INT64_MAX ? copies : std::min<uint32_t>(copies, 64u << std::min(rounds, 10u));
+      ++rounds;
+      const uint32_t nc = std::min<uint32_t>(room, (uint32_t)order.size());
       std::partial_sort(order.begin(), order.begin() + nc, order.end(), before);
       for (uint32_t i = 0; i < nc; ++i) hsrc[i] = i * n + order[i];
       launch_bfs_replicate(Vs, V, words, nc, st);
