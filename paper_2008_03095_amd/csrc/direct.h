@@ -19,17 +19,18 @@ struct BfsView {
   uint64_t* V;                    // [n][ntiles][4] visited columns (ballot layout)
   uint64_t* F;                    // frontier of this level (cleared as it is read)
   uint64_t* N;                    // frontier of the next level
-  const uint32_t* cur;            // frontier vertices of this level
-  uint32_t* next;                 // frontier vertices of the next level
+  const uint32_t* cur;            // frontier items of this level: vertex * ntiles + tile
+  uint32_t* next;                 // frontier items of the next level
   uint32_t* lcount;               // [3] list sizes, level l reads lcount[l % 3]
-  uint64_t* nbits;                // [ceil(n / 64)] vertices of the next frontier (zero between levels)
+  uint64_t* nbits;                // [ceil(n * ntiles / 64)] items of the next frontier (zero between levels)
   uint32_t* levels;               // largest level with a non-empty frontier
   unsigned long long* counts;     // [copies][kCountSlots] new bits
   unsigned long long* stats;      // [kCountSlots][3] work counts (items, arcs, live pairs), or nullptr
 };
 
 // Seeds S[i] (virtual ids) join the visited sets and the first frontier
-// (lists b.next / b.lcount[1]); their uncovered columns are counted.
+// (items (S[i], t) in b.next, their number in b.lcount[1]); their uncovered
+// columns are counted.  Item ids (n * ntiles) must fit in 32 bits.
 void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st);
 // One level, then the listing of the next frontier: the frontier size is
 // read on the device, so levels can be enqueued without waiting for the

@@ -5,12 +5,13 @@
 // Per (vertex, 256-column tile) the visited set V and the frontier F hold
 // one bit per column, as four 64-bit words: bit l of word i is column
 // 4l + i of the tile (the layout of a ballot over the wavefront's lanes).
-// A level visits, for every vertex of the frontier list and every tile where
-// its frontier is not empty, the candidate edges of the tile (tile
-// prefilter), and ors the columns where the edge is live and the vertex is
-// in the frontier into V and the next frontier N of the neighbour; a
-// neighbour that gains columns is marked in a bitmap, which a second kernel
-// turns into the next frontier list (in vertex order).  V and N are written only by atomics while a level runs (stale
+// A level visits, for every item (vertex, tile) of the frontier list, the
+// candidate edges of the tile (tile prefilter), and ors the columns where
+// the edge is live and the vertex is in the frontier into V and the next
+// frontier N of the neighbour; a neighbour that gains columns in the tile is
+// marked in a bitmap of items, which a second kernel turns into the next
+// frontier list (in item order), so only (vertex, tile) pairs whose
+// frontier is not empty are visited.  V and N are written only by atomics while a level runs (stale
 // reads of V only cause redundant atomics); F is only read, then cleared by
 // the wavefront that owns the item, so both frontier sets are all zero again
 // once a search ends.  The count is the number of bits the search sets in V,
@@ -49,7 +50,7 @@ __device__ inline void add_count(const BfsView& b, uint32_t copy, uint32_t pc) {
 __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t len) {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k == 0) {
-    b.lcount[1] = len;
+    b.lcount[1] = len * m.ntiles;
     b.lcount[2] = 0;
     *b.levels = 0;
   }
@@ -63,7 +64,7 @@ __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t le
     atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
     atomicAdd(&b.counts[(uint64_t)(v / b.gn) * kCountSlots + k % kCountSlots], (unsigned long long)__popcll(nb));
   }
-  if (r == 0) b.next[s] = v;
+  if (i == 0) b.next[(uint64_t)s * m.ntiles + t] = v * m.ntiles + t;  // item (seed, tile)
 }
 
 // One level.  A wavefront takes (frontier vertex, tile) items; for each
@@ -83,15 +84,22 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   if (ncur == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(b.levels, level);
   const uint32_t lane = threadIdx.x & 63, wsel = lane & 3, pslot = lane >> 2;
-  // item counts fit in 32 bits (n * ntiles < 2^32, checked by the host); the
-  // item index is wave-uniform, so its division by ntiles stays scalar
+  // item ids (vertex * ntiles + tile) fit in 32 bits (checked by the host);
+  // the item index is wave-uniform.  The item's frontier words, row bounds
+  // and tile X are requested together, and the next item's id one item
+  // ahead.  Listed items have frontier bits (seeds aside), so none is
+  // skipped: a test would defer the loads past it
   const uint64_t nw = gridDim.x * 4;
-  const uint64_t items = (uint64_t)ncur * m.ntiles;
+  const uint64_t items = ncur;
   uint32_t pc = 0;        // new bits set by this lane for copy pcopy
   uint32_t pcopy = 0;
   uint64_t s_items = 0, s_arcs = 0, s_live = 0;  // work counts of this wavefront (kept when b.stats)
-  for (uint64_t it = blockIdx.x * 4 + uni(threadIdx.x >> 6); it < items; it += nw) {
-    const uint32_t vv = uni(b.cur[(uint32_t)it / m.ntiles]), t = (uint32_t)it % m.ntiles;
+  const uint64_t it0 = blockIdx.x * 4 + uni(threadIdx.x >> 6);
+  uint32_t en = b.cur[min(it0, items - 1)];
+  for (uint64_t it = it0; it < items; it += nw) {
+    const uint32_t e0 = uni(en);
+    en = b.cur[min(it + nw, items - 1)];
+    const uint32_t vv = e0 / m.ntiles, t = e0 % m.ntiles;
     const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
     if (cb / b.gn != pcopy) {  // counts are added when the copy changes, and at the end
       if (__ballot(pc != 0)) add_count(b, pcopy, pc);
@@ -100,7 +108,8 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     }
     uint64_t* fw = b.F + ((uint64_t)vv * m.ntiles + t) * 4;
     const uint64_t f0 = fw[0], f1 = fw[1], f2 = fw[2], f3 = fw[3];
-    if (!(f0 | f1 | f2 | f3)) continue;
+    const uint32_t rb = g.row_ptr[v], re = g.row_ptr[v + 1];
+    const uint4 x4 = load_tile_x(m, t, lane);
     if (lane < 4) fw[lane] = 0;
     ++s_items;
     uint32_t fb[4];
@@ -109,8 +118,8 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     fb[2] = (uint32_t)(f2 >> lane) & 1u;
     fb[3] = (uint32_t)(f3 >> lane) & 1u;
     TileCtx tc;
-    tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
-    const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
+    tile_from_x(m, t, lane, x4, m.kshift, tc, PER_EDGE);
+    const uint32_t beg = uni(rb), end = uni(re);
     const bool inreg = end - beg <= (uint32_t)kWave;
     s_arcs += end - beg;
     uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
@@ -136,8 +145,8 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
       pc += (uint32_t)__popcll(nb);
       const uint64_t hit = __ballot(nb != 0);
       if (wsel == 0 && pslot < np && ((hit >> lane) & 0xFull)) {
-        const uint32_t uv = cb + pu;
-        atomicOr((unsigned long long*)&b.nbits[uv >> 6], 1ull << (uv & 63));
+        const uint32_t ui = (cb + pu) * m.ntiles + t;  // item (target, tile) of the next level
+        atomicOr((unsigned long long*)&b.nbits[ui >> 6], 1ull << (ui & 63));
       }
       np = 0;
       pm = 0;
@@ -173,12 +182,12 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   }
 }
 
-// The next frontier list from the bitmap left by level `level` (vertex
+// The next frontier list from the bitmap left by level `level` (item
 // order; the bitmap is cleared): one bitmap word per lane, positions from a
 // scan over the wavefront and one atomic add per wavefront.
 __global__ void k_bfs_compact(BfsView b, uint32_t level) {
   if (b.lcount[level % 3] == 0) return;  // an empty level marks nothing
-  const uint32_t words = (b.n + 63) / 64, lane = threadIdx.x & 63;
+  const uint32_t words = (uint32_t)(((uint64_t)b.n * b.ntiles + 63) / 64), lane = threadIdx.x & 63;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t w = 0;
   if (i < words) {
@@ -229,7 +238,7 @@ void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, u
 }
 
 void launch_bfs_compact(const BfsView& b, uint32_t level, hipStream_t st) {
-  const uint32_t words = (b.n + 63) / 64;
+  const uint32_t words = (uint32_t)(((uint64_t)b.n * b.ntiles + 63) / 64);
   hipLaunchKernelGGL(k_bfs_compact, dim3((words + 255) / 256), dim3(256), 0, st, b, level);
 }
 

@@ -1197,8 +1197,8 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
-  const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * 4);
-  const size_t b_nb = align256(((size_t)n + 63) / 64 * 8);
+  const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * ntiles * 4);
+  const size_t b_nb = align256(((size_t)n * ntiles + 63) / 64 * 8);
   // cnt: [0..2] list sizes, [3] levels; then the count slots and the work counts
   const size_t o_counts = 64, o_stats = align256(o_counts + kCountSlots * 8);
   const size_t b_cnt = align256(o_stats + kCountSlots * 24), b_S = align256((size_t)len * 4);
@@ -1301,7 +1301,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const uint32_t n = g->n, R = g->R, Rs = round_up(R, kTile), ntiles = Rs / kTile;
   const uint64_t T = thr_of(g->p);
   const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
-  const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * 4 + n / 8 + 1;
+  const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * ntiles * 4 + (uint64_t)n * ntiles / 8 + 1;
   const uint64_t copy_budget = 8ull << 30;
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
   // copies * n * ntiles level items must fit in 32 bits
@@ -1312,8 +1312,8 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
   // lc: [0..2] list sizes, [3] levels; then the work counts and the count slots of each copy
   const size_t o_stats = 64, o_counts = align256(o_stats + kCountSlots * 24);
-  const size_t b_list = align256((size_t)n * 4 * copies), b_cnt = align256(o_counts + (size_t)copies * kCountSlots * 8);
-  const size_t b_nb = align256(((size_t)n * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
+  const size_t b_list = align256((size_t)n * ntiles * 4 * copies), b_cnt = align256(o_counts + (size_t)copies * kCountSlots * 8);
+  const size_t b_nb = align256(((size_t)n * ntiles * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
   const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S;
   void* base = nullptr;
   im_status s = ctx_alloc(c, total, &base);
