@@ -11,10 +11,10 @@
 // frontier N of the neighbour; a neighbour that gains columns in the tile is
 // marked in a bitmap of items, which a second kernel turns into the next
 // frontier list (in item order), so only (vertex, tile) pairs whose
-// frontier is not empty are visited.  V and N are written only by atomics while a level runs (stale
-// reads of V only cause redundant atomics); F is only read, then cleared by
-// the wavefront that owns the item, so both frontier sets are all zero again
-// once a search ends.  The count is the number of bits the search sets in V,
+// frontier is not empty are visited.  V and N are written only by atomics
+// while a level runs; F is only read, then cleared by the wavefront that
+// owns the item, so both frontier sets are all zero again once a search
+// ends.  The count is the number of bits the search sets in V,
 // summed from the atomics' old values: sum over samples of |R_r(S)|, seeds
 // included (beyond the set V starts from).
 #include <algorithm>
@@ -71,9 +71,9 @@ __global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t le
 // candidate edge of the tile it forms the 256-bit set of columns where the
 // edge is live and the vertex is in the frontier, and parks it in four lanes
 // (lane 4j + i holds word i of the j-th pending target).  Sixteen targets
-// are then updated at once: each lane reads its word of V, ors the unseen
-// columns in (the atomic's old value decides which bits are new, so every
-// bit is counted once), adds the new ones to N, and one lane per target
+// are then updated at once: each lane ors its word into V (the atomic's
+// old value decides which bits are new, so every bit is counted once), adds
+// the new ones to N, and one lane per target
 // that gained columns marks it in the next frontier's bitmap.  The item's
 // frontier words are cleared once read: each (vertex, tile) is one item of
 // the level.
@@ -136,11 +136,8 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
       uint64_t nb = 0;
       if (pm) {
         const uint64_t at = ((uint64_t)(cb + pu) * m.ntiles + t) * 4 + wsel;
-        const uint64_t want = pm & ~b.V[at];  // a stale word only costs an atomic
-        if (want) {
-          nb = want & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)want);
-          if (nb) atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
-        }
+        nb = pm & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)pm);
+        if (nb) atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
       }
       pc += (uint32_t)__popcll(nb);
       const uint64_t hit = __ballot(nb != 0);
