@@ -180,33 +180,52 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
 }
 
 // The next frontier list from the bitmap left by level `level` (item
-// order; the bitmap is cleared): one bitmap word per lane, positions from a
-// scan over the wavefront and one atomic add per wavefront.
-__global__ void k_bfs_compact(BfsView b, uint32_t level) {
+// order; the bitmap is cleared): four bitmap words per thread, positions
+// from a scan over the workgroup and one atomic add per workgroup (one add
+// per wavefront made the adds of a launch contend on the list size).
+constexpr uint32_t kCompactWords = 4;
+
+__global__ void __launch_bounds__(256) k_bfs_compact(BfsView b, uint32_t level) {
   if (b.lcount[level % 3] == 0) return;  // an empty level marks nothing
-  const uint32_t words = (uint32_t)(((uint64_t)b.n * b.ntiles + 63) / 64), lane = threadIdx.x & 63;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t w = 0;
-  if (i < words) {
-    w = b.nbits[i];
-    if (w) b.nbits[i] = 0;
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t base_sh;
+  const uint64_t words = ((uint64_t)b.n * b.ntiles + 63) / 64;
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t w0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kCompactWords;
+  uint64_t w[kCompactWords];
+  uint32_t c = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kCompactWords; ++k) {
+    w[k] = w0 + k < words ? b.nbits[w0 + k] : 0ull;
+    if (w[k]) b.nbits[w0 + k] = 0;
+    c += (uint32_t)__popcll(w[k]);
   }
-  const uint32_t c = (uint32_t)__popcll(w);
   uint32_t incl = c;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = __shfl_up(incl, off);
     if (lane >= (uint32_t)off) incl += y;
   }
-  const uint32_t total = __shfl(incl, 63);
-  if (!total) return;
-  uint32_t base = 0;
-  if (lane == 63) base = atomicAdd(&b.lcount[(level + 1) % 3], total);
-  base = __shfl(base, 63);
-  uint32_t pos = base + incl - c;
-  while (w) {
-    b.next[pos++] = i * 64 + (uint32_t)__builtin_ctzll(w);
-    w &= w - 1;
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < blockDim.x / 64; ++i) {
+      const uint32_t x = wsum[i];
+      wsum[i] = total;  // exclusive prefix of the wavefronts
+      total += x;
+    }
+    base_sh = total ? atomicAdd(&b.lcount[(level + 1) % 3], total) : 0u;
+  }
+  __syncthreads();
+  uint32_t pos = base_sh + wsum[wv] + incl - c;
+#pragma unroll
+  for (uint32_t k = 0; k < kCompactWords; ++k) {
+    uint64_t x = w[k];
+    while (x) {
+      b.next[pos++] = (uint32_t)((w0 + k) * 64 + (uint64_t)__builtin_ctzll(x));
+      x &= x - 1;
+    }
   }
 }
 
@@ -235,8 +254,9 @@ void launch_bfs_level(const GraphView& g, const MemoView& m, const BfsView& b, u
 }
 
 void launch_bfs_compact(const BfsView& b, uint32_t level, hipStream_t st) {
-  const uint32_t words = (uint32_t)(((uint64_t)b.n * b.ntiles + 63) / 64);
-  hipLaunchKernelGGL(k_bfs_compact, dim3((words + 255) / 256), dim3(256), 0, st, b, level);
+  const uint64_t words = ((uint64_t)b.n * b.ntiles + 63) / 64;
+  const uint64_t per_block = 256ull * kCompactWords;
+  hipLaunchKernelGGL(k_bfs_compact, dim3((uint32_t)((words + per_block - 1) / per_block)), dim3(256), 0, st, b, level);
 }
 
 void launch_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words, uint32_t copies, hipStream_t st) {
