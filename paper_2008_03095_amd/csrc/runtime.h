@@ -175,5 +175,6 @@ struct im_graph {
   double phase_ms[4] = {0, 0, 0, 0};
   uint64_t last_evals = 0;
   uint64_t last_search[4] = {0, 0, 0, 0};  // memo-free searches: levels, items, arcs, live pairs
+  uint32_t spread_depth = 0;                // levels of the last memo-free spread (first-group guess)
   infuse::GraphView view() const;
 };

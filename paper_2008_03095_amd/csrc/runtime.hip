@@ -1139,16 +1139,19 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   return s;
 }
 
-// The levels of a search, enqueued eight at a time: each level reads its
+// The levels of a search, enqueued in groups: each level reads its
 // frontier size on the device (an empty frontier makes the rest no-ops) and
-// the host looks at it once per group.  The seed kernel has set the list
-// sizes of level 1; frontier sets fa / fb and lists la / lb alternate.
+// the host looks at it once per group.  The first group has `first` levels
+// (a caller's guess of the depth, 8 to 64: a surplus level costs two empty
+// launches, a missing one a host round trip), the later ones 8.  The
+// seed kernel has set the list sizes of level 1; frontier sets fa / fb and
+// lists la / lb alternate.
 static hipError_t bfs_levels(im_ctx* c, const GraphView& gv, const MemoView& mv, BfsView bv, uint64_t* fa,
-                             uint64_t* fb, uint32_t* la, uint32_t* lb, hipStream_t st, uint32_t* levels) {
-  constexpr int kGroup = 8;
+                             uint64_t* fb, uint32_t* la, uint32_t* lb, hipStream_t st, uint32_t* levels,
+                             uint32_t first = 8) {
   hipError_t e = hipSuccess;
-  for (uint32_t level = 1;;) {
-    for (int k = 0; k < kGroup; ++k, ++level) {
+  for (uint32_t level = 1, group = std::min(std::max(first, 8u), 64u);; group = 8) {
+    for (uint32_t k = 0; k < group; ++k, ++level) {
       bv.F = fa;
       bv.N = fb;
       bv.cur = la;
@@ -1258,7 +1261,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   {
     KTimer t(c, "sigma_direct", st);
     launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
-    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &nlev);
+    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &nlev, g->spread_depth + 2);
   }
   std::vector<unsigned long long> hb(b_cnt / 8);
   if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), cnt, b_cnt, hipMemcpyDeviceToHost, st);
@@ -1270,6 +1273,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   unsigned long long h = 0;
   for (uint32_t k = 0; k < kCountSlots; ++k) h += hc[k];
   g->last_search[0] = nlev;
+  g->spread_depth = nlev;
   for (int k = 1; k < 4; ++k) g->last_search[k] = 0;
   for (uint32_t k = 0; k < kCountSlots; ++k)
     for (int j = 0; j < 3; ++j) g->last_search[1 + j] += hs[k * 3 + j];
@@ -1365,6 +1369,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   std::vector<unsigned long long> hcnt((size_t)copies * kCountSlots);
   // searches from the sources src[c] of copies 0 .. nc-1, each over the
   // visited set Vv (nc copies); counts[c] receives copy c's new bits
+  uint32_t depth[2] = {0, 0};  // levels of the last batch search and of the last commit search
   auto search = [&](uint64_t* Vv, uint32_t nc) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(counts), (uint64_t)nc * kCountSlots * 2, 0u, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dS, hsrc.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st);
@@ -1382,7 +1387,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
     bv.stats = c->profiling >= 1 ? wstats : nullptr;
     launch_bfs_seed(mv, bv, dS, nc, st);
     uint32_t lv = 0;
-    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &lv);
+    uint32_t& d = depth[Vv == Vs ? 1 : 0];
+    if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &lv, d + 2);
+    d = lv;
     total_levels += lv;
   };
   std::vector<int64_t> key(n, INT64_MAX), when(n, -1);
