@@ -44,27 +44,44 @@ __device__ inline void add_count(const BfsView& b, uint32_t copy, uint32_t pc) {
 
 // Seeds (virtual ids): every sample column of every tile is visited; the
 // columns where the seed was not visited before join the frontier and the
-// count (V may start from a covered set, whose vertices add nothing).
-// Thread 0 also sets the list sizes of the first level (the seed list is
-// level 1's frontier, level 2's list starts empty) and the level count.
-__global__ void k_bfs_seed(MemoView m, BfsView b, const uint32_t* S, uint32_t len) {
+// count (V may start from a covered set, whose vertices add nothing).  The
+// items (seed, tile) are appended to the first list, kPieces entries for a
+// split row: positions from a scan over the wavefront, one add per
+// wavefront.
+__global__ void k_bfs_seed(GraphView g, MemoView m, BfsView b, const uint32_t* S, uint32_t len) {
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0) {
-    b.lcount[1] = len * m.ntiles;
-    b.lcount[2] = 0;
-    *b.levels = 0;
+  const uint32_t lane = threadIdx.x & 63;
+  const bool act = k < (uint64_t)len * m.ntiles * 4;
+  uint32_t v = 0, t = 0, cnt = 0;
+  if (act) {
+    const uint32_t s = (uint32_t)(k / (m.ntiles * 4)), r = (uint32_t)(k % (m.ntiles * 4)), i = r % 4;
+    v = S[s];
+    t = r / 4;
+    const uint64_t w = valid_word(m.R, t, i);
+    const uint64_t at = ((uint64_t)v * m.ntiles + t) * 4 + i;
+    const uint64_t nb = w & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)w);
+    if (nb) {
+      atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
+      atomicAdd(&b.counts[(uint64_t)(v / b.gn) * kCountSlots + k % kCountSlots], (unsigned long long)__popcll(nb));
+    }
+    if (i == 0) {
+      const uint32_t gv = v % b.gn;
+      cnt = b.pieces > 1 && g.row_ptr[gv + 1] - g.row_ptr[gv] > kSplitArcs ? b.pieces : 1u;
+    }
   }
-  if (k >= (uint64_t)len * m.ntiles * 4) return;
-  const uint32_t s = (uint32_t)(k / (m.ntiles * 4)), r = (uint32_t)(k % (m.ntiles * 4));
-  const uint32_t v = S[s], t = r / 4, i = r % 4;
-  const uint64_t w = valid_word(m.R, t, i);
-  const uint64_t at = ((uint64_t)v * m.ntiles + t) * 4 + i;
-  const uint64_t nb = w & ~(uint64_t)atomicOr((unsigned long long*)&b.V[at], (unsigned long long)w);
-  if (nb) {
-    atomicOr((unsigned long long*)&b.N[at], (unsigned long long)nb);
-    atomicAdd(&b.counts[(uint64_t)(v / b.gn) * kCountSlots + k % kCountSlots], (unsigned long long)__popcll(nb));
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off);
+    if (lane >= (uint32_t)off) incl += y;
   }
-  if (i == 0) b.next[(uint64_t)s * m.ntiles + t] = v * m.ntiles + t;  // item (seed, tile)
+  const uint32_t total = __shfl(incl, 63);
+  if (!total) return;
+  uint32_t base = 0;
+  if (lane == 63) base = atomicAdd(&b.lcount[1], total);
+  base = __shfl(base, 63);
+  const uint32_t item = v * m.ntiles + t;
+  for (uint32_t p = 0; p < cnt; ++p) b.next[base + incl - cnt + p] = item | (cnt > 1 ? p << kPieceShift : 0u);
 }
 
 // One level.  A wavefront takes (frontier vertex, tile) items; for each
@@ -99,7 +116,9 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   for (uint64_t it = it0; it < items; it += nw) {
     const uint32_t e0 = uni(en);
     en = b.cur[min(it + nw, items - 1)];
-    const uint32_t vv = e0 / m.ntiles, t = e0 % m.ntiles;
+    const uint32_t item = b.pieces > 1 ? e0 & ((1u << kPieceShift) - 1) : e0;
+    const uint32_t piece = b.pieces > 1 ? e0 >> kPieceShift : 0u;
+    const uint32_t vv = item / m.ntiles, t = item % m.ntiles;
     const uint32_t v = vv % b.gn, cb = vv - v;  // graph vertex, first virtual id of its copy
     if (cb / b.gn != pcopy) {  // counts are added when the copy changes, and at the end
       if (__ballot(pc != 0)) add_count(b, pcopy, pc);
@@ -110,8 +129,17 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     const uint64_t f0 = fw[0], f1 = fw[1], f2 = fw[2], f3 = fw[3];
     const uint32_t rb = g.row_ptr[v], re = g.row_ptr[v + 1];
     const uint4 x4 = load_tile_x(m, t, lane);
-    if (lane < 4) fw[lane] = 0;
-    ++s_items;
+    uint32_t beg = uni(rb), end = uni(re);
+    const bool split = b.pieces > 1 && end - beg > kSplitArcs;
+    if (!split) {
+      if (lane < 4) fw[lane] = 0;  // a split item's words are cleared after the level, once every piece has read them
+      ++s_items;
+    } else {
+      s_items += piece == 0;
+      const uint32_t len = ((end - beg + b.pieces - 1) / b.pieces + kWave - 1) & ~(uint32_t)(kWave - 1);
+      beg = min(end, beg + piece * len);
+      end = min(end, beg + len);
+    }
     uint32_t fb[4];
     fb[0] = (uint32_t)(f0 >> lane) & 1u;
     fb[1] = (uint32_t)(f1 >> lane) & 1u;
@@ -119,8 +147,7 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     fb[3] = (uint32_t)(f3 >> lane) & 1u;
     TileCtx tc;
     tile_from_x(m, t, lane, x4, m.kshift, tc, PER_EDGE);
-    const uint32_t beg = uni(rb), end = uni(re);
-    const bool inreg = end - beg <= (uint32_t)kWave;
+    const bool inreg = !split && end - beg <= (uint32_t)kWave;
     s_arcs += end - beg;
     uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
     if (inreg && beg + lane < end) {
@@ -169,36 +196,53 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     __shared__ unsigned long long ws[3];
     if (threadIdx.x < 3) ws[threadIdx.x] = 0;
     __syncthreads();
-    if (lane == 0 && s_items) {
+    if (lane == 0 && (s_items | s_arcs)) {  // a wavefront may have run pieces of split items only
       atomicAdd(&ws[0], (unsigned long long)s_items);
       atomicAdd(&ws[1], (unsigned long long)s_arcs);
       atomicAdd(&ws[2], (unsigned long long)s_live);
     }
     __syncthreads();
-    if (threadIdx.x < 3 && ws[0]) atomicAdd(&b.stats[(blockIdx.x % kCountSlots) * 3 + threadIdx.x], ws[threadIdx.x]);
+    if (threadIdx.x < 3 && ws[threadIdx.x])
+      atomicAdd(&b.stats[(blockIdx.x % kCountSlots) * 3 + threadIdx.x], ws[threadIdx.x]);
   }
 }
 
 // The next frontier list from the bitmap left by level `level` (item
-// order; the bitmap is cleared): four bitmap words per thread, positions
-// from a scan over the workgroup and one atomic add per workgroup (one add
-// per wavefront made the adds of a launch contend on the list size).
+// order; the bitmap is cleared; kPieces entries for an item of a split
+// row): four bitmap words per thread, positions from a scan over the
+// workgroup and one atomic add per workgroup (one add per wavefront made the
+// adds of a launch contend on the list size).  It also clears the frontier
+// words of the level's split items, which their pieces left in place.
 constexpr uint32_t kCompactWords = 4;
 
 __global__ void __launch_bounds__(256) k_bfs_compact(BfsView b, uint32_t level) {
-  if (b.lcount[level % 3] == 0) return;  // an empty level marks nothing
+  const uint32_t ncur = b.lcount[level % 3];
+  if (ncur == 0) return;  // an empty level marks nothing
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t base_sh;
+  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b.pieces > 1)
+    for (uint64_t k = gtid; k < ncur; k += (uint64_t)gridDim.x * blockDim.x) {
+      const uint32_t e = b.cur[k];
+      if (e >> kPieceShift == 1) {  // piece 1 is listed once per split item
+        uint64_t* fw = b.F + (uint64_t)(e & ((1u << kPieceShift) - 1)) * 4;
+        fw[0] = 0;
+        fw[1] = 0;
+        fw[2] = 0;
+        fw[3] = 0;
+      }
+    }
   const uint64_t words = ((uint64_t)b.n * b.ntiles + 63) / 64;
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t w0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kCompactWords;
-  uint64_t w[kCompactWords];
+  const uint64_t w0 = gtid * kCompactWords;
+  uint64_t w[kCompactWords], hm[kCompactWords];
   uint32_t c = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kCompactWords; ++k) {
     w[k] = w0 + k < words ? b.nbits[w0 + k] : 0ull;
     if (w[k]) b.nbits[w0 + k] = 0;
-    c += (uint32_t)__popcll(w[k]);
+    hm[k] = b.pieces > 1 && w0 + k < words ? w[k] & b.hubmask[w0 + k] : 0ull;
+    c += (uint32_t)__popcll(w[k] & ~hm[k]) + b.pieces * (uint32_t)__popcll(hm[k]);
   }
   uint32_t incl = c;
 #pragma unroll
@@ -223,9 +267,29 @@ __global__ void __launch_bounds__(256) k_bfs_compact(BfsView b, uint32_t level) 
   for (uint32_t k = 0; k < kCompactWords; ++k) {
     uint64_t x = w[k];
     while (x) {
-      b.next[pos++] = (uint32_t)((w0 + k) * 64 + (uint64_t)__builtin_ctzll(x));
+      const uint32_t bit = (uint32_t)__builtin_ctzll(x);
+      const uint32_t item = (uint32_t)((w0 + k) * 64 + bit);
       x &= x - 1;
+      if ((hm[k] >> bit) & 1ull)
+        for (uint32_t p = 0; p < b.pieces; ++p) b.next[pos++] = item | p << kPieceShift;
+      else
+        b.next[pos++] = item;
     }
+  }
+}
+
+// Bit (vertex * ntiles + t) is set when the vertex (its graph vertex, for
+// a copy) has more than kSplitArcs arcs.
+__global__ void k_bfs_hubmask(GraphView g, BfsView b, uint64_t* mask) {
+  const uint64_t items = (uint64_t)b.n * b.ntiles, words = (items + 63) / 64;
+  for (uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; wi < words;
+       wi += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t bits = 0;
+    for (uint32_t k = 0; k < 64 && wi * 64 + k < items; ++k) {
+      const uint32_t v = (uint32_t)((wi * 64 + k) / b.ntiles % b.gn);
+      if (g.row_ptr[v + 1] - g.row_ptr[v] > kSplitArcs) bits |= 1ull << k;
+    }
+    mask[wi] = bits;
   }
 }
 
@@ -237,9 +301,17 @@ __global__ void k_bfs_replicate(const uint64_t* src, uint64_t* V, uint64_t words
 
 // ---- launchers ---------------------------------------------------------------
 
-void launch_bfs_seed(const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len, hipStream_t st) {
-  const uint64_t k = std::max<uint64_t>(1, (uint64_t)len * m.ntiles * 4);
-  hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, m, b, S, len);
+void launch_bfs_seed(const GraphView& g, const MemoView& m, const BfsView& b, const uint32_t* S, uint32_t len,
+                     hipStream_t st) {
+  const uint64_t k = (uint64_t)len * m.ntiles * 4;
+  if (k) hipLaunchKernelGGL(k_bfs_seed, dim3((uint32_t)((k + 255) / 256)), dim3(256), 0, st, g, m, b, S, len);
+}
+
+void launch_bfs_hubmask(const GraphView& g, const BfsView& b, uint64_t* mask, hipStream_t st) {
+  const uint64_t words = ((uint64_t)b.n * b.ntiles + 63) / 64;
+  if (words)
+    hipLaunchKernelGGL(k_bfs_hubmask, dim3((uint32_t)std::min<uint64_t>(4096, (words + 255) / 256)), dim3(256), 0,
+                       st, g, b, mask);
 }
 
 // A fixed grid (the frontier size is known only on the device): four

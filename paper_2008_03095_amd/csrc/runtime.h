@@ -164,6 +164,7 @@ struct im_graph {
   uint2* hub_piece = nullptr;  // {hub, first slot} of every 64-slot piece of their smaller neighbours
   uint32_t nhubs = 0;
   uint32_t hub_pieces = 0;
+  uint32_t nlong = 0;  // vertices with more than kSplitArcs device arcs (split by the memo-free search)
   double p = 0.0;
   uint32_t R = 0, seed = 0;
   bool params_set = false;

@@ -891,6 +891,7 @@ static im_status load_graph(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t*
   const size_t b_poff = align256((size_t)hub_piece.size() * 8 + 8);
   g->nhubs = (uint32_t)hubs.size();
   g->hub_pieces = (uint32_t)hub_piece.size();
+  for (uint32_t u = 0; u < n; ++u) g->nlong += rp[u + 1] - rp[u] > kSplitArcs;
   void* base = nullptr;
   s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff, &base);
   if (s != IM_OK) {
@@ -1200,12 +1201,15 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   const size_t b_edges = align256((size_t)g->nnz * 8), b_x = align256((size_t)Rs * 4);
   const size_t b_pos = align256((size_t)R * 4), b_scr = align256((size_t)x_sort_scratch_elems(R) * 8);
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
-  const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)n * ntiles * 4);
-  const size_t b_nb = align256(((size_t)n * ntiles + 63) / 64 * 8);
+  // long rows are split into kPieces entries when item ids leave room for the piece
+  const uint32_t pieces = (uint64_t)n * ntiles <= (1ull << kPieceShift) && g->nlong ? kPieces : 1u;
+  const uint64_t entries = ((uint64_t)n + (uint64_t)(pieces - 1) * g->nlong) * ntiles;
+  const size_t b_bits = align256((size_t)words * 8), b_list = align256((size_t)entries * 4);
+  const size_t b_nb = align256(((size_t)n * ntiles + 63) / 64 * 8), b_hm = pieces > 1 ? b_nb : 0;
   // cnt: [0..2] list sizes, [3] levels; then the count slots and the work counts
   const size_t o_counts = 64, o_stats = align256(o_counts + kCountSlots * 8);
   const size_t b_cnt = align256(o_stats + kCountSlots * 24), b_S = align256((size_t)len * 4);
-  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 2 * b_list + b_nb + b_cnt + b_S;
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + 3 * b_bits + 2 * b_list + b_nb + b_cnt + b_S + b_hm;
   void* base = nullptr;
   s = ctx_alloc(c, total, &base);
   if (s != IM_OK) return s;
@@ -1236,6 +1240,7 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   uint64_t* nbits = reinterpret_cast<uint64_t*>(take(b_nb));
   uint32_t* cnt = reinterpret_cast<uint32_t*>(take(b_cnt));
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
+  uint64_t* hubmask = pieces > 1 ? reinterpret_cast<uint64_t*>(take(b_hm)) : nullptr;
   unsigned long long* counts = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(cnt) + o_counts);
   unsigned long long* wstats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(cnt) + o_stats);
   mv.edges = edges;
@@ -1257,10 +1262,13 @@ extern "C" im_status im_estimate_sigma_direct(im_graph* g, const uint32_t* S, ui
   bv.nbits = nbits;
   bv.counts = counts;
   bv.stats = c->profiling >= 1 ? wstats : nullptr;  // work counts cost atomics: kept while profiling
+  bv.pieces = pieces;
+  bv.hubmask = hubmask;
   uint32_t nlev = 0;
   {
     KTimer t(c, "sigma_direct", st);
-    launch_bfs_seed(mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
+    if (hubmask) launch_bfs_hubmask(gv, bv, hubmask, st);
+    launch_bfs_seed(gv, mv, bv, dS, len, st);  // the seeds: visited, and the first frontier in A / L0
     if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &nlev, g->spread_depth + 2);
   }
   std::vector<unsigned long long> hb(b_cnt / 8);
@@ -1305,7 +1313,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const uint32_t n = g->n, R = g->R, Rs = round_up(R, kTile), ntiles = Rs / kTile;
   const uint64_t T = thr_of(g->p);
   const uint64_t words = (uint64_t)n * ntiles * 4;  // u64 words of one copy's bit sets
-  const uint64_t per_copy = 3 * words * 8 + 2 * (uint64_t)n * ntiles * 4 + (uint64_t)n * ntiles / 8 + 1;
+  // list entries per copy: one per item, kPieces for an item of a long row (split when ids leave room)
+  const uint64_t entries_max = ((uint64_t)n + (uint64_t)(kPieces - 1) * g->nlong) * ntiles;
+  const uint64_t per_copy = 3 * words * 8 + 2 * entries_max * 4 + (uint64_t)n * ntiles / 4 + 1;
   const uint64_t copy_budget = 8ull << 30;
   if ((uint64_t)n * ntiles > UINT32_MAX) return fail(IM_ERR_INVALID_ARG, "n * ceil(R / 256) exceeds 2^32 - 1");
   // copies * n * ntiles level items must fit in 32 bits
@@ -1316,9 +1326,12 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   const size_t b_one = align256((size_t)words * 8), b_many = align256((size_t)words * 8 * copies);
   // lc: [0..2] list sizes, [3] levels; then the work counts and the count slots of each copy
   const size_t o_stats = 64, o_counts = align256(o_stats + kCountSlots * 24);
-  const size_t b_list = align256((size_t)n * ntiles * 4 * copies), b_cnt = align256(o_counts + (size_t)copies * kCountSlots * 8);
+  const uint32_t pieces = (uint64_t)n * ntiles * copies <= (1ull << kPieceShift) && g->nlong ? kPieces : 1u;
+  const uint64_t entries = ((uint64_t)n + (uint64_t)(pieces - 1) * g->nlong) * ntiles * copies;
+  const size_t b_list = align256((size_t)entries * 4), b_cnt = align256(o_counts + (size_t)copies * kCountSlots * 8);
   const size_t b_nb = align256(((size_t)n * ntiles * copies + 63) / 64 * 8), b_S = align256((size_t)copies * 4);
-  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S;
+  const size_t b_hm = pieces > 1 ? b_nb : 0;
+  const size_t total = b_edges + 2 * b_x + b_pos + b_scr + b_one + 3 * b_many + 2 * b_list + b_nb + b_cnt + b_S + b_hm;
   void* base = nullptr;
   im_status s = ctx_alloc(c, total, &base);
   if (s != IM_OK) return s;
@@ -1352,12 +1365,20 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   unsigned long long* wstats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lc) + o_stats);
   unsigned long long* counts = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lc) + o_counts);
   uint32_t* dS = reinterpret_cast<uint32_t*>(take(b_S));
+  uint64_t* hubmask = pieces > 1 ? reinterpret_cast<uint64_t*>(take(b_hm)) : nullptr;
   mv.edges = edges;
   mv.xs = xs;
   const GraphView gv = g->view();
   launch_edge_hash(gv, g->seed, edges, st);
   launch_x_sort(g->seed, R, Rs, scr, xs, inv, pos, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(Vs), words * 2, 0u, st);
+  if (hubmask) {  // over the items of every copy
+    BfsView hv = {};
+    hv.n = n * copies;
+    hv.gn = n;
+    hv.ntiles = ntiles;
+    launch_bfs_hubmask(gv, hv, hubmask, st);
+  }
   // the frontier sets and the bitmap start zero and every search leaves them zero
   launch_fill_u32(reinterpret_cast<uint32_t*>(A), words * 2 * copies, 0u, st);
   launch_fill_u32(reinterpret_cast<uint32_t*>(B), words * 2 * copies, 0u, st);
@@ -1372,6 +1393,7 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
   uint32_t depth[2] = {0, 0};  // levels of the last batch search and of the last commit search
   auto search = [&](uint64_t* Vv, uint32_t nc) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(counts), (uint64_t)nc * kCountSlots * 2, 0u, st);
+    launch_fill_u32(lc, 4, 0u, st);  // list sizes and level count
     if (e == hipSuccess) e = hipMemcpyAsync(dS, hsrc.data(), (size_t)nc * 4, hipMemcpyHostToDevice, st);
     BfsView bv = {};
     bv.n = n * nc;
@@ -1385,7 +1407,9 @@ extern "C" im_status im_select_seeds_direct(im_graph* g, uint32_t K, uint32_t* s
     bv.nbits = nbits;
     bv.counts = counts;
     bv.stats = c->profiling >= 1 ? wstats : nullptr;
-    launch_bfs_seed(mv, bv, dS, nc, st);
+    bv.pieces = pieces;
+    bv.hubmask = hubmask;
+    launch_bfs_seed(gv, mv, bv, dS, nc, st);
     uint32_t lv = 0;
     uint32_t& d = depth[Vv == Vs ? 1 : 0];
     if (e == hipSuccess) e = bfs_levels(c, gv, mv, bv, A, B, L0, L1, st, &lv, d + 2);

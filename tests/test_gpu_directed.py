@@ -184,3 +184,29 @@ def test_search_work_counts_on_a_forced_live_path(gpu_ctx):
         assert G.search_stats() == dict(levels=k - 5, items=0, arcs=0, live_pairs=0)
     finally:
         G.free()
+
+
+def test_search_on_a_split_row(gpu_ctx):
+    """A row longer than the split threshold is walked in pieces by several
+    wavefronts: on a forced-live out-star with 1,000 arcs the spread, the
+    levels and the work counts are exact (the centre's item counts once,
+    every arc once, every arc is live)."""
+    k = 1000
+    g = from_arc_list(k + 1, np.zeros(k, np.int64), np.arange(1, k + 1))
+    announce("search on a split row: out-star with 1000 arcs, p = 1")
+    G = P.Graph.from_csr(gpu_ctx, g)
+    try:
+        G.set_params(1.0, 300, 5)  # two tiles, the second ragged
+        gpu_ctx.set_profiling(1)
+        try:
+            cnt, _, levels = G.estimate_sigma_direct([0])
+            assert cnt == 300 * (k + 1) and levels == 2
+            assert G.search_stats() == dict(levels=2, items=2 * (1 + k), arcs=2 * k, live_pairs=2 * k)
+            cnt, _, levels = G.estimate_sigma_direct([0, 7])  # a leaf seed adds itself only
+            assert cnt == 300 * (k + 1) and levels == 2
+        finally:
+            gpu_ctx.set_profiling(0)
+        seeds, marg, cover = G.select_seeds_direct(2)
+        assert list(seeds) == [0, 1] and list(marg) == [300 * (k + 1), 0] and cover == 300 * (k + 1)
+    finally:
+        G.free()
