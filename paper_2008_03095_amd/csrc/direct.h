@@ -17,7 +17,7 @@ constexpr uint32_t kCountSlots = 128;
 // kSplitArcs arcs is listed kPieces times, entry = item | piece << kPieceShift,
 // and each piece walks an eighth of the row, so no item of a level waits on
 // a whole hub row.  Only when item ids fit below 2^kPieceShift.
-constexpr uint32_t kSplitArcs = 512;
+constexpr uint32_t kSplitArcs = 256;
 constexpr uint32_t kPieces = 8;
 constexpr uint32_t kPieceShift = 29;
 
