@@ -221,17 +221,35 @@ __global__ void __launch_bounds__(256) k_bfs_compact(BfsView b, uint32_t level) 
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t base_sh;
   const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b.pieces > 1)
-    for (uint64_t k = gtid; k < ncur; k += (uint64_t)gridDim.x * blockDim.x) {
-      const uint32_t e = b.cur[k];
-      if (e >> kPieceShift == 1) {  // piece 1 is listed once per split item
+  if (b.pieces > 1) {
+    // piece 1 is listed once per split item; the list is read four entries
+    // per load, two loads in flight per thread
+    const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+    auto clear = [&](uint32_t e) {
+      if (e >> kPieceShift == 1) {
         uint64_t* fw = b.F + (uint64_t)(e & ((1u << kPieceShift) - 1)) * 4;
         fw[0] = 0;
         fw[1] = 0;
         fw[2] = 0;
         fw[3] = 0;
       }
+    };
+    const uint64_t quads = ncur / 4;
+    const uint4* cq = reinterpret_cast<const uint4*>(b.cur);
+    for (uint64_t k = gtid; k < quads; k += 2 * nthr) {
+      const uint4 a = cq[k];
+      const uint4 c2 = k + nthr < quads ? cq[k + nthr] : make_uint4(0, 0, 0, 0);
+      clear(a.x);
+      clear(a.y);
+      clear(a.z);
+      clear(a.w);
+      clear(c2.x);
+      clear(c2.y);
+      clear(c2.z);
+      clear(c2.w);
     }
+    if (gtid < ncur % 4) clear(b.cur[quads * 4 + gtid]);
+  }
   const uint64_t words = ((uint64_t)b.n * b.ntiles + 63) / 64;
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t w0 = gtid * kCompactWords;
