@@ -541,6 +541,8 @@ def main():
     alg_bytes = (8 * R + R // 8) * (evals + K)
     achieved = alg_bytes / (roof_avg * 1e-3) / 1e9 if roof_avg else None
     traffic = read_traffic()
+    if traffic and (traffic.get("workload") != args.workload or args.weights != "const"):
+        traffic = None  # the counters were taken on another workload
     phases /= args.steps
     t_cc = phases[1]
     names = ["edge_hash", "x_sort", "hook", "hook_hubs", "lists", "link", "link_hubs", "flatten", "count",
