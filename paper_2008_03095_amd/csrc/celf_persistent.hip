@@ -584,8 +584,8 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
     const uint64_t k = ld64(&c.key[v]);
     mx = k > mx ? k : mx;
   }
-  mx = p_wmax(mx);
-  if ((threadIdx.x & 63) == 0 && mx) g_max64(&x->kmax, mx);
+  mx = block_max(L, mx);  // one max per workgroup, skipped when not above the value seen
+  if (threadIdx.x == 0 && mx && mx > ld64(&x->kmax)) g_max64(&x->kmax, mx);
   if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint64_t kmax = ld64(&x->kmax);
   if (kmax == 0) {  // nothing unselected: the caller reports it
@@ -674,24 +674,28 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
       for (uint32_t i = threadIdx.x; i < kBins; i += kPBlock) st32(&x->hist[i], 0u);
     if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   }
-  // collect the keys at or above the threshold
+  // collect the keys at or above the threshold: positions from a scan over
+  // the workgroup, one add per workgroup and pass
   uint64_t outside = 0;
-  for (uint32_t v = gtid; v < n; v += gstride) {
-    const uint64_t k = ld64(&c.key[v]);
-    if (k == 0) continue;
-    if (k >= thresh) {
-      const uint32_t at = g_add(&x->pool_cnt, 1u);
-      if (at < kPool) {
-        st32(&x->pool_id[at], v);
-        st64(&x->pool_key[at], k);
-      }
-    } else if (k > outside) {
-      outside = k;
+  for (uint32_t vb = G.bi * kPBlock; vb < n; vb += gstride) {  // uniform over the workgroup
+    const uint32_t v = vb + threadIdx.x;
+    const uint64_t k = v < n ? ld64(&c.key[v]) : 0ull;
+    const uint32_t take = k != 0 && k >= thresh;
+    if (k != 0 && k < thresh && k > outside) outside = k;
+    uint32_t tot;
+    const uint32_t pre = block_exscan(L, take, tot);
+    if (!tot) continue;
+    if (threadIdx.x == 0) L.cg[0] = g_add(&x->pool_cnt, tot);
+    __syncthreads();
+    const uint32_t at = L.cg[0] + pre;
+    if (take && at < kPool) {
+      st32(&x->pool_id[at], v);
+      st64(&x->pool_key[at], k);
     }
+    __syncthreads();  // L.cg[0] is rewritten by the next pass
   }
-  outside = p_wmax(outside);
-  if ((threadIdx.x & 63) == 0 && outside)
-    g_max64(&x->out_bound, outside);
+  outside = block_max(L, outside);
+  if (threadIdx.x == 0 && outside && outside > ld64(&x->out_bound)) g_max64(&x->out_bound, outside);
   if (!grid_sync(x, G, gen, clk, PClock::kRebuild)) return false;
   const uint32_t cnt = ld32(&x->pool_cnt);
   if (cnt > kPool) {  // the threshold admits at most kPool keys
@@ -750,7 +754,7 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
 }
 
 // Bulk evaluation of every stale vertex whose key exceeds kstar.
-__device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t kstar, uint32_t& gen,
+__device__ bool bulk_eval(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t s, uint64_t kstar, uint32_t& gen,
                           PClock& clk, uint64_t& evals) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
@@ -762,23 +766,22 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, uint32_t s, uint64_t 
   // the last commit's key store and the counter reset must be visible
   if (G.bi == 0 && threadIdx.x == 0) st32(&x->bulk_cnt, 0u);
   if (!grid_sync(x, G, gen, clk, PClock::kBulk)) return false;
-  // 1. list the candidates (wave-aggregated slots)
-  for (uint32_t base = gtid - lane; base < n; base += gstride) {
-    const uint32_t v = base + lane;
-    bool take = false;
+  // 1. list the candidates: positions from a scan over the workgroup and one
+  // add per workgroup and pass (an add per wavefront made them contend)
+  for (uint32_t vb = G.bi * kPBlock; vb < n; vb += gstride) {  // uniform over the workgroup
+    const uint32_t v = vb + threadIdx.x;
+    uint32_t take = 0;
     if (v < n) {
       const uint64_t k = ld64(&c.key[v]);
       take = k > kstar && ld32(&c.iter[v]) != s;
     }
-    const uint64_t mask = __ballot(take);
-    if (!mask) continue;
-    uint32_t slot0 = 0;
-    if (lane == 0) slot0 = g_add(&x->bulk_cnt, (uint32_t)__popcll(mask));
-    slot0 = __shfl(slot0, 0);
-    if (take) {
-      const uint32_t at = slot0 + (uint32_t)__popcll(mask & ((1ull << lane) - 1));
-      st32(&a.blist[at], v);
-    }
+    uint32_t tot;
+    const uint32_t pre = block_exscan(L, take, tot);
+    if (!tot) continue;
+    if (threadIdx.x == 0) L.cg[0] = g_add(&x->bulk_cnt, tot);
+    __syncthreads();
+    if (take) st32(&a.blist[L.cg[0] + pre], v);
+    __syncthreads();  // L.cg[0] is rewritten by the next pass
   }
   if (!grid_sync(x, G, gen, clk, PClock::kBulk)) return false;
   const uint32_t cnt = ld32(&x->bulk_cnt);
@@ -999,7 +1002,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       return;
     }
     if (nf && step_rebuilds > 0)
-      if (!bulk_eval(a, G, s, fbest, gen, clk, evals)) return;
+      if (!bulk_eval(a, G, L, s, fbest, gen, clk, evals)) return;
     if (threadIdx.x == 0) L.lead = kInvalid;  // the rebuilt F did not come from one round
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     synced = true;
