@@ -13,10 +13,11 @@
 // frontier list (in item order), so only (vertex, tile) pairs whose
 // frontier is not empty are visited.  V and N are written only by atomics
 // while a level runs; F is only read, then cleared by the wavefront that
-// owns the item, so both frontier sets are all zero again once a search
-// ends.  The count is the number of bits the search sets in V,
-// summed from the atomics' old values: sum over samples of |R_r(S)|, seeds
-// included (beyond the set V starts from).
+// owns the item (for an item split into pieces, by the listing kernel after
+// the level), so both frontier sets are all zero again once a search ends.
+// The count is the number of bits the search sets in V, summed from the
+// atomics' old values: sum over samples of |R_r(S)|, seeds included (beyond
+// the set V starts from).
 #include <algorithm>
 
 #include "common.h"
@@ -84,14 +85,15 @@ __global__ void k_bfs_seed(GraphView g, MemoView m, BfsView b, const uint32_t* S
   for (uint32_t p = 0; p < cnt; ++p) b.next[base + incl - cnt + p] = item | (cnt > 1 ? p << kPieceShift : 0u);
 }
 
-// One level.  A wavefront takes (frontier vertex, tile) items; for each
-// candidate edge of the tile it forms the 256-bit set of columns where the
-// edge is live and the vertex is in the frontier, and parks it in four lanes
-// (lane 4j + i holds word i of the j-th pending target).  Sixteen targets
-// are then updated at once: each lane ors its word into V (the atomic's
-// old value decides which bits are new, so every bit is counted once), adds
-// the new ones to N, and one lane per target
-// that gained columns marks it in the next frontier's bitmap.  The item's
+// One level.  A wavefront takes list entries, each an item (frontier
+// vertex, tile) or a piece of one; for each candidate edge of the item's
+// tile (of the piece's arcs) it forms the 256-bit set of columns where the
+// edge is live and the vertex is in the frontier, and parks it in four
+// lanes (lane 4j + i holds word i of the j-th pending target).  Sixteen
+// targets are then updated at once: each lane ors its word into V (the
+// atomic's old value decides which bits are new, so every bit is counted
+// once) and the new ones into N, and one lane per target that gained
+// columns marks it in the next frontier's bitmap.  An unsplit item's
 // frontier words are cleared once read: each (vertex, tile) is one item of
 // the level.
 template <bool PER_EDGE>
@@ -102,10 +104,10 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(b.levels, level);
   const uint32_t lane = threadIdx.x & 63, wsel = lane & 3, pslot = lane >> 2;
   // item ids (vertex * ntiles + tile) fit in 32 bits (checked by the host);
-  // the item index is wave-uniform.  The item's frontier words, row bounds
-  // and tile X are requested together, and the next item's id one item
-  // ahead.  Listed items have frontier bits (seeds aside), so none is
-  // skipped: a test would defer the loads past it
+  // the entry index is wave-uniform.  The item's frontier words, row bounds
+  // and tile X are requested together, and the next entry one entry ahead.
+  // Listed items have frontier bits (seeds aside), so none is skipped: a
+  // test would defer the loads past it.
   const uint64_t nw = gridDim.x * 4;
   const uint64_t items = ncur;
   uint32_t pc = 0;        // new bits set by this lane for copy pcopy
@@ -131,8 +133,10 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
     const uint4 x4 = load_tile_x(m, t, lane);
     uint32_t beg = uni(rb), end = uni(re);
     const bool split = b.pieces > 1 && end - beg > kSplitArcs;
+    // a split item's frontier words are cleared after the level, once every
+    // piece has read them
     if (!split) {
-      if (lane < 4) fw[lane] = 0;  // a split item's words are cleared after the level, once every piece has read them
+      if (lane < 4) fw[lane] = 0;
       ++s_items;
     } else {
       s_items += piece == 0;
