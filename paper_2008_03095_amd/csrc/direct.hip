@@ -213,11 +213,11 @@ __global__ void __launch_bounds__(256) k_bfs_level(GraphView g, MemoView m, BfsV
 
 // The next frontier list from the bitmap left by level `level` (item
 // order; the bitmap is cleared; kPieces entries for an item of a split
-// row): four bitmap words per thread, positions from a scan over the
+// row): two bitmap words per thread, positions from a scan over the
 // workgroup and one atomic add per workgroup (one add per wavefront made the
 // adds of a launch contend on the list size).  It also clears the frontier
 // words of the level's split items, which their pieces left in place.
-constexpr uint32_t kCompactWords = 4;
+constexpr uint32_t kCompactWords = 2;
 
 __global__ void __launch_bounds__(256) k_bfs_compact(BfsView b, uint32_t level) {
   const uint32_t ncur = b.lcount[level % 3];
