@@ -470,7 +470,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU path (R-sharding with one all-reduce of "
-              "int64 gains) is a design, not part of this build; run with --gpus 1.", file=sys.stderr)
+              "int64 gains) is designed, not implemented; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
