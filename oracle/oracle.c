@@ -625,55 +625,89 @@ int orc_celf(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int mode,
 
 /* CELF whose re-evaluation uses the stored labels and sizes (the memo of
  * Section III-C, Algorithm 7): gain(u | S) = sum_r |C_r(u)| over the samples
- * where u's label differs from the label of every seed.  Same queue
- * discipline as orc_celf.  labels/sizes are [n][R] vertex-major. */
+ * where u's component holds no seed.  Same selection rule as orc_celf (the
+ * largest (gain, -id) at the top is committed when its gain is current for
+ * |S|, else re-evaluated and put back), with the queue of Algorithm 7 kept as
+ * a binary heap and the seeds' components of every sample as a bitmap over
+ * (label, sample), so that graphs of 10^6 vertices finish in minutes.
+ * labels/sizes are [n][R] vertex-major. */
+typedef struct {
+    int64_t gain;
+    uint32_t id;
+} heap_item;
+
+/* a ranks above b: larger gain, then smaller id */
+static int heap_above(heap_item a, heap_item b) {
+    return a.gain > b.gain || (a.gain == b.gain && a.id < b.id);
+}
+
+static void heap_sift_down(heap_item *h, uint32_t len, uint32_t i) {
+    for (;;) {
+        uint32_t l = 2 * i + 1, r = l + 1, top = i;
+        if (l < len && heap_above(h[l], h[top])) top = l;
+        if (r < len && heap_above(h[r], h[top])) top = r;
+        if (top == i) return;
+        heap_item t = h[i];
+        h[i] = h[top];
+        h[top] = t;
+        i = top;
+    }
+}
+
 int orc_celf_memo(uint32_t n, uint32_t R, const int32_t *labels, const uint32_t *sizes,
                   const int64_t *g0, uint32_t K, uint32_t *seeds, int64_t *marginal,
                   int64_t *cover_count, uint64_t *n_evals) {
     if (K > n) return -2;
-    int64_t *mg = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    heap_item *heap = (heap_item *)malloc(sizeof(heap_item) * (n ? n : 1));
     uint32_t *iter = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
-    uint8_t *is_seed = (uint8_t *)calloc(n ? n : 1, 1);
-    if (!mg || !iter || !is_seed) return -1;
-    for (uint32_t v = 0; v < n; ++v) mg[v] = g0[v];
+    const uint64_t cbits = (uint64_t)n * R;
+    uint64_t *covered = (uint64_t *)calloc(cbits / 64 + 1, sizeof(uint64_t));
+    if (!heap || !iter || !covered) {
+        free(heap);
+        free(iter);
+        free(covered);
+        return -1;
+    }
+    uint32_t len = n;
+    for (uint32_t v = 0; v < n; ++v) {
+        heap[v].gain = g0[v];
+        heap[v].id = v;
+    }
+    for (uint32_t i = n / 2; i-- > 0;) heap_sift_down(heap, len, i);
     uint32_t s_size = 0;
     int64_t cover = 0;
     uint64_t evals = 0;
     while (s_size < K) {
-        int64_t best = -1;
-        uint32_t top = 0;
-        for (uint32_t v = 0; v < n; ++v) {
-            if (is_seed[v]) continue;
-            if (mg[v] > best) {
-                best = mg[v];
-                top = v;
-            }
-        }
+        const uint32_t top = heap[0].id;
         if (iter[top] == s_size) {
             seeds[s_size] = top;
-            marginal[s_size] = mg[top];
-            cover += mg[top];
-            is_seed[top] = 1;
+            marginal[s_size] = heap[0].gain;
+            cover += heap[0].gain;
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint64_t b = (uint64_t)(uint32_t)labels[(uint64_t)top * R + r] * R + r;
+                covered[b >> 6] |= 1ull << (b & 63);
+            }
             ++s_size;
+            heap[0] = heap[--len];
+            heap_sift_down(heap, len, 0);
         } else {
             const int32_t *lu = labels + (uint64_t)top * R;
             const uint32_t *su = sizes + (uint64_t)top * R;
             int64_t gain = 0;
             for (uint32_t r = 0; r < R; ++r) {
-                int covered = 0;
-                for (uint32_t k = 0; k < s_size && !covered; ++k)
-                    covered = labels[(uint64_t)seeds[k] * R + r] == lu[r];
-                if (!covered) gain += su[r];
+                const uint64_t b = (uint64_t)(uint32_t)lu[r] * R + r;
+                if (!((covered[b >> 6] >> (b & 63)) & 1)) gain += su[r];
             }
-            mg[top] = gain;
+            heap[0].gain = gain;
             iter[top] = s_size;
             ++evals;
+            heap_sift_down(heap, len, 0);
         }
     }
     *cover_count = cover;
     if (n_evals) *n_evals = evals;
-    free(mg);
+    free(heap);
     free(iter);
-    free(is_seed);
+    free(covered);
     return 0;
 }

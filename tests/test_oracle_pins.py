@@ -483,7 +483,8 @@ def test_hash_sampler_matches_its_exact_expectation():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,m,p,R,K,seed", [(600, 2400, 0.05, 64, 12, 2), (1500, 4000, 0.2, 32, 9, 3),
-                                            (300, 1500, 0.01, 200, 20, 4), (80, 200, 1.0, 8, 30, 5)])
+                                            (300, 1500, 0.01, 200, 20, 4), (80, 200, 1.0, 8, 30, 5),
+                                            (50, 120, 0.0, 16, 50, 6), (400, 1600, 0.3, 24, 400, 7)])
 def test_memo_celf_equals_randcas_celf(n, m, p, R, K, seed):
     g = chung_lu(n, m, 2.4, seed)
     s = oracle.Sampler("hash", p=p, R=R, seed=seed)
