@@ -199,9 +199,9 @@ uint64_t im_graph_nnz(const im_graph *g);
  *   use_graphs  per-step mode: 1 = the K steps' launches are captured into
  *               one hipGraph (kernel nodes only) and launched once, 2 = direct
  *               launches (default)
- *   celf_mode   1 = all greedy steps in one persistent cooperative kernel
- *               (default where the device supports cooperative launch),
- *               2 = one launch per step and phase
+ *   celf_mode   1 = all greedy steps in one persistent kernel whose grid
+ *               is resident at once (default), 2 = one launch per step and
+ *               phase
  *   celf_round0 persistent kernel: candidates re-evaluated in the first round
  *               of a step (doubling in later rounds); 0 = automatic (16,
  *               fewer when that exceeds one tile per wavefront)              */

@@ -1,4 +1,4 @@
-// CELF on the memo (Algorithm 7) as one persistent, cooperative kernel.
+// CELF on the memo (Algorithm 7) as one persistent kernel.
 //
 // A grid of co-resident workgroups runs all K greedy steps.  Keys pack the
 // gain above the id bits (larger id = smaller key), so key order is gain
@@ -1071,11 +1071,10 @@ uint64_t pcelf_scratch_bytes() { return sizeof(PCelfScratch); }
 uint64_t pcelf_prof_offset() { return offsetof(PCelfScratch, prof); }
 uint64_t pcelf_err_offset() { return offsetof(PCelfScratch, err); }
 
-// Co-resident workgroups for a cooperative launch on `device` (0: the
-// device cannot run it).
+// Workgroups of the persistent grid on `device`: two per compute unit, or
+// one where occupancy allows only one (0: the kernel cannot run there).
 uint32_t pcelf_grid(int device) {
-  int coop = 0, cus = 0, per = 0;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  int cus = 0, per = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_celf_persistent, kPBlock, 0) != hipSuccess || per < 1)
@@ -1105,10 +1104,15 @@ void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* 
 
 hipError_t launch_celf_persistent(const void* jobs, uint32_t njobs, uint32_t grid, uint32_t group_blocks,
                                   const uint32_t* first, hipStream_t st) {
+  // An ordinary launch on the caller's stream: the grid is at most two
+  // workgroups per compute unit, within the kernel's occupancy, so every
+  // workgroup becomes resident once the kernels already running drain (the
+  // caller orders the context's other streams around it).  A cooperative
+  // launch would add nothing the kernel uses (its barriers are its own) and
+  // routes the kernel through a separate device queue.
   const PCelfJob* j = static_cast<const PCelfJob*>(jobs);
-  void* args[] = {&j, &njobs, &group_blocks, &first};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_celf_persistent), dim3(grid), dim3(kPBlock),
-                                    args, 0, st);
+  hipLaunchKernelGGL(k_celf_persistent, dim3(grid), dim3(kPBlock), 0, st, j, njobs, group_blocks, first);
+  return hipGetLastError();
 }
 
 }  // namespace infuse

@@ -132,12 +132,12 @@ struct im_ctx {
   std::vector<im_graph*> graphs;
   std::unordered_map<void*, size_t> sizes;
   std::recursive_mutex mu;
-  // persistent CELF: workgroups of a cooperative launch (0: unavailable),
-  // and the completion of the last one enqueued
   // serving loop hook: number of queued queries that want memo m of graph g
   // (evictions prefer memos nobody waits for)
   uint32_t (*memo_demand)(void* user, const im_graph* g, const infuse::Memo* m) = nullptr;
   void* memo_demand_user = nullptr;
+  // persistent CELF: workgroups of its grid (0: unavailable), and the
+  // completion of the last launch enqueued
   uint32_t coop_grid = 0;
   hipEvent_t coop_done = nullptr;
   bool coop_pending = false;
