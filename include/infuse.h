@@ -159,6 +159,22 @@ im_status im_estimate_sigma(im_graph *g, const uint32_t *S, uint32_t s_len, int6
 im_status im_estimate_sigma_direct(im_graph *g, const uint32_t *S, uint32_t s_len, int64_t *count,
                                    double *sigma, uint32_t *levels);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the count
+ * of im_estimate_sigma, with the same semantics and outputs, computed on the
+ * memo already resident for the graph's current parameters without any
+ * device allocation.  The scratch (count, seed list and, for more than 128
+ * distinct seeds, a bitmap of n * R / 8 bytes rounded up) lives in a 16 MiB
+ * device array that the library holds on each GPU until the process ends.
+ * Calls on one GPU share that array: calls that overlap on one GPU (other
+ * host threads or unordered streams) race on it.  Synchronises the context's
+ * stream.  Errors: IM_ERR_INVALID_ARG for an id >= n, when no memo is
+ * resident for the current parameters (this call builds none: call
+ * im_build_memo first) or when the query needs more than 16 MiB of scratch;
+ * IM_ERR_DEVICE when the array is unavailable. */
+im_status im_estimate_sigma_noalloc(im_graph *g, const uint32_t *S, uint32_t s_len, int64_t *count,
+                                    double *sigma);
+
 /* Greedy selection of K seeds without a memo, for graphs whose memo would
  * not fit and for directed graphs (whose spread is reachability, not
  * connectivity; the paper leaves them to future work): the marginal gain of

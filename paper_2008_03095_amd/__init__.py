@@ -212,6 +212,16 @@ class Graph:
                                           C.byref(cnt), C.byref(sig)))
         return int(cnt.value), float(sig.value)
 
+    def estimate_sigma_noalloc(self, S: Sequence[int]):
+        """sigma(S) on the resident memo without device allocation
+        (im_estimate_sigma_noalloc): (count, sigma)."""
+        arr = np.ascontiguousarray(np.asarray(S, dtype=np.uint32))
+        cnt = C.c_int64()
+        sig = C.c_double()
+        check(self._lib.im_estimate_sigma_noalloc(self.handle, _ptr(arr) if arr.size else None, int(arr.size),
+                                                  C.byref(cnt), C.byref(sig)))
+        return int(cnt.value), float(sig.value)
+
     def select_seeds_direct(self, K: int):
         """Greedy selection without a memo (im_select_seeds_direct), also for
         directed graphs: (seeds, marginal, cover)."""

@@ -68,6 +68,7 @@ SIGNATURES = {
     "im_select_seeds": (C.c_int, [vp, u32, vp, vp, P(i64)]),
     "im_estimate_sigma": (C.c_int, [vp, vp, u32, P(i64), P(dbl)]),
     "im_estimate_sigma_direct": (C.c_int, [vp, vp, u32, P(i64), P(dbl), P(u32)]),
+    "im_estimate_sigma_noalloc": (C.c_int, [vp, vp, u32, P(i64), P(dbl)]),
     "im_select_seeds_direct": (C.c_int, [vp, u32, vp, vp, P(i64)]),
     "im_copy_labels": (C.c_int, [vp, vp, u32, u32]),
     "im_copy_sizes": (C.c_int, [vp, vp, u32, u32]),

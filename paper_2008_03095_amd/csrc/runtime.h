@@ -86,6 +86,10 @@ im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std:
 im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
                         void** scratch, unsigned long long** dev_out);
 
+// noalloc.hip: device address of the per-device scratch array of the
+// allocation-free sigma call (looked up once per device), or nullptr.
+void* noalloc_scratch_setup(int device);
+
 // Records HIP events around a launch on `st` when profiling is on.
 class KTimer {
  public:

@@ -699,6 +699,9 @@ extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator*
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
     return fail(IM_ERR_DEVICE, "device %d not available (%d devices)", device, count);
   if (hipSetDevice(device) != hipSuccess) return fail(IM_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+  // scratch of im_estimate_sigma_noalloc on this device (a failed lookup is
+  // retried, and reported, by that call)
+  (void)noalloc_scratch_setup(device);
   if (alloc && (!alloc->alloc || !alloc->free))
     return fail(IM_ERR_INVALID_ARG, "allocator needs both alloc and free");
   im_ctx* c = new im_ctx();
