@@ -31,7 +31,10 @@ class Context:
     """
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, torch_memory: bool = True,
-                 stream=None):
+                 stream=None, allocator=None):
+        """allocator: optional (alloc(nbytes) -> device pointer or None,
+        free(ptr)) pair of callables used as the context's allocator
+        callbacks instead of PyTorch's caching allocator."""
         self._lib = load()
         self._cb = None
         self.device = device
@@ -49,7 +52,22 @@ class Context:
             handle = stream.cuda_stream
         else:
             self._stream = None
-        if have_torch and torch_memory:
+        if allocator is not None:
+            user_alloc, user_free = allocator
+
+            def _alloc(user, nbytes, s):
+                try:
+                    return user_alloc(int(nbytes))
+                except Exception:
+                    return None
+
+            def _free(user, ptr, s):
+                user_free(ptr)
+
+            self._cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+            self._alloc_struct = im_allocator(self._cb[0], self._cb[1], None)
+            alloc_p = C.byref(self._alloc_struct)
+        elif have_torch and torch_memory:
             dev = device
             st = handle
 
