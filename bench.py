@@ -30,6 +30,10 @@ METRIC = "edge-samples/s (m·R/s), K-seed time; serving p50/p99 vs plain per-que
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "celf_persistent_c4_traffic.txt")
 ROOF_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("celf_persistent.hip", "common.h")]
+# the labelling kernels of the memo construction (components phase)
+CC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cc_kernels_c4_traffic.txt")
+CC_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("cc.hip", "tile.h", "common.h")]
+CC_KERNELS = ("hook", "hook_hubs", "lists", "link", "link_hubs", "flatten", "count")
 # the memo-free search (directed workload): level kernel and its sources
 BFS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_level_d1_traffic.txt")
 BFS_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f)
@@ -75,6 +79,46 @@ def bfs_algorithmic_bytes(stats: dict, per_arc_p: bool) -> int:
     The 1 KiB of sample values of a tile is shared by every item and left
     out."""
     return 72 * stats["items"] + (12 if per_arc_p else 8) * stats["arcs"] + 96 * stats["live_pairs"]
+
+
+def celf_algorithmic_bytes(evals: int, K: int, mwords: int, listed_tiles: int, gathers: int) -> int:
+    """Bytes the memo-formula gain moves by its definition on the sparse memo,
+    from the CELF kernel's work counts: per evaluation (and per commit) the
+    candidate's tile-mask words (4 B each); per listed (candidate, tile)
+    pair its row of 256 labels (1 KiB); per column of a non-singleton
+    component the component's size (4 B) and its coverage word (4 B).  A
+    tile without its mask bit holds singletons only, counted in closed form
+    (no bytes)."""
+    return 4 * mwords * (evals + K) + 1024 * listed_tiles + 8 * gathers
+
+
+def cc_algorithmic_bytes(work: dict, n: int, mwords: int, light_slots: int, hub_slots: int, listed: int,
+                         link_tiles: int) -> dict:
+    """Bytes each labelling kernel moves by its definition, from the work
+    counts of one construction (Graph.memo_work) and the sizes of the lists:
+      hook (light rows) : its rows' slots (neighbour + hash, 8 B) once, 1 KiB
+                          per tile row written, the mask words of every vertex
+      hook_hubs         : the hubs' slots once (8 B), 1 KiB per tile row written
+      lists             : mask words read, one 4 B entry per listed and per
+                          union tile, the initial gains set (8 B per vertex)
+      link + link_hubs  : 1 KiB of hook parents per union tile, and per union
+                          attempt the two entries read and one written (12 B)
+      flatten           : 1 KiB read per listed tile, 1 KiB per row rewritten
+      count             : 1 KiB read per listed tile, 8 B per size decrement
+                          made in device memory (read and write)
+      gain0             : 1 KiB read per listed tile, 4 B per size gathered,
+                          8 B per vertex (the gain)"""
+    masks = 8 * mwords * n
+    link = 1024 * link_tiles + 12 * work["union_attempts"]
+    return {
+        "hook": 8 * light_slots + 1024 * work["row_tiles"] + masks,
+        "hook_hubs": 8 * hub_slots + 1024 * work["hub_tiles"],
+        "lists": masks + 4 * (listed + link_tiles) + 8 * n,
+        "link+link_hubs": link,
+        "flatten": 1024 * listed + 1024 * work["flatten_rewrites"],
+        "count": 1024 * listed + 8 * work["count_atomics"],
+        "gain0": 1024 * listed + 4 * work["gain_gathers"] + 8 * n,
+    }
 
 
 def cpu_baseline(workload, samples: int):
@@ -452,7 +496,7 @@ def main():
     ap.add_argument("--queries", type=int, default=300, help="serving workload: queries of the trace")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: concurrent query slots")
     ap.add_argument("--hbm-budget-gib", type=float, default=224.0, help="serving workload: memo budget")
-    ap.add_argument("--cpu-samples", type=int, default=2048)
+    ap.add_argument("--cpu-samples", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-selection", action="store_true", help="d1: the spread only")
@@ -460,6 +504,7 @@ def main():
                     help="edge probabilities: the workload's constant p, or per edge U[0,0.1] or "
                          "N(0.05,0.025) clipped (the paper's other weight settings)")
     ap.add_argument("--cc-chunk", type=int, default=0, help="columns per wavefront in labelling")
+    ap.add_argument("--list-blocks", type=int, default=0, help="workgroups of the list-walking kernels")
     ap.add_argument("--celf-width", type=int, default=0, help="CELF candidates per round (per-step mode)")
     ap.add_argument("--celf-mode", type=int, default=0, help="1 persistent kernel, 2 per-step kernels")
     ap.add_argument("--celf-round0", type=int, default=None,
@@ -501,6 +546,7 @@ def main():
 
     ctx = P.Context(device=0)
     ctx.set_tuning(cc_chunk=args.cc_chunk, celf_width=args.celf_width, celf_mode=args.celf_mode,
+                   list_blocks=args.list_blocks,
                    celf_round0=args.celf_round0)
     G = P.Graph.from_csr(ctx, g)
     G.set_params(p, R, seed)
@@ -530,19 +576,8 @@ def main():
 
     ms_per_step = dt * 1e3 / args.steps
     value = g.m * R * args.steps / dt
-    # roofline kernel: the persistent CELF kernel (one launch per step, the
-    # largest share of the step).  Per evaluation of a candidate (and per
-    # commit) the method reads the vertex's label in all R samples, gathers
-    # the size of each labelled component and reads one coverage bit per
-    # sample: 4R + 4R + R/8 bytes.
     roof_n, roof_ms = ctx.kernel_stats("celf")
     roof_avg = roof_ms / roof_n if roof_n else None
-    evals = G.celf_evals()
-    alg_bytes = (8 * R + R // 8) * (evals + K)
-    achieved = alg_bytes / (roof_avg * 1e-3) / 1e9 if roof_avg else None
-    traffic = read_traffic()
-    if traffic and (traffic.get("workload") != args.workload or args.weights != "const"):
-        traffic = None  # the counters were taken on another workload
     phases /= args.steps
     t_cc = phases[1]
     names = ["edge_hash", "x_sort", "hook", "hook_hubs", "lists", "link", "link_hubs", "flatten", "count",
@@ -553,6 +588,46 @@ def main():
         names += ["celf.barrier", "celf.eval", "celf.commit", "celf.restale", "celf.prep", "celf.post",
                   "celf.rebuild", "celf.bulk", "celf.sort", "celf.move", "celf.lookahead_commits"]
     stats = {k: ctx.kernel_stats(k) for k in names}
+    evals = G.celf_evals()
+    memo_stats = G.memo_stats()
+
+    # one more step, untimed, with every work count on (level 3: the
+    # labelling kernels' counts and the CELF kernel's listed tiles and
+    # gathers; they cost atomics, so the timed steps run without them)
+    ctx.set_profiling(3)
+    ctx.reset_kernel_stats()
+    step()
+    torch.cuda.synchronize()
+    work = G.memo_work()
+    celf_tiles = ctx.kernel_stats("celf.listed_tiles")[0]
+    celf_gathers = ctx.kernel_stats("celf.gathers")[0]
+    ctx.set_profiling(False)
+
+    mwords = (((R + 255) // 256) + 31) // 32
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    light_slots = int(deg[deg <= 64].sum())
+    hub_slots = int(deg[deg > 64].sum())
+    cc_alg = cc_algorithmic_bytes(work, g.n, mwords, light_slots, hub_slots, memo_stats["listed_tiles"],
+                                  memo_stats["link_tiles"])
+    cc_phase_alg = sum(v for k, v in cc_alg.items() if k != "gain0")
+    cc_traffic = read_traffic(CC_TRAFFIC_FILE, CC_SOURCES)
+    if cc_traffic and (cc_traffic.get("workload") != args.workload or args.weights != "const"):
+        cc_traffic = None
+
+    # roofline kernel: the persistent CELF kernel (one launch per step, the
+    # largest single kernel of the step), at the sparse memo's own bytes
+    alg_bytes = celf_algorithmic_bytes(evals, K, mwords, celf_tiles, celf_gathers)
+    dense_bytes = (8 * R + R // 8) * (evals + K)
+    achieved = alg_bytes / (roof_avg * 1e-3) / 1e9 if roof_avg else None
+    traffic = read_traffic()
+    if traffic and (traffic.get("workload") != args.workload or args.weights != "const"):
+        traffic = None  # the counters were taken on another workload
+    # components phase (hook ... count): the labelling kernels' algorithmic
+    # bytes over the phase's device time; beside it the survey's dense-memo
+    # floor (every label written once, both endpoint labels of every live
+    # edge-sample read) over the same time, as a model
+    cc_ach = cc_phase_alg / (t_cc * 1e-3) / 1e9 if t_cc > 0 else None
+    dense_floor = 4 * g.n * R + 8 * work["live_pairs"]
     rec = {
         "metric": METRIC,
         "value": value,
@@ -573,7 +648,7 @@ def main():
         "phase_ms": {"sampler_prep": phases[0], "components": phases[1], "gains0": phases[2],
                      "celf": phases[3]},
         "edge_samples_per_s_components": g.m * R / (t_cc * 1e-3) if t_cc > 0 else None,
-        "celf_evals": G.celf_evals(),
+        "celf_evals": evals,
         "cover_count": cover,
         "kernel_avg_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in stats.items()},
         "kernel_launches_per_step": {k: v[0] / args.steps for k, v in stats.items()},
@@ -587,11 +662,31 @@ def main():
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": traffic["bytes_per_launch"] if traffic else None,
             "algorithmic_bytes": alg_bytes,
+            "work": {"evaluations": evals, "commits": K, "listed_tiles": celf_tiles, "gathers": celf_gathers},
             "avg_launch_ms": roof_avg,
+            "dense_model_bytes": dense_bytes,
+        },
+        "roofline_components": {
+            "bound": "hbm",
+            "kernels": list(CC_KERNELS),
+            "achieved": cc_ach,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": cc_ach / HBM_PEAK_GBS if cc_ach else None,
+            "algorithmic_bytes": cc_phase_alg,
+            "phase_ms": t_cc,
+            "traffic": cc_traffic["bytes_components"] if cc_traffic else None,
+            "traffic_frac": (cc_traffic["bytes_components"] / (t_cc * 1e-3) / 1e9 / HBM_PEAK_GBS
+                             if cc_traffic and t_cc > 0 else None),
+            "dense_floor_bytes": dense_floor,
+            "dense_floor_frac": dense_floor / (t_cc * 1e-3) / 1e9 / HBM_PEAK_GBS if t_cc > 0 else None,
+            "per_kernel_algorithmic_bytes": cc_alg,
+            "per_kernel_traffic": cc_traffic["per_kernel_bytes"] if cc_traffic else None,
+            "work": work,
         },
         "cpu_baseline": None,
     }
-    rec["memo_stats"] = G.memo_stats()
+    rec["memo_stats"] = memo_stats
     # sigma of the selected seeds without a memo (search over all samples),
     # outside the timed steps
     t_direct = []

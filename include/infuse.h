@@ -220,24 +220,29 @@ uint64_t im_graph_nnz(const im_graph *g);
  *               phase
  *   celf_round0 persistent kernel: candidates re-evaluated in the first round
  *               of a step (doubling in later rounds); 0 = automatic (16,
- *               fewer when that exceeds one tile per wavefront)              */
+ *               fewer when that exceeds one tile per wavefront)
+ *   list_blocks workgroups of the kernels that walk the work lists (unions
+ *               of light vertices, flatten, initial gains), 256 to 65536
+ *               (default 8192); in a batched construction each graph takes
+ *               at most this many                                          */
 typedef struct {
     uint32_t cc_chunk;
     uint32_t celf_width;
     uint32_t use_graphs;
     uint32_t celf_mode;
     uint32_t celf_round0;
-    uint32_t reserved[3];
+    uint32_t list_blocks;
+    uint32_t reserved[2];
 } im_tuning;
 im_status im_set_tuning(im_ctx *ctx, const im_tuning *t);
 im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);
 
 /* Autotuner (not part of the paper's method: it picks launch shapes).  Times
  * `reps` cold K-seed selections of g (memo dropped before each) for every
- * candidate cc_chunk in {256, 512, 1024} and, with the persistent CELF
- * kernel, celf_round0 in {8, 16, 32}; checks that all of them select the same
- * seeds (IM_ERR_DEVICE otherwise), applies the fastest to g's context and
- * writes it to *best.  g's memo is rebuilt each time (the resident memo is
+ * candidate cc_chunk in {256, 512, 1024}, list_blocks in {2048, 8192,
+ * 32768} and, with the persistent CELF kernel, celf_round0 in {8, 16, 32};
+ * checks that all of them select the same seeds (IM_ERR_DEVICE otherwise),
+ * applies the fastest to g's context and writes it to *best.  g's memo is rebuilt each time (the resident memo is
  * dropped).  Errors: NULL arguments, parameters not set, K outside 1..n. */
 im_status im_autotune(im_graph *g, uint32_t K, uint32_t reps, im_tuning *best);
 
@@ -246,7 +251,8 @@ im_status im_autotune(im_graph *g, uint32_t K, uint32_t reps, im_tuning *best);
  * once per memo construction or query (edge_hash, x_sort, hook, link,
  * flatten, count, gain0, sigma); 2: also every CELF round launch
  * (celf_topw, celf_eval, celf_bulk), whose events perturb the timing of
- * such short kernels.  im_kernel_stats returns the number of launches and
+ * such short kernels, and the persistent CELF kernel's phase clock; 3: also
+ * the work counts of memo constructions (im_memo_work).  im_kernel_stats returns the number of launches and
  * the summed milliseconds of the named kernel since the last reset. */
 im_status im_set_profiling(im_ctx *ctx, int level);
 im_status im_reset_kernel_stats(im_ctx *ctx);
@@ -269,6 +275,19 @@ uint64_t im_last_celf_evals(const im_graph *g);
  * else they read zero.  Errors: NULL arguments. */
 im_status im_last_search_stats(const im_graph *g, uint64_t *out4);
 
+/* Work counts of the construction of the memo resident for the current
+ * parameters, kept when it was built while profiling was at level 3 (they
+ * cost atomics in every labelling kernel).  Writes out[0 .. n_out-1] (zero
+ * past the last count): out[0] live (edge, simulation) pairs, out[1] union
+ * attempts of the link kernels, out[2] rows rewritten by the flatten pass,
+ * out[3] component-size decrements made in device memory by the count pass,
+ * out[4] and out[5] (vertex, 256-column tile) rows written by the hook of
+ * light vertices and of vertices with more than 64 neighbours, out[6]
+ * component-size gathers of the initial gains, out[7] union wavefronts of
+ * the latter vertices.  Errors: IM_ERR_INVALID_ARG when no memo is resident or it was
+ * built without counting. */
+im_status im_memo_work(im_graph *g, uint64_t *out, uint32_t n_out);
+
 /* Work counts of the resident memo for the current parameters (built if
  * needed; waits for it): out[0] (vertex, 256-column tile) pairs that may
  * hold a non-singleton component, out[1] pairs with a column of two or more
@@ -278,12 +297,19 @@ im_status im_memo_stats(im_graph *g, uint64_t *out4);
 
 /* ---- batching: many graphs in one launch per phase --------------------- */
 
-/* Builds the memos of n_graphs graphs (each with its own parameters set by
- * im_set_params) with one launch per phase over all graphs, then selects
- * K[i] seeds for every graph with CELF rounds that serve all graphs per
- * launch.  seeds[i] / marginal[i] point to caller arrays of K[i] entries;
- * cover[i] receives the cover count.  All graphs must share the context.
- * Results are identical to calling im_select_seeds per graph. */
+/* K[i]-seed selections on n_graphs graphs (each with its own parameters set
+ * by im_set_params; the paper's CPU code gives each batch of simulations a
+ * thread of its own, Section III).  The memos of the graphs that have none
+ * resident are built together: one launch per labelling phase (set-up,
+ * hooks, work lists, unions, flatten, count, initial gains) over all of
+ * them, each launch's workgroups divided among the graphs by prefix sums of
+ * per-graph shapes.  Then all selections run in one launch of the
+ * persistent CELF kernel, each graph on a group of workgroups sized by its
+ * memo.  seeds[i] / marginal[i] point to caller arrays of K[i] entries;
+ * cover[i] receives the cover count.  All graphs must share the context and
+ * appear once.  Results are identical to calling im_select_seeds per
+ * graph.  Errors: IM_ERR_INVALID_ARG for a graph of another context, a
+ * repeated or directed graph, missing parameters or K[i] > n. */
 im_status im_batch_select(im_ctx *ctx, uint32_t n_graphs, im_graph *const *graphs,
                           const uint32_t *K, uint32_t *const *seeds, int64_t *const *marginal,
                           int64_t *cover);

@@ -109,9 +109,10 @@ class Context:
     CELF_PERSISTENT, CELF_PER_STEP = 1, 2
 
     def set_tuning(self, cc_chunk: int = 0, celf_width: int = 0, use_graphs: Optional[bool] = None,
-                   celf_mode: int = 0, celf_round0: Optional[int] = None):
+                   celf_mode: int = 0, celf_round0: Optional[int] = None, list_blocks: int = 0):
         t = im_tuning()
         t.cc_chunk = cc_chunk
+        t.list_blocks = list_blocks
         t.celf_width = celf_width
         t.use_graphs = 0 if use_graphs is None else (1 if use_graphs else 2)
         t.celf_mode = celf_mode
@@ -123,7 +124,7 @@ class Context:
         t = im_tuning()
         check(self._lib.im_get_tuning(self.handle, C.byref(t)))
         return dict(cc_chunk=t.cc_chunk, celf_width=t.celf_width, use_graphs=bool(t.use_graphs),
-                    celf_mode=t.celf_mode, celf_round0=t.celf_round0)
+                    celf_mode=t.celf_mode, celf_round0=t.celf_round0, list_blocks=t.list_blocks)
 
     def autotune(self, graph: "Graph", K: int, reps: int = 2, cache: Optional[str] = None) -> dict:
         """Launch shapes for `graph` (im_autotune), applied to this context.
@@ -143,7 +144,8 @@ class Context:
                 with open(cache) as f:
                     known = json.load(f)
                 if key in known:
-                    self.set_tuning(cc_chunk=known[key]["cc_chunk"], celf_round0=known[key]["celf_round0"])
+                    self.set_tuning(cc_chunk=known[key]["cc_chunk"], celf_round0=known[key]["celf_round0"],
+                                    list_blocks=known[key].get("list_blocks", 0))
                     return self.tuning()
         t = im_tuning()
         check(self._lib.im_autotune(graph.handle, int(K), int(reps), C.byref(t)))
@@ -159,7 +161,8 @@ class Context:
         return out
 
     def set_profiling(self, level):
-        """0/False: off; 1/True: per-build kernels; 2: also every CELF launch."""
+        """0/False: off; 1/True: per-build kernels; 2: also every CELF launch and
+        the persistent CELF phase clock; 3: also memo-construction work counts."""
         check(self._lib.im_set_profiling(self.handle, int(level)))
 
     def reset_kernel_stats(self):
@@ -289,6 +292,16 @@ class Graph:
         a = (C.c_uint64 * 4)()
         check(self._lib.im_last_search_stats(self.handle, a))
         return dict(levels=int(a[0]), items=int(a[1]), arcs=int(a[2]), live_pairs=int(a[3]))
+
+    WORK_KEYS = ("live_pairs", "union_attempts", "flatten_rewrites", "count_atomics", "row_tiles", "hub_tiles",
+                 "gain_gathers", "hub_link_waves")
+
+    def memo_work(self) -> dict:
+        """Work counts of the resident memo's construction (built while the
+        context's profiling level was 3)."""
+        a = (C.c_uint64 * len(self.WORK_KEYS))()
+        check(self._lib.im_memo_work(self.handle, a, len(self.WORK_KEYS)))
+        return {k: int(v) for k, v in zip(self.WORK_KEYS, a)}
 
     def memo_stats(self) -> dict:
         a = (C.c_uint64 * 4)()

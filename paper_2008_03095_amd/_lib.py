@@ -32,7 +32,8 @@ class im_allocator(C.Structure):
 
 class im_tuning(C.Structure):
     _fields_ = [("cc_chunk", C.c_uint32), ("celf_width", C.c_uint32), ("use_graphs", C.c_uint32),
-                ("celf_mode", C.c_uint32), ("celf_round0", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("celf_mode", C.c_uint32), ("celf_round0", C.c_uint32), ("list_blocks", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
 class im_server_config(C.Structure):
@@ -85,6 +86,7 @@ SIGNATURES = {
     "im_last_celf_evals": (u64, [vp]),
     "im_last_search_stats": (C.c_int, [vp, P(u64)]),
     "im_memo_stats": (C.c_int, [vp, P(u64)]),
+    "im_memo_work": (C.c_int, [vp, P(u64), u32]),
     "im_batch_select": (C.c_int, [vp, u32, P(vp), P(u32), P(P(u32)), P(P(i64)), P(i64)]),
     "im_server_create": (C.c_int, [vp, P(im_server_config), P(vp)]),
     "im_server_submit": (C.c_int, [vp, vp, P(im_query), P(u64)]),

@@ -1,7 +1,8 @@
 // Autotuner (im_autotune): picks launch shapes for a graph by timing cold
 // selections.  The knobs change only how the work is spread over the device
-// (simulations per hub wavefront, candidates of a CELF step's first round),
-// never the result, which the tuner checks.
+// (simulations per hub wavefront, workgroups of the list-walking kernels,
+// candidates of a CELF step's first round), never the result, which the
+// tuner checks.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -20,16 +21,19 @@ extern "C" im_status im_autotune(im_graph* g, uint32_t K, uint32_t reps, im_tuni
   im_ctx* c = g->ctx;
   const im_tuning saved = c->tune;
   const uint32_t chunks[] = {256, 512, 1024};
+  const uint32_t lists[] = {2048, 8192, 32768};
   const uint32_t round0s[] = {8, 16, 32};
   std::vector<uint32_t> seeds(K), ref;
   std::vector<int64_t> marg(K);
   double best_ms = 1e300;
   im_tuning pick = saved;
   for (uint32_t ch : chunks)
+    for (uint32_t lb : lists)
     for (uint32_t r0 : round0s) {
       if (c->tune.celf_mode != 1 && r0 != round0s[0]) continue;  // round0 only shapes the persistent kernel
       im_tuning t = saved;
       t.cc_chunk = ch;
+      t.list_blocks = lb;
       t.celf_round0 = r0;
       c->tune = t;
       double ms = 1e300;

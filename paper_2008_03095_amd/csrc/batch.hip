@@ -1,8 +1,11 @@
-// Many graphs per call (im_batch_select).  The memos of graphs that are not
-// resident are built on kBatchStreams streams at once (the kernels of small
-// graphs overlap on the device), then every selection runs in one launch of
-// the persistent CELF kernel, which gives each graph its own group of
-// workgroups, sized by the graph's memo; one synchronisation at the end.
+// Many graphs per call (im_batch_select).  The memos of the graphs that are
+// not resident are built together: one launch per labelling phase (set-up,
+// hook of light rows, hook of hubs, work lists, unions of light rows and of
+// hubs, flatten, count, initial gains) over all of them, each launch's
+// workgroups split among the graphs by prefix sums of per-graph shapes.
+// Then every selection runs in one launch of the persistent CELF kernel,
+// which gives each graph its own group of workgroups, sized by the graph's
+// memo; one synchronisation at the end.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -13,19 +16,109 @@
 
 using namespace infuse;
 
-static constexpr uint32_t kBatchStreams = 4;
+static const char* const kPhaseNames[kBatchPhases] = {"batch.prep",  "batch.hook",    "batch.hook_hubs",
+                                                      "batch.lists", "batch.link",    "batch.link_hubs",
+                                                      "batch.flatten", "batch.count", "batch.gain0"};
 
-static bool batch_streams(im_ctx* c) {
-  if (!c->bstreams.empty()) return true;
-  for (uint32_t i = 0; i < kBatchStreams; ++i) {
-    hipStream_t s = nullptr;
-    hipEvent_t e = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
-    c->bstreams.push_back(s);
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
-    c->bevents.push_back(e);
+// Allocates and builds the memos of graphs[todo[k]] (returned pinned in
+// memos[]) with one launch per phase on the context stream.  *djobs receives
+// the device copy of the job descriptions, to be freed once the stream has
+// passed the launches.  On failure no memo of this call stays registered.
+static im_status batch_build(im_ctx* c, im_graph* const* graphs, const std::vector<uint32_t>& todo,
+                             std::vector<Memo*>& memos, void** djobs) {
+  hipStream_t st = c->stream;
+  const uint32_t nj = (uint32_t)todo.size();
+  im_status s = IM_OK;
+  uint32_t made = 0;
+  for (; made < nj && s == IM_OK; ++made) {
+    im_graph* g = graphs[todo[made]];
+    s = memo_alloc(g, g->p, g->R, g->seed, &memos[todo[made]]);
+    if (s != IM_OK) break;
   }
-  return true;
+  auto undo = [&]() {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    for (uint32_t k = 0; k < made; ++k) {
+      Memo*& m = memos[todo[k]];
+      if (m) memo_destroy(graphs[todo[k]], m);
+      m = nullptr;
+    }
+  };
+  if (s != IM_OK) {
+    undo();
+    return s;
+  }
+  std::vector<BuildJob> jobs(nj);
+  std::vector<uint32_t> first((size_t)kBatchPhases * (nj + 1), 0);
+  uint64_t total[kBatchPhases] = {};
+  const uint32_t chunk_tiles = hub_chunk_tiles(c);
+  for (uint32_t k = 0; k < nj; ++k) {
+    im_graph* g = graphs[todo[k]];
+    Memo* m = memos[todo[k]];
+    const GraphView gv = g->view();
+    BuildJob& J = jobs[k];
+    J.g = gv;
+    J.m = m->view(g);
+    J.edges = m->edges;
+    J.xs = m->xs;
+    J.inv = m->inv;
+    J.pos = m->pos;
+    J.seed = m->seed;
+    uint32_t blocks[kBatchPhases] = {};
+    build_job_shape(gv, J.m, chunk_tiles, c->tune.list_blocks, &J, blocks);
+    // X of a large R is sorted by the single-graph kernels beforehand
+    J.sort_blocks = m->R <= x_sort_single_max() ? 1u : 0u;
+    if (!J.sort_blocks) launch_x_sort(m->seed, m->R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
+    J.hash_blocks = std::max(1u, std::min(65536u, (g->n + 3) / 4));
+    J.fill_words = (uint32_t)((reinterpret_cast<char*>(m->lmask) - reinterpret_cast<char*>(m->tmask)) / 4 +
+                              (uint64_t)g->n * m->mwords);
+    const uint32_t fill_blocks = std::min(4096u, (J.fill_words + 2047) / 2048);
+    blocks[kBpPrep] = J.sort_blocks + J.hash_blocks + fill_blocks;
+    for (uint32_t ph = 0; ph < kBatchPhases; ++ph) {
+      total[ph] += blocks[ph];
+      if (total[ph] > 0x7FFFFFFFull) {
+        undo();
+        return fail(IM_ERR_INVALID_ARG, "batched construction: more than 2^31 workgroups in one phase");
+      }
+      first[(size_t)ph * (nj + 1) + k + 1] = (uint32_t)total[ph];
+    }
+  }
+  const size_t jb = (sizeof(BuildJob) * nj + 255) / 256 * 256;
+  s = ctx_alloc(c, jb + first.size() * 4, djobs);
+  if (s != IM_OK) {
+    undo();
+    return s;
+  }
+  char* d = static_cast<char*>(*djobs);
+  if (hipMemcpyAsync(d, jobs.data(), sizeof(BuildJob) * nj, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d + jb, first.data(), first.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+    undo();
+    return fail(IM_ERR_DEVICE, "batched construction: job upload failed");
+  }
+  BuildBatch b;
+  b.jobs = reinterpret_cast<const BuildJob*>(d);
+  b.first = reinterpret_cast<const uint32_t*>(d + jb);
+  b.njobs = nj;
+  {
+    KTimer t(c, kPhaseNames[kBpPrep], st);
+    launch_prep_batch(b, (uint32_t)total[kBpPrep], st);
+  }
+  for (uint32_t ph = kBpHookRows; ph < kBatchPhases; ++ph) {
+    KTimer t(c, kPhaseNames[ph], st);
+    launch_build_batch(b, ph, (uint32_t)total[ph], st);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    undo();
+    return fail(IM_ERR_DEVICE, "batched construction failed to launch: %s", hipGetErrorString(e));
+  }
+  for (uint32_t k = 0; k < nj; ++k) {
+    Memo* m = memos[todo[k]];
+    if (hipEventCreateWithFlags(&m->ready_ev, hipEventDisableTiming) == hipSuccess)
+      (void)hipEventRecord(m->ready_ev, st);
+    graphs[todo[k]]->timed_build = false;
+  }
+  return IM_OK;
 }
 
 extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* graphs, const uint32_t* K,
@@ -36,44 +129,30 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     if (K[i] > graphs[i]->n) return fail(IM_ERR_INVALID_ARG, "K[%u] exceeds n", i);
     if (!graphs[i]->params_set) return fail(IM_ERR_INVALID_ARG, "graph %u has no parameters", i);
     if (graphs[i]->directed) return fail(IM_ERR_INVALID_ARG, "graph %u is directed: no memo selection", i);
+    for (uint32_t k = 0; k < i; ++k)
+      if (graphs[k] == graphs[i]) return fail(IM_ERR_INVALID_ARG, "graph %u appears twice", i);
   }
   std::vector<Memo*> memos(ng, nullptr);
   std::vector<CelfBuffers> cbs(ng);
   im_status st = IM_OK;
-  // memos: resident ones are pinned, missing ones built round-robin on the
-  // batch streams; the context stream then waits for every batch stream
-  const bool multi = ng > 1 && batch_streams(c);
-  std::vector<bool> used(kBatchStreams, false);
-  for (uint32_t i = 0; i < ng && st == IM_OK; ++i) {
+  // memos: resident ones are pinned (the context stream waits for their
+  // construction), missing ones built together
+  std::vector<uint32_t> todo;
+  for (uint32_t i = 0; i < ng; ++i) {
     im_graph* g = graphs[i];
-    {
-      std::lock_guard<std::recursive_mutex> lk(c->mu);
-      Memo* m = memo_find(g, g->p, g->R, g->seed);
-      if (m) {
-        m->pins++;
-        m->last_use = ++c->use_clock;
-        memos[i] = m;
-      }
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    Memo* m = memo_find(g, g->p, g->R, g->seed);
+    if (m) {
+      m->pins++;
+      m->last_use = ++c->use_clock;
+      memos[i] = m;
+      if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+    } else {
+      todo.push_back(i);
     }
-    if (memos[i]) {
-      if (memos[i]->ready_ev) (void)hipStreamWaitEvent(c->stream, memos[i]->ready_ev, 0);
-      continue;
-    }
-    const uint32_t b = i % kBatchStreams;
-    hipStream_t bs = multi ? c->bstreams[b] : c->stream;
-    if (multi && !used[b]) {  // batch streams start after the context stream's earlier work
-      (void)hipEventRecord(c->bevents[b], c->stream);
-      (void)hipStreamWaitEvent(bs, c->bevents[b], 0);
-      used[b] = true;
-    }
-    st = memo_build(g, g->p, g->R, g->seed, bs, &memos[i]);  // returned pinned
   }
-  if (multi)
-    for (uint32_t b = 0; b < kBatchStreams; ++b)
-      if (used[b]) {
-        (void)hipEventRecord(c->bevents[b], c->bstreams[b]);
-        (void)hipStreamWaitEvent(c->stream, c->bevents[b], 0);
-      }
+  void* dbuild = nullptr;
+  if (!todo.empty()) st = batch_build(c, graphs, todo, memos, &dbuild);
   for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
     if (K[i]) st = celf_alloc(graphs[i], memos[i], K[i], c->tune.celf_width, &cbs[i]);
   void* djobs = nullptr;
@@ -139,6 +218,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
   }
   if (st != IM_OK) (void)hipStreamSynchronize(c->stream);
   if (djobs) ctx_free(c, djobs);
+  if (dbuild) ctx_free(c, dbuild);
   for (uint32_t i = 0; i < ng; ++i) {
     if (cbs[i].base) ctx_free(c, cbs[i].base);
     if (memos[i]) memo_release(graphs[i], memos[i]);

@@ -40,6 +40,16 @@
 
 namespace infuse {
 
+// Adds the wavefront's sum of x to work count i (one atomic per wavefront;
+// only while the construction is counted).
+__device__ inline void work_add(const MemoView& m, uint32_t i, uint32_t x) {
+  if (!m.work) return;
+  uint64_t s = x;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&m.work[i], (unsigned long long)s);
+}
+
 // Hook of one tile: for each of the lane's columns, the smallest live
 // neighbour u < v (or -1), stored as one 16-byte write when the tile has a
 // candidate edge at all; otherwise v is a singleton in every column of the
@@ -74,6 +84,10 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
   const int4v ov = {out.x, out.y, out.z, out.w};
   if (any) __builtin_nontemporal_store(ov, reinterpret_cast<int4v*>(row + tc.q0));
   need = __ballot(cnt[0] > 1 || cnt[1] > 1 || cnt[2] > 1 || cnt[3] > 1) != 0;
+  if (m.work) {
+    work_add(m, kWorkLivePairs, cnt[0] + cnt[1] + cnt[2] + cnt[3]);
+    work_add(m, inreg ? kWorkRowTiles : kWorkHubTiles, (any && (threadIdx.x & 63) == 0) ? 1u : 0u);
+  }
 }
 
 // k_hook_rows: one wavefront per vertex with at most kWave neighbours (the
@@ -85,8 +99,8 @@ __device__ inline void hook_tile(const GraphView& g, const MemoView& m, uint32_t
 // current one is processed.  The wave owns the vertex's mask words and
 // stores them directly.
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
-  const uint32_t v = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
+__device__ inline void hook_rows_body(const GraphView& g, const MemoView& m, uint32_t bid) {
+  const uint32_t v = uni(bid * 4 + (threadIdx.x >> 6));
   if (v >= g.n) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
@@ -158,8 +172,9 @@ __global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
 // (vertex, chunk of tiles); the neighbour list is streamed in 64-slot
 // pieces.  Several wavefronts share a vertex's mask words (atomic or).
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_hook_hubs(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
-  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__device__ inline void hook_hubs_body(const GraphView& g, const MemoView& m, uint32_t chunk, uint32_t wpv,
+                                      uint32_t bid) {
+  const uint64_t wid = (uint64_t)bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint32_t hi = uni((uint32_t)(wid / wpv));
   if (hi >= g.nhubs) return;
   const uint32_t c = uni((uint32_t)(wid % wpv));
@@ -188,9 +203,9 @@ __global__ void __launch_bounds__(256) k_hook_hubs(GraphView g, MemoView m, uint
 // One workgroup per sub-list; positions come from workgroup prefix sums, so
 // no global counter is contended.  It also sets mg_v = R, the gain of an all
 // singleton row, to which k_gain0 adds the listed tiles.
-__global__ void __launch_bounds__(256) k_lists(MemoView m) {
+__device__ inline void lists_body(const MemoView& m, uint32_t bid) {
   __shared__ uint32_t wsum[2][4];
-  const uint32_t j = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t j = bid, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t vps = (m.n + kSubLists - 1) / kSubLists;
   const uint32_t v0 = min(m.n, j * vps), v1 = min(m.n, v0 + vps);
   uint32_t* tout = m.tlist + (uint64_t)j * m.list_cap;
@@ -316,8 +331,8 @@ struct ListIter {
     return list[(uint64_t)lo * cap + (idx - pre[lo])];
   }
 };
-__device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, int which,
-                                     uint32_t* pre) {
+__device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, int which, uint32_t* pre,
+                                     uint32_t bid, uint32_t nblk) {
   static_assert(kSubLists == 256, "one prefix element per thread of a 256-thread workgroup");
   const uint32_t tid = threadIdx.x;
   uint32_t x = m.counts[2 * tid + which];
@@ -336,8 +351,8 @@ __device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, in
   it.pre = pre;
   it.cap = m.list_cap;
   it.total = uni(pre[kSubLists]);
-  it.first = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  it.stride = gridDim.x * (blockDim.x >> 6);
+  it.first = uni(bid * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  it.stride = nblk * (blockDim.x >> 6);
   return it;
 }
 
@@ -360,16 +375,15 @@ __device__ inline int4 list_row(const MemoView& m, uint32_t e, uint32_t lane) {
 }
 
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
+__device__ inline void link_body(const GraphView& g, const MemoView& m, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
-  const ListIter it = list_iter(m, m.llist, 1, pre);
+  const ListIter it = list_iter(m, m.llist, 1, pre, bid, nblk);
   for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
     const uint32_t e = uni(it.at(idx));
     const uint32_t v = e / m.ntiles, t = e % m.ntiles;
     const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]), split = uni(g.split[v]);
     if (end - beg > (uint32_t)kWave) continue;  // hub: k_link_hubs
-    const bool inreg = true;
     uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
     if (beg + lane < end) {
       const uint2 ed = m.edges[beg + lane];
@@ -387,18 +401,21 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
     // root of v's tree per column, looked up when the first further live
     // smaller neighbour needs joining
     uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
-    for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, inreg, rcol, rh, rtm1, tc,
+    uint32_t tries = 0;
+    for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, true, rcol, rh, rtm1, tc,
                                    [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
 #pragma unroll
                                      for (int i = 0; i < 4; ++i) {
                                        const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
                                        if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
+                                         ++tries;
                                          if (rv[i] == kInvalid)
                                            rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
                                          rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
                                        }
                                      }
                                    });
+    work_add(m, kWorkUnions, tries);
   }
 }
 
@@ -407,8 +424,8 @@ __global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
 // an lmask bit are skipped.  The piece table gives the hub and the piece's
 // first slot.
 template <bool PER_EDGE>
-__global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
-  const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__device__ inline void link_hubs_body(const GraphView& g, const MemoView& m, uint32_t bid) {
+  const uint64_t wid = (uint64_t)bid * 4 + (threadIdx.x >> 6);
   const uint32_t pg = uni((uint32_t)(wid / m.ntiles)), t = uni((uint32_t)(wid % m.ntiles));
   if (pg >= g.hub_pieces) return;
   const uint2 pc = g.hub_piece[pg];
@@ -422,6 +439,7 @@ __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
   const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
   const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
   uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
+  uint32_t tries = 0;
   for (uint32_t beg = pbeg; beg < pend; beg += kWave) {
   const uint32_t end = min(beg + (uint32_t)kWave, pend);
   uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
@@ -437,6 +455,7 @@ __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
                                    for (int i = 0; i < 4; ++i) {
                                      const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
                                      if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
+                                       ++tries;
                                        if (rv[i] == kInvalid)
                                          rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
                                        rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
@@ -444,16 +463,20 @@ __global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
                                    }
                                  });
   }
+  if (m.work) {
+    work_add(m, kWorkUnions, tries);
+    work_add(m, kWorkHubLinkWaves, lane == 0 ? 1u : 0u);
+  }
 }
 
 // k_flatten: every non-root entry of a listed tile is replaced by its root
 // (plain loads and stores only; a stale value read during the walk is an
 // older ancestor, so every walk still ends at the root).  The four columns
 // of a lane walk together, one load each per step.
-__global__ void __launch_bounds__(256) k_flatten(MemoView m) {
+__device__ inline void flatten_body(const MemoView& m, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
-  const ListIter it = list_iter(m, m.tlist, 0, pre);
+  const ListIter it = list_iter(m, m.tlist, 0, pre, bid, nblk);
   for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
     uint32_t cnt;
     const uint32_t ent = list_chunk(it, k0, lane, cnt);
@@ -495,6 +518,7 @@ __global__ void __launch_bounds__(256) k_flatten(MemoView m) {
           changed = true;
         }
       if (changed) *reinterpret_cast<int4*>(row + q0) = out;
+      if (m.work) work_add(m, kWorkRewrites, (__ballot(changed) != 0 && lane == 0) ? 1u : 0u);
     }
   }
 }
@@ -517,10 +541,10 @@ static uint32_t count_block_verts(const MemoView& m) {
   return (uint32_t)std::min<uint64_t>(kCountMaxBlockVerts, std::max<uint64_t>(256, vb));
 }
 
-__global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts) {
+__device__ inline void count_body(const MemoView& m, uint32_t block_verts, uint32_t bid) {
   __shared__ uint32_t hot[kHotRoots][kTile];
-  const uint32_t t = blockIdx.x % m.ntiles;
-  const uint32_t v0 = (blockIdx.x / m.ntiles) * block_verts;
+  const uint32_t t = bid % m.ntiles;
+  const uint32_t v0 = (bid / m.ntiles) * block_verts;
   const uint32_t v1 = min(v0 + block_verts, m.n);
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < kHotRoots * kTile; i += blockDim.x) (&hot[0][0])[i] = 0;
@@ -530,6 +554,7 @@ __global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts)
   // 64 vertices' mask words per load; the wave then visits the flagged ones,
   // four rows requested together
   constexpr int kRows = 4;
+  uint32_t nat = 0;  // root decrements made in device memory (work count)
   for (uint32_t vb = v0 + wv * 64; vb < v1; vb += 4 * 64) {
     const uint32_t vl = vb + lane;
     const bool flagged = vl < v1 && ((m.tmask[(uint64_t)vl * m.mwords + word] >> bit) & 1u);
@@ -557,16 +582,19 @@ __global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts)
           if (q >= m.R || c < 0) continue;
           if ((uint32_t)c < kHotRoots) atomicAdd(&hot[c][lane * kPerLane + i], 1u);
           else atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -1);
+          nat += (uint32_t)c >= kHotRoots ? 1u : 0u;
         }
       }
     }
   }
+  work_add(m, kWorkCountAtomics, nat);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < kHotRoots * kTile; i += blockDim.x) {
     const uint32_t cnt = (&hot[0][0])[i];
     if (!cnt) continue;
     const uint32_t c = i / kTile, q = t * kTile + i % kTile;
     atomicAdd(&m.M[(uint64_t)c * m.Rs + q], -(int32_t)cnt);
+    if (m.work) atomicAdd(&m.work[kWorkCountAtomics], 1ull);
   }
 }
 
@@ -579,10 +607,10 @@ __device__ inline uint64_t wave_sum_u64(uint64_t x) {
 // mg_v = sum_q |C_q(v)| = R + sum over the listed tiles of v of
 // sum_q (|C_q(v)| - 1): unlisted tiles hold only singleton columns.
 
-__global__ void __launch_bounds__(256) k_gain0(MemoView m) {
+__device__ inline void gain0_body(const MemoView& m, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
-  const ListIter it = list_iter(m, m.tlist, 0, pre);
+  const ListIter it = list_iter(m, m.tlist, 0, pre, bid, nblk);
   for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
     uint32_t cnt;
     const uint32_t ent = list_chunk(it, k0, lane, cnt);
@@ -608,10 +636,94 @@ __global__ void __launch_bounds__(256) k_gain0(MemoView m) {
         const int32_t sz = vals[i] < 0 ? -vals[i] : -raw[i];
         sum += (q0 + i < m.R) ? (uint64_t)(sz - 1) : 0;
       }
+      if (m.work)
+        work_add(m, kWorkGathers, (uint32_t)(vals[0] >= 0) + (vals[1] >= 0) + (vals[2] >= 0) + (vals[3] >= 0));
       sum = wave_sum_u64(sum);
       if (lane == 0 && sum) atomicAdd((unsigned long long*)&m.g0[v], (unsigned long long)sum);
     }
   }
+}
+
+// ---- kernels: one graph per launch, or many graphs per launch (batching) ----
+
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_hook_rows(GraphView g, MemoView m) {
+  hook_rows_body<PER_EDGE>(g, m, blockIdx.x);
+}
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_hook_hubs(GraphView g, MemoView m, uint32_t chunk, uint32_t wpv) {
+  hook_hubs_body<PER_EDGE>(g, m, chunk, wpv, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_lists(MemoView m) { lists_body(m, blockIdx.x); }
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_link(GraphView g, MemoView m) {
+  link_body<PER_EDGE>(g, m, blockIdx.x, gridDim.x);
+}
+template <bool PER_EDGE>
+__global__ void __launch_bounds__(256) k_link_hubs(GraphView g, MemoView m) {
+  link_hubs_body<PER_EDGE>(g, m, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_flatten(MemoView m) { flatten_body(m, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts) {
+  count_body(m, block_verts, blockIdx.x);
+}
+__global__ void __launch_bounds__(256) k_gain0(MemoView m) { gain0_body(m, blockIdx.x, gridDim.x); }
+
+// Batched: workgroup blockIdx.x of the phase belongs to the graph found in
+// the phase's prefix sums; per-slot and uniform probabilities are chosen per
+// graph (uniform over a workgroup).
+__global__ void __launch_bounds__(256) k_hook_rows_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const BuildJob& J = b.jobs[batch_job(b, kBpHookRows, blockIdx.x, local, nblk)];
+  const GraphView g = J.g;
+  const MemoView m = J.m;
+  if (g.tm1) hook_rows_body<true>(g, m, local);
+  else hook_rows_body<false>(g, m, local);
+}
+__global__ void __launch_bounds__(256) k_hook_hubs_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const BuildJob& J = b.jobs[batch_job(b, kBpHookHubs, blockIdx.x, local, nblk)];
+  const GraphView g = J.g;
+  const MemoView m = J.m;
+  if (g.tm1) hook_hubs_body<true>(g, m, J.hub_chunk, J.hub_wpv, local);
+  else hook_hubs_body<false>(g, m, J.hub_chunk, J.hub_wpv, local);
+}
+__global__ void __launch_bounds__(256) k_lists_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const MemoView m = b.jobs[batch_job(b, kBpLists, blockIdx.x, local, nblk)].m;
+  lists_body(m, local);
+}
+__global__ void __launch_bounds__(256) k_link_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const BuildJob& J = b.jobs[batch_job(b, kBpLink, blockIdx.x, local, nblk)];
+  const GraphView g = J.g;
+  const MemoView m = J.m;
+  if (g.tm1) link_body<true>(g, m, local, nblk);
+  else link_body<false>(g, m, local, nblk);
+}
+__global__ void __launch_bounds__(256) k_link_hubs_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const BuildJob& J = b.jobs[batch_job(b, kBpLinkHubs, blockIdx.x, local, nblk)];
+  const GraphView g = J.g;
+  const MemoView m = J.m;
+  if (g.tm1) link_hubs_body<true>(g, m, local);
+  else link_hubs_body<false>(g, m, local);
+}
+__global__ void __launch_bounds__(256) k_flatten_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const MemoView m = b.jobs[batch_job(b, kBpFlatten, blockIdx.x, local, nblk)].m;
+  flatten_body(m, local, nblk);
+}
+__global__ void __launch_bounds__(256) k_count_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const BuildJob& J = b.jobs[batch_job(b, kBpCount, blockIdx.x, local, nblk)];
+  const MemoView m = J.m;
+  count_body(m, J.count_bv, local);
+}
+__global__ void __launch_bounds__(256) k_gain0_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const MemoView m = b.jobs[batch_job(b, kBpGain0, blockIdx.x, local, nblk)].m;
+  gain0_body(m, local, nblk);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value) {
@@ -660,12 +772,11 @@ void launch_lists(const MemoView& m, hipStream_t st) {
 }
 
 
-void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk, hipStream_t st) {
-  (void)chunk;
+void launch_link(const GraphView& g, const MemoView& m, uint32_t blocks, hipStream_t st) {
   if (g.tm1)
-    hipLaunchKernelGGL(k_link<true>, dim3(kListBlocks), dim3(256), 0, st, g, m);
+    hipLaunchKernelGGL(k_link<true>, dim3(blocks), dim3(256), 0, st, g, m);
   else
-    hipLaunchKernelGGL(k_link<false>, dim3(kListBlocks), dim3(256), 0, st, g, m);
+    hipLaunchKernelGGL(k_link<false>, dim3(blocks), dim3(256), 0, st, g, m);
 }
 
 void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st) {
@@ -678,9 +789,8 @@ void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st) {
     hipLaunchKernelGGL(k_link_hubs<false>, grid, dim3(256), 0, st, g, m);
 }
 
-void launch_compress(const MemoView& m, uint32_t chunk, hipStream_t st) {
-  (void)chunk;
-  hipLaunchKernelGGL(k_flatten, dim3(kListBlocks), dim3(256), 0, st, m);
+void launch_flatten(const MemoView& m, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_flatten, dim3(blocks), dim3(256), 0, st, m);
 }
 
 void launch_count(const MemoView& m, hipStream_t st) {
@@ -689,8 +799,44 @@ void launch_count(const MemoView& m, hipStream_t st) {
   hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m, bv);
 }
 
-void launch_gain0(const MemoView& m, hipStream_t st) {
-  hipLaunchKernelGGL(k_gain0, dim3(kListBlocks), dim3(256), 0, st, m);
+void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_gain0, dim3(blocks), dim3(256), 0, st, m);
+}
+
+// Workgroups of one graph in each labelling phase of a batched launch: the
+// single-graph grids, except the list kernels, whose grid scales with the
+// graph's (vertex, tile) pairs (64 per workgroup, at most list_blocks).
+void build_job_shape(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, uint32_t list_blocks,
+                     BuildJob* job, uint32_t* blocks) {
+  job->hub_chunk = chunk_tiles;
+  job->hub_wpv = waves_per_vertex(m, chunk_tiles);
+  job->count_bv = count_block_verts(m);
+  const uint64_t pairs = (uint64_t)m.n * m.ntiles;
+  const uint32_t lb = (uint32_t)std::min<uint64_t>(list_blocks, std::max<uint64_t>(1, (pairs + 63) / 64));
+  blocks[kBpHookRows] = (m.n + 3) / 4;
+  blocks[kBpHookHubs] = g.nhubs ? grid_for(g.nhubs, job->hub_wpv).x : 0;
+  blocks[kBpLists] = kSubLists;
+  blocks[kBpLink] = lb;
+  blocks[kBpLinkHubs] = g.hub_pieces ? (uint32_t)(((uint64_t)g.hub_pieces * m.ntiles + 3) / 4) : 0;
+  blocks[kBpFlatten] = lb;
+  blocks[kBpCount] = ((m.n + job->count_bv - 1) / job->count_bv) * m.ntiles;
+  blocks[kBpGain0] = lb;
+}
+
+void launch_build_batch(const BuildBatch& b, uint32_t phase, uint32_t blocks, hipStream_t st) {
+  if (!blocks) return;
+  const dim3 grid(blocks), block(256);
+  switch (phase) {
+    case kBpHookRows: hipLaunchKernelGGL(k_hook_rows_batch, grid, block, 0, st, b); break;
+    case kBpHookHubs: hipLaunchKernelGGL(k_hook_hubs_batch, grid, block, 0, st, b); break;
+    case kBpLists: hipLaunchKernelGGL(k_lists_batch, grid, block, 0, st, b); break;
+    case kBpLink: hipLaunchKernelGGL(k_link_batch, grid, block, 0, st, b); break;
+    case kBpLinkHubs: hipLaunchKernelGGL(k_link_hubs_batch, grid, block, 0, st, b); break;
+    case kBpFlatten: hipLaunchKernelGGL(k_flatten_batch, grid, block, 0, st, b); break;
+    case kBpCount: hipLaunchKernelGGL(k_count_batch, grid, block, 0, st, b); break;
+    case kBpGain0: hipLaunchKernelGGL(k_gain0_batch, grid, block, 0, st, b); break;
+    default: break;
+  }
 }
 
 }  // namespace infuse

@@ -57,6 +57,10 @@ struct PCelfScratch {
   uint64_t kmax;
   uint64_t pad1[4];
   uint64_t prof[16];                  // workgroup 0's phase clock, then counts
+  // profiling: listed (candidate, tile) pairs evaluated and their columns of
+  // non-singleton components (each a size gather and a coverage word), added
+  // once per wavefront at the end; a line of its own (only atomics write it)
+  alignas(128) uint64_t work[2];
   alignas(128) uint32_t arrive[kGroups][32];  // one 128-byte line per group
   uint32_t top[32];
   uint32_t release[kGroups][32];
@@ -392,6 +396,27 @@ __device__ inline uint64_t p_sum_list(const CelfView& c, uint32_t u, const uint3
     }
   }
   return sum;
+}
+
+// Profiling work counts of one (candidate, tile) evaluation: whether the
+// tile is listed (its row words hold the candidate's components) and, if so,
+// this wavefront's columns of non-singleton components (their size and
+// coverage words are gathered).  Only while profiling: it loads the row again.
+__device__ inline void p_count_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane, uint64_t& tiles,
+                                    uint64_t& cols) {
+  const MemoView& m = c.m;
+  const uint32_t tw = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
+  if (!((tw >> (t & 31)) & 1u)) return;
+  const uint32_t q0 = t * kTile + lane * kPerLane;
+  const p_i4 r = ldg4(m.M + (uint64_t)u * m.Rs + q0);
+  uint64_t k = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) k += (q0 + i < m.R && r[i] != -1) ? 1u : 0u;
+  k = p_wsum(k);
+  if (lane == 0) {
+    tiles += 1;
+    cols += k;
+  }
 }
 
 // Bitonic sort of key/id[0, cnt) descending, cnt a power of two.
@@ -754,7 +779,8 @@ __device__ bool pool_rebuild(const PCelfJob& a, const Grp& G, PoolLds& L, uint32
 }
 
 // Bulk evaluation of every stale vertex whose key exceeds kstar.
-__device__ bool bulk_eval(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t s, uint64_t kstar, uint32_t& gen,
+__device__ bool bulk_eval(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t s, uint64_t kstar, uint64_t& ptiles,
+                          uint64_t& pcols, uint32_t& gen,
                           PClock& clk, uint64_t& evals) {
   const CelfView& c = a.c;
   PCelfScratch* x = a.x;
@@ -836,6 +862,10 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t 
           p_take_tiles(sparse, ntiles, nrem, npos, nt);
         p_load_list(c, more ? v : vn, nt, lane, nxt, nword);
         sum += p_sum_list(c, v, ct, lane, cur, cword);
+        if (a.prof)
+#pragma unroll
+          for (int b = 0; b < kBulkB; ++b)
+            if (ct[b] != kInvalid) p_count_tile(c, v, ct[b], lane, ptiles, pcols);
       }
       sum = p_wsum(sum) + singles;
       if (lane == 0) {
@@ -864,6 +894,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, prev = kInvalid, step_rebuilds = 0;
   bool synced = true;  // a grid barrier has passed since the last commit
   uint64_t evals = 0;
+  uint64_t ptiles = 0, pcols = 0;  // profiling work counts of this wavefront
   PClock clk;
   clk.start(a.prof != 0);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
@@ -959,6 +990,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         const uint32_t u = L.sid[head + w];
         uint64_t ov;
         const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, ahead ? lead : u, ov));
+        if (a.prof) p_count_tile(c, u, t, lane, ptiles, pcols);
         ov = ahead ? p_wsum(ov) : 0;
         if (lane == 0 && part) g_add64(&g[w], part);
         if (lane == 0 && ov) g_add64(&g[kMaxCand + w], ov);
@@ -1002,7 +1034,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       return;
     }
     if (nf && step_rebuilds > 0)
-      if (!bulk_eval(a, G, L, s, fbest, gen, clk, evals)) return;
+      if (!bulk_eval(a, G, L, s, fbest, ptiles, pcols, gen, clk, evals)) return;
     if (threadIdx.x == 0) L.lead = kInvalid;  // the rebuilt F did not come from one round
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     synced = true;
@@ -1012,6 +1044,10 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       return;
     }
     just_rebuilt = true;
+  }
+  if (a.prof && lane == 0) {
+    g_add64(&x->work[0], ptiles);
+    g_add64(&x->work[1], pcols);
   }
   if (G.bi == 0 && threadIdx.x == 0) {
     c.st->s = s;
@@ -1069,6 +1105,7 @@ __global__ void __launch_bounds__(kPBlock) k_celf_persistent(const PCelfJob* __r
 
 uint64_t pcelf_scratch_bytes() { return sizeof(PCelfScratch); }
 uint64_t pcelf_prof_offset() { return offsetof(PCelfScratch, prof); }
+uint64_t pcelf_work_offset() { return offsetof(PCelfScratch, work); }
 uint64_t pcelf_err_offset() { return offsetof(PCelfScratch, err); }
 
 // Workgroups of the persistent grid on `device`: two per compute unit, or

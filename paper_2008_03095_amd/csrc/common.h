@@ -103,6 +103,22 @@ struct MemoView {
                         // neighbours (k_link)
   uint32_t* counts;     // [2 * j] = |tlist_j|, [2 * j + 1] = |llist_j|
   uint32_t list_cap;
+  // work counts of the construction (kWork* below), or nullptr when not
+  // counting (they cost atomics: only while profiling at level 3)
+  unsigned long long* work;
+};
+
+// Indices of MemoView::work.
+enum : uint32_t {
+  kWorkLivePairs = 0,    // live (edge, column) pairs: every live edge-sample, seen from its larger end
+  kWorkUnions = 1,       // union attempts of the link kernels
+  kWorkRewrites = 2,     // rows rewritten by k_flatten
+  kWorkCountAtomics = 3, // root decrements of k_count made in device memory (the others are summed in LDS)
+  kWorkRowTiles = 4,     // tiles written by k_hook_rows
+  kWorkHubTiles = 5,     // tiles written by k_hook_hubs
+  kWorkGathers = 6,      // root-size gathers of k_gain0 (member columns)
+  kWorkHubLinkWaves = 7, // k_link_hubs wavefronts with a union tile
+  kWorkCounts = 8
 };
 
 // Memo entry of v in column q (see MemoView::M): -1 where v's tile has no
@@ -113,6 +129,61 @@ __device__ inline int32_t memo_entry(const MemoView& m, uint32_t v, uint32_t q) 
   const int32_t val = m.M[(uint64_t)v * m.Rs + q];
   const bool on = (m.tmask[(uint64_t)v * m.mwords + (t >> 5)] >> (t & 31)) & 1u;
   return on ? val : -1;
+}
+
+// Memo constructions of many graphs in one launch per phase (batching):
+// per graph its views and launch shapes, and per phase the prefix sums of
+// the workgroups each graph takes (a workgroup finds its graph by binary
+// search, then runs the single-graph code on its share).
+enum : uint32_t {
+  kBpPrep = 0,   // X sort (R <= 4096), edge hashes, mask and counter clearing
+  kBpHookRows,
+  kBpHookHubs,
+  kBpLists,
+  kBpLink,
+  kBpLinkHubs,
+  kBpFlatten,
+  kBpCount,
+  kBpGain0,
+  kBatchPhases
+};
+
+struct BuildJob {
+  GraphView g;
+  MemoView m;
+  uint2* edges;          // writable views of the sampler arrays (m.edges, m.xs)
+  uint32_t* xs;
+  uint32_t* inv;
+  uint32_t* pos;
+  uint32_t seed;
+  uint32_t sort_blocks;  // prep: 1 when the X sort runs here, 0 when done before
+  uint32_t hash_blocks;  // prep: edge-hash workgroups after the sort's
+  uint32_t hub_chunk;    // hook_hubs: tiles per wavefront
+  uint32_t hub_wpv;      // hook_hubs: wavefronts per hub vertex
+  uint32_t count_bv;     // count: vertices per workgroup
+  uint32_t fill_words;   // prep: u32 words cleared from m.tmask on (both mask arrays)
+};
+
+struct BuildBatch {
+  const BuildJob* jobs;
+  const uint32_t* first;  // [kBatchPhases][njobs + 1] workgroup prefix sums
+  uint32_t njobs;
+};
+
+// The graph of workgroup `block` in `phase`, its index among that graph's
+// workgroups and their number.
+__device__ inline uint32_t batch_job(const BuildBatch& b, uint32_t phase, uint32_t block, uint32_t& local,
+                                     uint32_t& nblk) {
+  const uint32_t* f = b.first + (uint64_t)phase * (b.njobs + 1);
+  uint32_t lo = 0, hi = b.njobs;  // the last lo with f[lo] <= block
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (f[mid] <= block) lo = mid;
+    else hi = mid;
+  }
+  local = block - f[lo];
+  nblk = f[lo + 1] - f[lo];
+  return lo;
 }
 
 constexpr uint32_t kHubPiece = 256;  // smaller neighbours of a hub per union wavefront

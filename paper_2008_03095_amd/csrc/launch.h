@@ -11,17 +11,26 @@ void launch_edge_hash(const GraphView& g, uint32_t seed, uint2* edges, hipStream
 uint32_t x_sort_scratch_elems(uint32_t R);
 void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, uint32_t* xs,
                    uint32_t* inv, uint32_t* pos, hipStream_t st);
+uint32_t x_sort_single_max();  // largest R the batched set-up sorts itself
+// batched set-up (kBpPrep) over the jobs of b; `blocks` = the phase's total
+void launch_prep_batch(const BuildBatch& b, uint32_t blocks, hipStream_t st);
 
 // cc.hip
 void launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t st);
 void launch_hook_rows(const GraphView& g, const MemoView& m, hipStream_t st);
 void launch_hook_hubs(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
 void launch_lists(const MemoView& m, hipStream_t st);
-void launch_link(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_link(const GraphView& g, const MemoView& m, uint32_t blocks, hipStream_t st);
 void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st);
-void launch_compress(const MemoView& m, uint32_t chunk_tiles, hipStream_t st);
+void launch_flatten(const MemoView& m, uint32_t blocks, hipStream_t st);
 void launch_count(const MemoView& m, hipStream_t st);
-void launch_gain0(const MemoView& m, hipStream_t st);
+void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st);
+// batched labelling: the shape of one graph's job (hook_hubs and count
+// parameters; workgroups per phase into blocks[kBatchPhases], prep excluded)
+// and one phase's launch over all jobs of b (`blocks` = the phase's total)
+void build_job_shape(const GraphView& g, const MemoView& m, uint32_t chunk_tiles, uint32_t list_blocks, BuildJob* job,
+                     uint32_t* blocks);
+void launch_build_batch(const BuildBatch& b, uint32_t phase, uint32_t blocks, hipStream_t st);
 
 // celf.hip
 uint32_t celf_topw_blocks(uint32_t n);
@@ -34,7 +43,8 @@ void launch_celf_bulk(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 // celf_persistent.hip
 uint64_t pcelf_scratch_bytes();
 uint64_t pcelf_err_offset();   // u32 error flag of the persistent kernel
-uint64_t pcelf_prof_offset();  // 8 x u64: phase ticks (100 MHz) x5, barriers, rounds, rebuilds
+uint64_t pcelf_prof_offset();  // 16 x u64: phase ticks (100 MHz) x10, -, -, barriers, rounds, rebuilds/bulks, look-ahead commits
+uint64_t pcelf_work_offset();  // 2 x u64 (profiling): listed tiles evaluated, their non-singleton columns
 uint32_t pcelf_grid(int device);
 uint64_t pcelf_job_bytes();
 // Writes the description of one selection (for a group of group_blocks

@@ -42,6 +42,8 @@ struct Memo {
   uint32_t* tlist = nullptr;
   uint32_t* llist = nullptr;
   uint32_t* counts = nullptr;
+  unsigned long long* work = nullptr;  // [kWorkCounts], right after counts
+  bool counted = false;                // work holds the counts of the construction
   uint32_t list_cap = 0;
   uint64_t last_use = 0;
   int pins = 0;
@@ -68,6 +70,8 @@ void ctx_free(im_ctx* c, void* p);
 void memo_destroy(im_graph* g, Memo* m);
 uint64_t memo_bytes(const im_graph* g, uint32_t R);
 Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed);
+im_status memo_alloc(im_graph* g, double p, uint32_t R, uint32_t seed, Memo** out);
+uint32_t hub_chunk_tiles(const im_ctx* c);
 bool memo_matches(const im_graph* g, const Memo* m, double p, uint32_t R, uint32_t seed);
 im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out);
 im_status memo_acquire(im_graph* g, Memo** out);

@@ -217,6 +217,7 @@ MemoView Memo::view(const im_graph* g) const {
   v.llist = llist;
   v.counts = counts;
   v.list_cap = list_cap;
+  v.work = nullptr;
   return v;
 }
 
@@ -247,7 +248,7 @@ uint64_t memo_bytes(const im_graph* g, uint32_t R) {
   b += align256((size_t)g->n * mwords * 4) * 2;
   b += align256((size_t)g->n * 8);
   b += align256((size_t)list_capacity(g->n, ntiles) * kSubLists * 4) * 2;
-  b += align256((size_t)kSubLists * 2 * 4);
+  b += align256((size_t)kSubLists * 2 * 4 + kWorkCounts * 8);
   return b;
 }
 
@@ -262,8 +263,12 @@ Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
   return nullptr;
 }
 
-// Allocates the memo and enqueues its construction on `st`.
-im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out) {
+// Tiles per hook_hubs wavefront from the context's cc_chunk (columns).
+uint32_t hub_chunk_tiles(const im_ctx* c) { return std::max(1u, std::min(32u, c->tune.cc_chunk / kTile)); }
+
+// Allocates the memo of (p, R, seed), registers it with the graph and
+// returns it pinned; nothing is enqueued.
+im_status memo_alloc(im_graph* g, double p, uint32_t R, uint32_t seed, Memo** out) {
   if (g->directed)
     return fail(IM_ERR_INVALID_ARG,
                 "directed graph: components do not give reachability; use im_estimate_sigma_direct");
@@ -279,6 +284,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->never_live = (!g->per_edge && T == 0) ? 1u : 0u;
   m->tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
   m->kshift = bitlen32(m->tm1);
+  m->counted = false;
   if (g->nhubs) {
     if (hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming) != hipSuccess) m->fork_ev = nullptr;
     if (hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming) != hipSuccess) m->join_ev = nullptr;
@@ -312,7 +318,8 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   m->list_cap = list_capacity(g->n, m->ntiles);
   m->tlist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
   m->llist = reinterpret_cast<uint32_t*>(take((size_t)m->list_cap * kSubLists * 4));
-  m->counts = reinterpret_cast<uint32_t*>(take((size_t)kSubLists * 2 * 4));
+  m->counts = reinterpret_cast<uint32_t*>(take((size_t)kSubLists * 2 * 4 + kWorkCounts * 8));
+  m->work = reinterpret_cast<unsigned long long*>(m->counts + 2 * kSubLists);
   {
     // returned pinned: nothing may evict it before the caller is done with it
     std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -320,9 +327,23 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     g->memos.push_back(m);
     m->last_use = ++c->use_clock;
   }
+  *out = m;
+  return IM_OK;
+}
 
-  const MemoView mv = m->view(g);
-  const uint32_t chunk_tiles = std::max(1u, std::min(32u, c->tune.cc_chunk / kTile));
+// Allocates the memo and enqueues its construction on `st`.
+im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out) {
+  Memo* m = nullptr;
+  im_status s = memo_alloc(g, p, R, seed, &m);
+  if (s != IM_OK) return s;
+  im_ctx* c = g->ctx;
+  MemoView mv = m->view(g);
+  m->counted = c->profiling >= 3;
+  if (m->counted) {
+    mv.work = m->work;
+    launch_fill_u32(reinterpret_cast<uint32_t*>(m->work), 2 * kWorkCounts, 0u, st);
+  }
+  const uint32_t chunk_tiles = hub_chunk_tiles(c);
   const bool timed = g->ev[0] != nullptr && st == c->stream;
   if (timed) (void)hipEventRecord(g->ev[0], st);
   {
@@ -380,7 +401,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   }
   {
     KTimer t(c, "link", st);
-    launch_link(g->view(), mv, chunk_tiles, st);
+    launch_link(g->view(), mv, c->tune.list_blocks, st);
   }
   if (fork2) {
     (void)hipStreamWaitEvent(st, m->join_ev, 0);
@@ -390,7 +411,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   }
   {
     KTimer t(c, "flatten", st);
-    launch_compress(mv, chunk_tiles, st);
+    launch_flatten(mv, c->tune.list_blocks, st);
   }
   {
     KTimer t(c, "count", st);
@@ -399,7 +420,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   if (timed) (void)hipEventRecord(g->ev[2], st);
   {
     KTimer t(c, "gain0", st);
-    launch_gain0(mv, st);
+    launch_gain0(mv, c->tune.list_blocks, st);
   }
   if (timed) (void)hipEventRecord(g->ev[3], st);
   hipError_t e = hipGetLastError();
@@ -675,6 +696,13 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
       }
       c->kstats["celf.lookahead_commits"].first += pr[15];  // steps decided without a round
     }
+    uint64_t wk[2];
+    if (hipMemcpy(wk, static_cast<char*>(cb->pscratch) + pcelf_work_offset(), sizeof(wk), hipMemcpyDeviceToHost) ==
+        hipSuccess) {
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      c->kstats["celf.listed_tiles"].first += wk[0];  // listed (candidate, tile) pairs evaluated
+      c->kstats["celf.gathers"].first += wk[1];       // their non-singleton columns
+    }
   }
   if (hs.s != v.K) return fail(IM_ERR_DEVICE, "CELF committed %u of %u seeds", hs.s, v.K);
   int64_t tot = 0;
@@ -724,6 +752,7 @@ extern "C" im_status im_ctx_create(int device, void* stream, const im_allocator*
   c->tune.cc_chunk = 256;
   c->tune.celf_width = 16;
   c->tune.use_graphs = 0;
+  c->tune.list_blocks = kListBlocks;
   c->coop_grid = pcelf_grid(device);
   c->tune.celf_mode = c->coop_grid ? 1 : 2;
   if (c->coop_grid && hipEventCreateWithFlags(&c->coop_done, hipEventDisableTiming) != hipSuccess) {
@@ -781,6 +810,11 @@ extern "C" im_status im_set_tuning(im_ctx* c, const im_tuning* t) {
     if (t->celf_round0 > 1024) return fail(IM_ERR_INVALID_ARG, "celf_round0 must be <= 1024");
     c->tune.celf_round0 = t->celf_round0;
   }
+  if (t->list_blocks) {
+    if (t->list_blocks < 256 || t->list_blocks > 65536)
+      return fail(IM_ERR_INVALID_ARG, "list_blocks must be in 256 .. 65536");
+    c->tune.list_blocks = t->list_blocks;
+  }
   return IM_OK;
 }
 
@@ -792,7 +826,7 @@ extern "C" im_status im_get_tuning(const im_ctx* c, im_tuning* t) {
 
 extern "C" im_status im_set_profiling(im_ctx* c, int level) {
   if (!c) return fail(IM_ERR_INVALID_ARG, "NULL context");
-  if (level < 0 || level > 2) return fail(IM_ERR_INVALID_ARG, "profiling level must be 0, 1 or 2");
+  if (level < 0 || level > 3) return fail(IM_ERR_INVALID_ARG, "profiling level must be 0, 1, 2 or 3");
   c->profiling = level;
   return IM_OK;
 }
@@ -1551,6 +1585,31 @@ extern "C" im_status im_last_phase_ms(const im_graph* g, double* ms4) {
 }
 
 extern "C" uint64_t im_last_celf_evals(const im_graph* g) { return g ? g->last_evals : 0; }
+
+extern "C" im_status im_memo_work(im_graph* g, uint64_t* out, uint32_t n_out) {
+  if (!g || (n_out && !out)) return fail(IM_ERR_INVALID_ARG, "NULL argument");
+  if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
+  im_ctx* c = g->ctx;
+  Memo* m = nullptr;
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    m = memo_find(g, g->p, g->R, g->seed);
+    if (m) m->pins++;
+  }
+  if (!m) return fail(IM_ERR_INVALID_ARG, "no resident memo for the current parameters");
+  if (!m->counted) {
+    memo_release(g, m);
+    return fail(IM_ERR_INVALID_ARG, "the memo was built without work counting (profiling level 3)");
+  }
+  unsigned long long h[kWorkCounts];
+  if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+  hipError_t e = hipMemcpyAsync(h, m->work, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  memo_release(g, m);
+  if (e != hipSuccess) return fail(IM_ERR_DEVICE, "work count copy failed: %s", hipGetErrorString(e));
+  for (uint32_t k = 0; k < n_out; ++k) out[k] = k < kWorkCounts ? h[k] : 0;
+  return IM_OK;
+}
 
 extern "C" im_status im_memo_stats(im_graph* g, uint64_t* out4) {
   if (!g || !out4) return fail(IM_ERR_INVALID_ARG, "NULL argument");

@@ -13,10 +13,11 @@
 
 namespace infuse {
 
-__global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, uint2* edges) {
+// One wavefront per vertex row, strided over the `nblk` workgroups.
+__device__ inline void edge_hash_body(const GraphView& g, uint32_t seed, uint2* edges, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t wave = (bid * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (nblk * blockDim.x) >> 6;
   for (uint32_t u = wave; u < g.n; u += nwaves) {
     const uint32_t beg = g.row_ptr[u], end = g.row_ptr[u + 1];
     for (uint32_t j = beg + lane; j < end; j += kWave) {
@@ -24,6 +25,10 @@ __global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, u
       edges[j] = make_uint2(v, fmix32(seed ^ (g.directed ? arc_key32(u, v, g.n) : edge_key32(u, v, g.n))));
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_edge_hash(GraphView g, uint32_t seed, uint2* edges) {
+  edge_hash_body(g, seed, edges, blockIdx.x, gridDim.x);
 }
 
 constexpr int kSortChunk = 4096;  // elements sorted per block in LDS
@@ -60,10 +65,10 @@ __global__ void __launch_bounds__(1024) k_x_sort_chunk(uint32_t seed, uint32_t R
   for (uint32_t i = threadIdx.x; i < kSortChunk; i += blockDim.x) out[base + i] = i < len ? a[i] : ~0ull;
 }
 
-// R <= kSortChunk: one workgroup sorts and writes the column order and the
-// padding columns directly.
-__global__ void __launch_bounds__(1024) k_x_sort_single(uint32_t seed, uint32_t R, uint32_t Rs, uint32_t* xs,
-                                                        uint32_t* inv, uint32_t* pos) {
+// R <= kSortChunk: one workgroup (of any size) sorts and writes the column
+// order and the padding columns directly.
+__device__ inline void x_sort_single_body(uint32_t seed, uint32_t R, uint32_t Rs, uint32_t* xs, uint32_t* inv,
+                                          uint32_t* pos) {
   __shared__ uint64_t a[kSortChunk];
   uint32_t len = kSortChunk;
   while (len > 2 && len / 2 >= R) len /= 2;
@@ -98,6 +103,36 @@ __global__ void __launch_bounds__(1024) k_x_sort_single(uint32_t seed, uint32_t 
       inv[q] = kInvalid;
     }
   }
+}
+
+__global__ void __launch_bounds__(1024) k_x_sort_single(uint32_t seed, uint32_t R, uint32_t Rs, uint32_t* xs,
+                                                        uint32_t* inv, uint32_t* pos) {
+  x_sort_single_body(seed, R, Rs, xs, inv, pos);
+}
+
+// Batched set-up of many memos: per graph, one workgroup sorts X (when
+// R <= kSortChunk; larger R is sorted by the single-graph kernels first),
+// the next ones hash the edges and the rest clear the mask arrays.
+__global__ void __launch_bounds__(256) k_prep_batch(BuildBatch b) {
+  uint32_t local, nblk;
+  const uint32_t j = batch_job(b, kBpPrep, blockIdx.x, local, nblk);
+  const BuildJob& J = b.jobs[j];
+  const uint32_t sort_blocks = J.sort_blocks, hash_blocks = J.hash_blocks;
+  if (local < sort_blocks) {
+    x_sort_single_body(J.seed, J.m.R, J.m.Rs, J.xs, J.inv, J.pos);
+    return;
+  }
+  local -= sort_blocks;
+  if (local < hash_blocks) {
+    const GraphView g = J.g;
+    edge_hash_body(g, J.seed, J.edges, local, hash_blocks);
+    return;
+  }
+  local -= hash_blocks;
+  const uint32_t fb = nblk - sort_blocks - hash_blocks;
+  uint32_t* p = J.m.tmask;
+  const uint64_t words = J.fill_words;
+  for (uint64_t i = (uint64_t)local * blockDim.x + threadIdx.x; i < words; i += (uint64_t)fb * blockDim.x) p[i] = 0u;
 }
 
 // Global rank of each element = its rank in its own sorted chunk plus the
@@ -142,6 +177,12 @@ void launch_edge_hash(const GraphView& g, uint32_t seed, uint2* edges, hipStream
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(256), 0, st, g, seed, edges);
 }
+
+void launch_prep_batch(const BuildBatch& b, uint32_t blocks, hipStream_t st) {
+  if (blocks) hipLaunchKernelGGL(k_prep_batch, dim3(blocks), dim3(256), 0, st, b);
+}
+
+uint32_t x_sort_single_max() { return kSortChunk; }
 
 uint32_t x_sort_scratch_elems(uint32_t R) {
   return (R + kSortChunk - 1) / kSortChunk * kSortChunk;

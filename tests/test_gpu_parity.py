@@ -329,15 +329,18 @@ def test_autotune_picks_a_shape_and_keeps_results(gpu_ctx, tmp_path):
         cache = str(tmp_path / "tuning.json")
         t = gpu_ctx.autotune(G, 12, reps=1, cache=cache)
         assert t["cc_chunk"] in (256, 512, 1024)
+        assert t["list_blocks"] in (2048, 8192, 32768)
         if t["celf_mode"] == P.Context.CELF_PERSISTENT:
             assert t["celf_round0"] in (8, 16, 32)
         again = gpu_ctx.autotune(G, 12, reps=1, cache=cache)  # from the cache
         assert again["cc_chunk"] == t["cc_chunk"] and again["celf_round0"] == t["celf_round0"]
+        assert again["list_blocks"] == t["list_blocks"]
         ref = oracle.run_memo(g, oracle.Sampler("hash", p=0.04, R=512, seed=8), 12, threads=4)
         seeds, marg, cover = G.select_seeds(12)
         assert list(seeds) == list(ref["seeds"]) and cover == ref["cover"]
     finally:
-        gpu_ctx.set_tuning(cc_chunk=old["cc_chunk"], celf_mode=old["celf_mode"], celf_round0=old["celf_round0"])
+        gpu_ctx.set_tuning(cc_chunk=old["cc_chunk"], celf_mode=old["celf_mode"], celf_round0=old["celf_round0"],
+                           list_blocks=old["list_blocks"])
         G.free()
 
 
