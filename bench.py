@@ -173,7 +173,10 @@ def serve_bench(args):
         return srv.submit_select(Gs[q.graph], q.K, q.p, q.R, seed)
 
     # warm-up: one query of each kind (device code loading, allocator pools)
-    srv = P.Server(ctx, slots=args.slots)
+    def server():
+        return P.Server(ctx, slots=args.slots, persistent_min_mwords=args.persistent_min_mwords)
+
+    srv = server()
     for q in trace[:2]:
         srv.poll(submit(srv, q), wait_ms=600000)
     srv.close()
@@ -181,7 +184,7 @@ def serve_bench(args):
         G.drop_memo()
 
     # served: real-time arrivals, continuous admission, memo reuse, overlap
-    srv = P.Server(ctx, slots=args.slots)
+    srv = server()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = []
@@ -202,7 +205,7 @@ def serve_bench(args):
     # the makespan measures the server's capacity rather than the arrival rate
     for G in Gs:
         G.drop_memo()
-    srv = P.Server(ctx, slots=args.slots)
+    srv = server()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = [submit(srv, q) for q in trace]
@@ -261,7 +264,8 @@ def serve_bench(args):
         "config": {"workload": "c5: Chung-Lu 15k/31k, Chung-Lu 37k/175k, R-MAT 18 ef 5, R-MAT 20 ef 8; "
                                "Poisson 200 queries/s, seed 4, 70% sigma(S) |S| in 1..50, 30% selections; "
                                "p in {.005,.01,.02,.05}, R in {256,1024,4096,8192}, K in {10,50,100}",
-                   "queries": len(trace), "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib},
+                   "queries": len(trace), "slots": args.slots, "hbm_budget_gib": args.hbm_budget_gib,
+                   "persistent_min_mwords": args.persistent_min_mwords},
         "served": {"throughput_qps": len(trace) / t_served, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
                    "by_kind": {k: {"n": len(v), "p50_ms": _pct(v, 50), "p99_ms": _pct(v, 99)}
                                for k, v in by_kind.items()},
@@ -493,7 +497,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c3", "c5", "d1"])
-    ap.add_argument("--queries", type=int, default=300, help="serving workload: queries of the trace")
+    ap.add_argument("--queries", type=int, default=2000, help="serving workload: queries of the trace")
+    ap.add_argument("--persistent-min-mwords", type=int, default=0,
+                    help="serving workload: memo size (2^20 words) below which selections run the per-step "
+                         "kernels beside the other slots (0: every selection persistent)")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: concurrent query slots")
     ap.add_argument("--hbm-budget-gib", type=float, default=224.0, help="serving workload: memo budget")
     ap.add_argument("--cpu-samples", type=int, default=8192)

@@ -323,7 +323,13 @@ im_status im_batch_select(im_ctx *ctx, uint32_t n_graphs, im_graph *const *graph
  * direct calls.  Graphs passed to submit must outlive the server. */
 typedef struct {
     uint32_t slots;        /* concurrent queries on the device (>= 1) */
-    uint32_t reserved[7];
+    /* selections whose memo has fewer (vertex, simulation) words than this,
+     * in units of 2^20, run the per-step CELF kernels on their slot, beside
+     * the other slots' work; the others run the persistent CELF kernel,
+     * which holds the whole device while it runs (the other slots wait).
+     * 0 (default): every selection persistent; 0xFFFFFFFF: none. */
+    uint32_t persistent_min_mwords;
+    uint32_t reserved[6];
 } im_server_config;
 
 typedef struct {

@@ -330,11 +330,12 @@ class Server:
 
     SIGMA, SELECT = 0, 1
 
-    def __init__(self, ctx: Context, slots: int = 4):
+    def __init__(self, ctx: Context, slots: int = 4, persistent_min_mwords: int = 0):
         self._lib = ctx._lib
         self.ctx = ctx
         cfg = im_server_config()
         cfg.slots = slots
+        cfg.persistent_min_mwords = persistent_min_mwords
         out = C.c_void_p()
         check(self._lib.im_server_create(ctx.handle, C.byref(cfg), C.byref(out)))
         self.handle = out

@@ -37,7 +37,7 @@ class im_tuning(C.Structure):
 
 
 class im_server_config(C.Structure):
-    _fields_ = [("slots", C.c_uint32), ("reserved", C.c_uint32 * 7)]
+    _fields_ = [("slots", C.c_uint32), ("persistent_min_mwords", C.c_uint32), ("reserved", C.c_uint32 * 6)]
 
 
 class im_query(C.Structure):

@@ -579,9 +579,9 @@ bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_
   return true;
 }
 
-void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
+void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st, bool persistent_ok) {
   celf_prepare(cb, st);
-  if (c->tune.celf_mode == 1 && c->coop_grid) {
+  if (persistent_ok && c->tune.celf_mode == 1 && c->coop_grid) {
     pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0,
                    c->profiling >= 2);
     if (hipMemcpyAsync(cb->pjob, cb->hjob, pcelf_job_bytes(), hipMemcpyHostToDevice, st) == hipSuccess &&

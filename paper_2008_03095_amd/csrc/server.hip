@@ -72,6 +72,7 @@ struct im_server {
   bool stop = false;
   uint64_t next_id = 1;
   uint64_t admitted = 0, completed = 0, rejected = 0, hits = 0, builds = 0, peak = 0;
+  uint64_t persistent_min_words = 0;  // selections on smaller memos run the per-step kernels
   uint32_t busy = 0;
 };
 
@@ -163,7 +164,8 @@ static bool admit(im_server* sv, Slot& s, Ticket* t) {
       st = celf_alloc(g, m, t->K, c->tune.celf_width, &cb);
       if (st == IM_OK) {
         s.scratch = cb.base;
-        celf_enqueue(c, &cb, s.stream);
+        const uint64_t words = (uint64_t)g->n * m->Rs;
+        celf_enqueue(c, &cb, s.stream, words >= sv->persistent_min_words);
         const size_t off = 256 + ((size_t)t->K * 4 + 255) / 256 * 256;
         if (!ensure_host(s, off + (size_t)t->K * 8)) {
           st = fail(IM_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
@@ -299,6 +301,9 @@ extern "C" im_status im_server_create(im_ctx* c, const im_server_config* cfg, im
   if (n > 64) return fail(IM_ERR_INVALID_ARG, "at most 64 slots");
   im_server* sv = new im_server();
   sv->ctx = c;
+  if (cfg)
+    sv->persistent_min_words = cfg->persistent_min_mwords == 0xFFFFFFFFu ? ~0ull
+                                                                        : (uint64_t)cfg->persistent_min_mwords << 20;
   sv->slots.resize(n);
   for (Slot& s : sv->slots) {
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||

@@ -53,16 +53,20 @@ def _alone(ctx, Gs, q):
     return (list(seeds), list(marg), cover)
 
 
-def test_server_results_alone_equal_mixed(gpu_ctx):
+@pytest.mark.parametrize("persistent_min_mwords", [0, 0xFFFFFFFF])
+def test_server_results_alone_equal_mixed(gpu_ctx, persistent_min_mwords):
+    # 0 (default): every selection runs the persistent kernel, which holds
+    # back the other slots; 0xFFFFFFFF: every selection runs the per-step
+    # kernels beside the other slots
     graphs = _graphs()
     qs = _queries(graphs)
-    announce(f"server mix of {len(qs)} queries")
+    announce(f"server mix of {len(qs)} queries, persistent_min_mwords={persistent_min_mwords}")
     Gs = [P.Graph.from_csr(gpu_ctx, g) for g in graphs]
     try:
         alone = [_alone(gpu_ctx, Gs, q) for q in qs]
         for G in Gs:
             G.drop_memo()
-        srv = P.Server(gpu_ctx, slots=4)
+        srv = P.Server(gpu_ctx, slots=4, persistent_min_mwords=persistent_min_mwords)
         try:
             tickets = []
             for kind, gi, p, R, s, arg in qs:
