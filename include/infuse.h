@@ -191,11 +191,11 @@ im_status im_select_seeds_direct(im_graph *g, uint32_t K, uint32_t *seeds, int64
 /* Copies component labels of simulations first_sample .. first_sample +
  * n_samples - 1 for every vertex into host[n][n_samples] (vertex-major).
  * Errors: IM_ERR_INVALID_ARG when the range exceeds R. */
-im_status im_copy_labels(im_graph *g, int32_t *host, uint32_t first_sample, uint32_t n_samples);
+im_status im_copy_labels(im_graph *g, int32_t *host, uint64_t first_sample, uint32_t n_samples);
 
 /* Copies the component size of every (vertex, simulation) pair for the same
  * range, host[n][n_samples]. */
-im_status im_copy_sizes(im_graph *g, int32_t *host, uint32_t first_sample, uint32_t n_samples);
+im_status im_copy_sizes(im_graph *g, int32_t *host, uint64_t first_sample, uint32_t n_samples);
 
 /* Copies the initial gains mg_v (int64[n], Algorithm 5) to the host. */
 im_status im_copy_gains0(im_graph *g, int64_t *host);

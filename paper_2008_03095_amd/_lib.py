@@ -71,8 +71,8 @@ SIGNATURES = {
     "im_estimate_sigma_direct": (C.c_int, [vp, vp, u32, P(i64), P(dbl), P(u32)]),
     "im_estimate_sigma_noalloc": (C.c_int, [vp, vp, u32, P(i64), P(dbl)]),
     "im_select_seeds_direct": (C.c_int, [vp, u32, vp, vp, P(i64)]),
-    "im_copy_labels": (C.c_int, [vp, vp, u32, u32]),
-    "im_copy_sizes": (C.c_int, [vp, vp, u32, u32]),
+    "im_copy_labels": (C.c_int, [vp, vp, u64, u32]),
+    "im_copy_sizes": (C.c_int, [vp, vp, u64, u32]),
     "im_copy_gains0": (C.c_int, [vp, vp]),
     "im_graph_n": (u32, [vp]),
     "im_graph_nnz": (u64, [vp]),

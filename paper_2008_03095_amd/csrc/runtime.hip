@@ -1526,10 +1526,10 @@ extern "C" im_status im_last_search_stats(const im_graph* g, uint64_t* out4) {
   return IM_OK;
 }
 
-static im_status export_range(im_graph* g, int32_t* host, uint32_t first, uint32_t cnt, int mode) {
+static im_status export_range(im_graph* g, int32_t* host, uint64_t first, uint32_t cnt, int mode) {
   if (!g) return fail(IM_ERR_INVALID_ARG, "NULL graph");
   if (!g->params_set) return fail(IM_ERR_INVALID_ARG, "im_set_params has not been called");
-  if ((uint64_t)first + cnt > g->R) return fail(IM_ERR_INVALID_ARG, "sample range exceeds R");
+  if (first > g->R || cnt > g->R - first) return fail(IM_ERR_INVALID_ARG, "sample range exceeds R");
   if (cnt == 0) return IM_OK;
   if (!host) return fail(IM_ERR_INVALID_ARG, "NULL output");
   im_ctx* c = g->ctx;
@@ -1547,7 +1547,7 @@ static im_status export_range(im_graph* g, int32_t* host, uint32_t first, uint32
   const MemoView mv = m->view(g);
   for (uint32_t v0 = 0; v0 < g->n && s == IM_OK; v0 += vchunk) {
     const uint32_t nv = std::min(vchunk, g->n - v0);
-    launch_export(mv, m->pos, first, cnt, v0, nv, mode, static_cast<int32_t*>(buf), c->stream);
+    launch_export(mv, m->pos, (uint32_t)first, cnt, v0, nv, mode, static_cast<int32_t*>(buf), c->stream);
     hipError_t e = hipMemcpyAsync(host + (uint64_t)v0 * cnt, buf, (size_t)nv * cnt * 4,
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1558,11 +1558,11 @@ static im_status export_range(im_graph* g, int32_t* host, uint32_t first, uint32
   return s;
 }
 
-extern "C" im_status im_copy_labels(im_graph* g, int32_t* host, uint32_t first, uint32_t n_samples) {
+extern "C" im_status im_copy_labels(im_graph* g, int32_t* host, uint64_t first, uint32_t n_samples) {
   return export_range(g, host, first, n_samples, 0);
 }
 
-extern "C" im_status im_copy_sizes(im_graph* g, int32_t* host, uint32_t first, uint32_t n_samples) {
+extern "C" im_status im_copy_sizes(im_graph* g, int32_t* host, uint64_t first, uint32_t n_samples) {
   return export_range(g, host, first, n_samples, 1);
 }
 
