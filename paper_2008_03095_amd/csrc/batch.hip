@@ -188,7 +188,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
         CelfBuffers& cb = cbs[sel[k]];
         const uint32_t gb = shaped ? first[k + 1] - first[k] : 1;
         pcelf_fill_job(hjobs.data() + k * jb, cb.v, cb.pscratch, cb.blist, gb, c->tune.celf_round0,
-                       c->profiling >= 2);
+                       pcelf_prof_bits(c));
       }
       std::memcpy(hjobs.data() + jb * nj, first.data(), fb);
       if (ctx_alloc(c, hjobs.size(), &djobs) == IM_OK &&

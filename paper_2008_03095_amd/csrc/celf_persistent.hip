@@ -76,7 +76,8 @@ struct PCelfJob {
   PCelfScratch* x;
   uint32_t* blist;   // [n] bulk candidates
   uint32_t w0;       // candidates of the first round of a step
-  uint32_t prof;     // 1: keep the phase clock (each reading is a scalar memory access)
+  uint32_t prof;     // bit 0: keep the phase clock (each reading is a scalar memory
+                     // access); bit 1: count listed tiles and gathers (loads rows again)
 };
 
 // The workgroups that run one selection together: their number and this
@@ -88,6 +89,16 @@ struct Grp {
 
 __device__ inline uint32_t p_uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline void p_wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Workgroup barrier for LDS data only: waits for the wave's LDS (and scalar)
+// operations, not its global ones, so global loads, stores and atomics
+// issued before it stay in flight (the pool routines touch LDS only; every
+// global write a later reader depends on is complete at the next grid
+// barrier, which waits for all of them).
+__device__ inline void p_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 // Global-memory accessors.  The buffers reach this kernel through a job
 // record in memory, so the compiler cannot prove their address space and
 // would emit flat instructions, which also hold the LDS wait counter; the
@@ -211,11 +222,11 @@ __device__ uint64_t block_max(PoolLds& L, uint64_t v) {
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   v = p_wmax(v);
   if (lane == 0) L.wmax[wv] = v;
-  __syncthreads();
+  p_lds_sync();
   uint64_t m = 0;
 #pragma unroll
   for (uint32_t i = 0; i < kPBlock / 64; ++i) m = L.wmax[i] > m ? L.wmax[i] : m;
-  __syncthreads();
+  p_lds_sync();
   return m;
 }
 
@@ -437,7 +448,7 @@ __device__ void lds_sort_desc(uint64_t* key, uint32_t* id, uint32_t cnt) {
           }
         }
       }
-      __syncthreads();
+      p_lds_sync();
     }
   }
 }
@@ -469,7 +480,7 @@ __device__ void f_best(PoolLds& L) {
   best = block_max(L, best);
   for (uint32_t i = threadIdx.x; i < nf; i += kPBlock)
     if (L.fkey[i] == best) L.fbest = i;
-  __syncthreads();
+  p_lds_sync();
 }
 
 // Restale of at most 64 F entries.  Wavefront 0 ranks F across its lanes
@@ -497,7 +508,7 @@ __device__ void pool_restale_small(PoolLds& L, uint32_t nf, uint32_t head, uint3
     fpos = l < nf ? rank + c : kPool;
   }
   clk.lap(PClock::kSort);
-  __syncthreads();
+  p_lds_sync();
   constexpr uint32_t kR = kPool / kPBlock;
   uint64_t k[kR];
   uint32_t v[kR], sh[kR];
@@ -517,7 +528,7 @@ __device__ void pool_restale_small(PoolLds& L, uint32_t nf, uint32_t head, uint3
 #pragma unroll
     for (uint32_t j = 0; j < kR; ++j) sh[j] += probe[j] <= threadIdx.x + j * kPBlock ? step : 0u;
   }
-  __syncthreads();
+  p_lds_sync();
 #pragma unroll
   for (uint32_t j = 0; j < kR; ++j) {
     const uint32_t i = threadIdx.x + j * kPBlock;
@@ -535,7 +546,7 @@ __device__ void pool_restale_small(PoolLds& L, uint32_t nf, uint32_t head, uint3
     L.head = 0;
     L.nf = 0;
   }
-  __syncthreads();
+  p_lds_sync();
   clk.lap(PClock::kMove);
 }
 
@@ -553,7 +564,7 @@ __device__ void pool_restale(PoolLds& L, PClock& clk) {
     L.fkey[i] = 0;
     L.fid[i] = kInvalid;
   }
-  __syncthreads();
+  p_lds_sync();
   lds_sort_desc(L.fkey, L.fid, np2);
   // merge by rank into registers, then write S
   constexpr uint32_t kR = kPool / kPBlock;
@@ -571,7 +582,7 @@ __device__ void pool_restale(PoolLds& L, PClock& clk) {
     v[kR + j] = fin ? L.fid[i] : kInvalid;
     pos[kR + j] = fin ? i + count_greater(L.skey + head, ns, k[kR + j]) : kPool;
   }
-  __syncthreads();
+  p_lds_sync();
 #pragma unroll
   for (uint32_t j = 0; j < 2 * kR; ++j)
     if (pos[j] < kPool) {
@@ -583,7 +594,7 @@ __device__ void pool_restale(PoolLds& L, PClock& clk) {
     L.head = 0;
     L.nf = 0;
   }
-  __syncthreads();
+  p_lds_sync();
 }
 
 // Rebuilds the pool from the keys of all unselected vertices.
@@ -862,7 +873,7 @@ __device__ bool bulk_eval(const PCelfJob& a, const Grp& G, PoolLds& L, uint32_t 
           p_take_tiles(sparse, ntiles, nrem, npos, nt);
         p_load_list(c, more ? v : vn, nt, lane, nxt, nword);
         sum += p_sum_list(c, v, ct, lane, cur, cword);
-        if (a.prof)
+        if (a.prof & 2u)
 #pragma unroll
           for (int b = 0; b < kBulkB; ++b)
             if (ct[b] != kInvalid) p_count_tile(c, v, ct[b], lane, ptiles, pcols);
@@ -896,7 +907,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   uint64_t evals = 0;
   uint64_t ptiles = 0, pcols = 0;  // profiling work counts of this wavefront
   PClock clk;
-  clk.start(a.prof != 0);
+  clk.start((a.prof & 1u) != 0);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   if (threadIdx.x == 0) L.lead = kInvalid;
   if (!pool_rebuild(a, G, L, s, gen, clk)) return;
@@ -931,7 +942,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       // measured each one's overlap with id
       const bool ahead = L.lead == id;
       clk.lap(PClock::kCommit);
-      __syncthreads();
+      p_lds_sync();  // the marking atomics stay in flight through the pool work
       if (threadIdx.x == 0) {  // drop the seed from F
         const uint32_t b = L.fbest;
         L.fkey[b] = L.fkey[nf - 1];
@@ -940,7 +951,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         L.nf = nf - 1;
         L.lead = kInvalid;
       }
-      __syncthreads();
+      p_lds_sync();
       if (ahead) {
         // the keys for the next step are exact: F stays fresh, S unchanged
         for (uint32_t i = threadIdx.x; i + 1 < nf; i += kPBlock) {
@@ -951,7 +962,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
             st32(&c.iter[L.fid[i]], s + 1);
           }
         }
-        __syncthreads();
+        p_lds_sync();
         f_best(L);
         ++clk.ahead;
       } else {
@@ -990,7 +1001,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         const uint32_t u = L.sid[head + w];
         uint64_t ov;
         const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, ahead ? lead : u, ov));
-        if (a.prof) p_count_tile(c, u, t, lane, ptiles, pcols);
+        if (a.prof & 2u) p_count_tile(c, u, t, lane, ptiles, pcols);
         ov = ahead ? p_wsum(ov) : 0;
         if (lane == 0 && part) g_add64(&g[w], part);
         if (lane == 0 && ov) g_add64(&g[kMaxCand + w], ov);
@@ -1045,7 +1056,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     }
     just_rebuilt = true;
   }
-  if (a.prof && lane == 0) {
+  if ((a.prof & 2u) && lane == 0) {
     g_add64(&x->work[0], ptiles);
     g_add64(&x->work[1], pcols);
   }
@@ -1130,13 +1141,13 @@ static uint32_t pcelf_w0(const CelfView& c, uint32_t group_blocks, uint32_t roun
 }
 
 void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* blist, uint32_t group_blocks,
-                    uint32_t round0, bool prof) {
+                    uint32_t round0, uint32_t prof) {
   PCelfJob* j = static_cast<PCelfJob*>(host_job);
   j->c = c;
   j->x = static_cast<PCelfScratch*>(scratch);
   j->blist = blist;
   j->w0 = pcelf_w0(c, group_blocks, round0);
-  j->prof = prof ? 1u : 0u;
+  j->prof = prof;
 }
 
 hipError_t launch_celf_persistent(const void* jobs, uint32_t njobs, uint32_t grid, uint32_t group_blocks,

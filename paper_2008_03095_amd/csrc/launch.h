@@ -49,9 +49,9 @@ uint32_t pcelf_grid(int device);
 uint64_t pcelf_job_bytes();
 // Writes the description of one selection (for a group of group_blocks
 // workgroups) into host memory of pcelf_job_bytes() bytes.
+// prof: bit 0 phase clock, bit 1 work counts (listed tiles and gathers)
 void pcelf_fill_job(void* host_job, const CelfView& c, void* scratch, uint32_t* blist, uint32_t group_blocks,
-                    uint32_t round0,
-                    bool prof);
+                    uint32_t round0, uint32_t prof);
 // jobs: device array of njobs descriptions.  first: device prefix sums of
 // workgroups per description (njobs + 1 entries, each at least one), or
 // nullptr for grid / group_blocks equal groups taking descriptions in turn.

@@ -72,6 +72,7 @@ uint64_t memo_bytes(const im_graph* g, uint32_t R);
 Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed);
 im_status memo_alloc(im_graph* g, double p, uint32_t R, uint32_t seed, Memo** out);
 uint32_t hub_chunk_tiles(const im_ctx* c);
+uint32_t pcelf_prof_bits(const im_ctx* c);
 bool memo_matches(const im_graph* g, const Memo* m, double p, uint32_t R, uint32_t seed);
 im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream_t st, Memo** out);
 im_status memo_acquire(im_graph* g, Memo** out);

@@ -264,6 +264,10 @@ Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
 }
 
 // Tiles per hook_hubs wavefront from the context's cc_chunk (columns).
+// Profiling bits of a persistent CELF launch: the phase clock from level 2,
+// the work counts (listed tiles, gathers) at level 3.
+uint32_t pcelf_prof_bits(const im_ctx* c) { return (c->profiling >= 2 ? 1u : 0u) | (c->profiling >= 3 ? 2u : 0u); }
+
 uint32_t hub_chunk_tiles(const im_ctx* c) { return std::max(1u, std::min(32u, c->tune.cc_chunk / kTile)); }
 
 // Allocates the memo of (p, R, seed), registers it with the graph and
@@ -583,7 +587,7 @@ void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st, bool persistent_ok
   celf_prepare(cb, st);
   if (persistent_ok && c->tune.celf_mode == 1 && c->coop_grid) {
     pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0,
-                   c->profiling >= 2);
+                   pcelf_prof_bits(c));
     if (hipMemcpyAsync(cb->pjob, cb->hjob, pcelf_job_bytes(), hipMemcpyHostToDevice, st) == hipSuccess &&
         celf_launch_persistent(c, cb->pjob, 1, c->coop_grid, nullptr, st)) {
       cb->persistent = true;
@@ -697,8 +701,9 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
       c->kstats["celf.lookahead_commits"].first += pr[15];  // steps decided without a round
     }
     uint64_t wk[2];
-    if (hipMemcpy(wk, static_cast<char*>(cb->pscratch) + pcelf_work_offset(), sizeof(wk), hipMemcpyDeviceToHost) ==
-        hipSuccess) {
+    if (c->profiling >= 3 &&
+        hipMemcpy(wk, static_cast<char*>(cb->pscratch) + pcelf_work_offset(), sizeof(wk), hipMemcpyDeviceToHost) ==
+            hipSuccess) {
       std::lock_guard<std::recursive_mutex> lk(c->mu);
       c->kstats["celf.listed_tiles"].first += wk[0];  // listed (candidate, tile) pairs evaluated
       c->kstats["celf.gathers"].first += wk[1];       // their non-singleton columns
