@@ -104,7 +104,9 @@ __device__ inline void hook_rows_body(const GraphView& g, const MemoView& m, uin
   if (v >= g.n) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t beg = uni(g.row_ptr[v]), end = uni(g.row_ptr[v + 1]);
-  if (end - beg > (uint32_t)kWave) return;  // k_hook_hubs
+  // no edge: the vertex is a singleton in every column, its mask words stay
+  // as cleared and its memo row is never read
+  if (end == beg || end - beg > (uint32_t)kWave) return;  // more than kWave: k_hook_hubs
   const uint32_t split = uni(g.split[v]);
   const bool has = beg + lane < end;
   uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;

@@ -2,7 +2,7 @@
 
 import numpy as np
 
-from workloads import splitmix64_stream
+from workloads import chung_lu, from_edge_list, splitmix64_stream
 
 
 def digest_weights(n: int) -> np.ndarray:
@@ -41,3 +41,18 @@ def gains_checksum(g0: np.ndarray) -> str:
     w = splitmix64_stream(0x6A1, 0, g0.size) | np.uint64(1)
     with np.errstate(over="ignore"):
         return "%016x" % int((g0.astype(np.uint64) * w).sum(dtype=np.uint64))
+
+
+def hub_mix_graph(seed):
+    """Hub rows of very different lengths in one graph: vertex n-1 joined to
+    0 .. 4,999 (a row of 5,000 slots, nearly all of them smaller neighbours:
+    thousands of unions per column), vertex 3 to 1,000 .. 3,999 (3,000 slots,
+    nearly all larger), vertex 4,500 to 100 random vertices, over a Chung-Lu
+    background (its own hubs of a few hundred slots)."""
+    n = 6000
+    bg = chung_lu(n, 15000, 2.2, seed)
+    rows = np.repeat(np.arange(n), bg.degrees())
+    rng = np.random.default_rng(seed)
+    us = [rows, np.full(5000, n - 1), np.full(3000, 3), np.full(100, 4500)]
+    vs = [bg.col.astype(np.int64), np.arange(5000), np.arange(1000, 4000), rng.integers(0, n, 100)]
+    return from_edge_list(n, np.concatenate(us), np.concatenate(vs))

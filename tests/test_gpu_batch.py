@@ -16,6 +16,7 @@ import pytest
 import oracle
 import paper_2008_03095_amd as P
 from tests.conftest import announce
+from tests.helpers import hub_mix_graph
 from workloads import chung_lu, from_edge_list, star_graph, trivalency_p, uniform_p
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +35,8 @@ def _specs():
     g_tri.p_slot = trivalency_p(g_tri, 81)
     g_uni = chung_lu(900, 4000, 2.1, 82)
     g_uni.p_slot = uniform_p(g_uni, 82)
+    g_hub_tri = hub_mix_graph(88)
+    g_hub_tri.p_slot = trivalency_p(g_hub_tri, 88)
     return [
         # (graph, p, R, hash seed, K)
         (chung_lu(1500, 7000, 2.1, 80), 0.06, 512, 80, 15),   # hubs, uniform p
@@ -43,6 +46,8 @@ def _specs():
         (chung_lu(600, 2000, 2.5, 84), 0.04, 5000, 84, 7),    # R above the set-up sort's size
         (chung_lu(500, 1500, 2.5, 85), 0.0, 256, 85, 4),      # p = 0: all singletons
         (from_edge_list(1, [], []), 0.3, 64, 86, 1),          # one vertex, no edge
+        (hub_mix_graph(89), 0.02, 1024, 89, 6),               # hub rows of 100 to 5,000 slots
+        (g_hub_tri, 0.0, 300, 88, 6),                         # the same, per-edge p, ragged R
     ]
 
 

@@ -10,7 +10,7 @@ import pytest
 import oracle
 import paper_2008_03095_amd as P
 from tests.conftest import announce
-from tests.helpers import digest_weights, label_digests
+from tests.helpers import digest_weights, hub_mix_graph, label_digests
 from workloads import (chung_lu, from_edge_list, make_config, normal_p, path_graph, random_small_graph,
                        star_graph, trivalency_p, uniform_p)
 
@@ -128,6 +128,20 @@ def test_per_slot_zero_and_one(gpu_ctx):
         ps[j] = und_key[k]
     g.p_slot = ps
     _full_check(gpu_ctx, g, 0.0, 200, 9, 5, sigma_sets=[[0, 1]], name="p_slot {0,1,...}")
+
+
+@pytest.mark.parametrize("probs", ["uniform", "trivalency"])
+@pytest.mark.parametrize("R", [300, 1024])
+def test_hub_rows_of_several_lengths(gpu_ctx, probs, R):
+    g = hub_mix_graph(91)
+    deg = g.degrees()
+    assert deg.max() >= 5000 and int(((deg > 64) & (deg < 1000)).sum()) > 10
+    p = 0.02
+    if probs == "trivalency":
+        g.p_slot = trivalency_p(g, 91)
+        p = 0.0
+    _full_check(gpu_ctx, g, p, R, 91, 10, sigma_sets=[[g.n - 1, 3], [0, 1, 4500]],
+                name=f"hub mix {probs} R={R}")
 
 
 def test_c2_full(gpu_ctx):
