@@ -303,9 +303,10 @@ im_status im_memo_stats(im_graph *g, uint64_t *out4);
  * resident are built together: one launch per labelling phase (set-up,
  * hooks, work lists, unions, flatten, count, initial gains) over all of
  * them, each launch's workgroups divided among the graphs by prefix sums of
- * per-graph shapes.  Then all selections run in one launch of the
- * persistent CELF kernel, each graph on a group of workgroups sized by its
- * memo.  seeds[i] / marginal[i] point to caller arrays of K[i] entries;
+ * per-graph shapes.  Then all selections are set up by one launch and run
+ * in one launch of the persistent CELF kernel, each graph on a group of
+ * workgroups sized by its memo; their results come back in one download.
+ * seeds[i] / marginal[i] point to caller arrays of K[i] entries;
  * cover[i] receives the cover count.  All graphs must share the context and
  * appear once.  Results are identical to calling im_select_seeds per
  * graph.  Errors: IM_ERR_INVALID_ARG for a graph of another context, a

@@ -16,6 +16,8 @@
 
 using namespace infuse;
 
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 static const char* const kPhaseNames[kBatchPhases] = {"batch.prep",  "batch.hook",    "batch.hook_hubs",
                                                       "batch.lists", "batch.link",    "batch.link_hubs",
                                                       "batch.flatten", "batch.count", "batch.gain0"};
@@ -155,67 +157,122 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
   if (!todo.empty()) st = batch_build(c, graphs, todo, memos, &dbuild);
   for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
     if (K[i]) st = celf_alloc(graphs[i], memos[i], K[i], c->tune.celf_width, &cbs[i]);
+  // the selections: set up in one launch, run in one persistent launch (or
+  // the per-step kernels), their results packed by one launch and
+  // downloaded with one copy; the descriptions of all launches go up in one
+  // copy
   void* djobs = nullptr;
-  std::vector<unsigned char> hjobs;
-  if (st == IM_OK) {
-    std::vector<uint32_t> sel;
-    for (uint32_t i = 0; i < ng; ++i)
-      if (K[i]) {
-        celf_prepare(&cbs[i], c->stream);
-        sel.push_back(i);
+  std::vector<uint32_t> sel;
+  for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
+    if (K[i]) sel.push_back(i);
+  if (st == IM_OK && !sel.empty()) {
+    const uint32_t nj = (uint32_t)sel.size();
+    std::vector<CelfBatchJob> bj(nj);
+    std::vector<uint32_t> pfirst(nj + 1, 0);
+    uint64_t rec_bytes = 0;
+    for (uint32_t k = 0; k < nj; ++k) {
+      CelfBuffers& cb = cbs[sel[k]];
+      CelfBatchJob& J = bj[k];
+      J.v = cb.v;
+      J.pscratch = static_cast<uint32_t*>(cb.pscratch);
+      J.perr = reinterpret_cast<const uint32_t*>(static_cast<char*>(cb.pscratch) + pcelf_err_offset());
+      J.scratch_words = (uint32_t)(pcelf_scratch_bytes() / 4);
+      const uint64_t cw = (uint64_t)cb.v.m.n * cb.v.cwords;
+      J.cov_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(1024, (cw + 4095) / 4096));
+      J.init_blocks = (cb.v.m.n + 255) / 256;
+      J.rec_off = (uint32_t)rec_bytes;
+      rec_bytes += 8 + sizeof(CelfState) + (((uint64_t)cb.v.K * 4 + 7) & ~7ull) + (uint64_t)cb.v.K * 8;
+      const uint64_t f = (uint64_t)pfirst[k] + J.cov_blocks + J.init_blocks + 1;
+      if (f > 0x7FFFFFFFull || rec_bytes > 0xFFFFFFFFull) {
+        st = fail(IM_ERR_INVALID_ARG, "batched selection: too many selections for one call");
+        break;
       }
-    bool launched = false;
-    if (!sel.empty() && c->tune.celf_mode == 1 && c->coop_grid) {
-      const uint32_t nj = (uint32_t)sel.size(), grid = c->coop_grid;
-      // workgroups per selection: one each, the rest in proportion to the
-      // memo words (n * ntiles); with more selections than workgroups, one
-      // workgroup each, taking selections in turn
-      std::vector<uint32_t> first(nj + 1, 0);
-      const bool shaped = nj <= grid;
-      if (shaped) {
-        double wsum = 0;
-        for (uint32_t i : sel) wsum += (double)cbs[i].v.m.n * cbs[i].v.m.ntiles;
+      pfirst[k + 1] = (uint32_t)f;
+    }
+    const bool coop = c->tune.celf_mode == 1 && c->coop_grid;
+    // workgroups of the persistent launch per selection: one each, the rest
+    // in proportion to the memo words (n * ntiles); with more selections than
+    // workgroups, one workgroup each, taking selections in turn
+    const uint32_t grid = c->coop_grid;
+    std::vector<uint32_t> first(nj + 1, 0);
+    const bool shaped = coop && nj <= grid;
+    if (shaped) {
+      double wsum = 0;
+      for (uint32_t i : sel) wsum += (double)cbs[i].v.m.n * cbs[i].v.m.ntiles;
+      for (uint32_t k = 0; k < nj; ++k) {
+        const CelfView& v = cbs[sel[k]].v;
+        const uint32_t extra = (uint32_t)((double)(grid - nj) * ((double)v.m.n * v.m.ntiles) / wsum);
+        first[k + 1] = first[k] + 1 + extra;
+      }
+    }
+    // one device block: prepare jobs | their prefix | persistent jobs | their
+    // prefix | packed records
+    const size_t jb = pcelf_job_bytes();
+    const size_t o_pf = align256(sizeof(CelfBatchJob) * nj);
+    const size_t o_pj = o_pf + align256((nj + 1) * 4);
+    const size_t o_fi = o_pj + (coop ? align256(jb * nj) : 0);
+    const size_t o_rec = o_fi + (coop ? align256((nj + 1) * 4) : 0);
+    std::vector<unsigned char> up, rec;
+    if (st == IM_OK) {
+      up.assign(o_rec, 0);
+      rec.resize(rec_bytes);
+      std::memcpy(up.data(), bj.data(), sizeof(CelfBatchJob) * nj);
+      std::memcpy(up.data() + o_pf, pfirst.data(), (nj + 1) * 4);
+      if (coop) {
         for (uint32_t k = 0; k < nj; ++k) {
-          const CelfView& v = cbs[sel[k]].v;
-          const uint32_t extra = (uint32_t)((double)(grid - nj) * ((double)v.m.n * v.m.ntiles) / wsum);
-          first[k + 1] = first[k] + 1 + extra;
+          CelfBuffers& cb = cbs[sel[k]];
+          const uint32_t gb = shaped ? first[k + 1] - first[k] : 1;
+          pcelf_fill_job(up.data() + o_pj + k * jb, cb.v, cb.pscratch, cb.blist, gb, c->tune.celf_round0,
+                         pcelf_prof_bits(c));
+        }
+        std::memcpy(up.data() + o_fi, first.data(), (nj + 1) * 4);
+      }
+      st = ctx_alloc(c, o_rec + rec_bytes, &djobs);
+    }
+    if (st == IM_OK) {
+      char* d = static_cast<char*>(djobs);
+      const CelfBatchJob* dbj = reinterpret_cast<const CelfBatchJob*>(d);
+      if (hipMemcpyAsync(d, up.data(), o_rec, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        st = fail(IM_ERR_DEVICE, "batched selection: upload failed");
+      } else {
+        launch_celf_prepare_batch(dbj, reinterpret_cast<const uint32_t*>(d + o_pf), nj, pfirst[nj], c->stream);
+        bool launched = false;
+        if (coop && celf_launch_persistent(c, d + o_pj, nj, 1,
+                                           shaped ? reinterpret_cast<const uint32_t*>(d + o_fi) : nullptr,
+                                           c->stream)) {
+          launched = true;
+          for (uint32_t i : sel) cbs[i].persistent = true;
+        }
+        (void)hipGetLastError();
+        if (!launched)
+          for (uint32_t i : sel) celf_enqueue_steps(c, &cbs[i], c->stream);
+        launch_celf_collect_batch(dbj, nj, reinterpret_cast<unsigned char*>(d + o_rec), c->stream);
+        if (hipMemcpyAsync(rec.data(), d + o_rec, rec_bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+          hipError_t e = hipGetLastError();
+          st = fail(IM_ERR_DEVICE, "batched selection failed on the device: %s", hipGetErrorString(e));
         }
       }
-      const size_t jb = pcelf_job_bytes();
-      const size_t fb = (nj + 1) * sizeof(uint32_t);
-      hjobs.resize(jb * nj + fb);
-      for (uint32_t k = 0; k < nj; ++k) {
-        CelfBuffers& cb = cbs[sel[k]];
-        const uint32_t gb = shaped ? first[k + 1] - first[k] : 1;
-        pcelf_fill_job(hjobs.data() + k * jb, cb.v, cb.pscratch, cb.blist, gb, c->tune.celf_round0,
-                       pcelf_prof_bits(c));
-      }
-      std::memcpy(hjobs.data() + jb * nj, first.data(), fb);
-      if (ctx_alloc(c, hjobs.size(), &djobs) == IM_OK &&
-          hipMemcpyAsync(djobs, hjobs.data(), hjobs.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
-          celf_launch_persistent(c, djobs, nj, 1,
-                                 shaped ? reinterpret_cast<const uint32_t*>(static_cast<char*>(djobs) + jb * nj)
-                                        : nullptr,
-                                 c->stream)) {
-        launched = true;
-        for (uint32_t i : sel) cbs[i].persistent = true;
-      }
-      (void)hipGetLastError();
     }
-    if (!launched)
-      for (uint32_t i : sel) celf_enqueue_steps(c, &cbs[i], c->stream);
-    for (uint32_t i = 0; i < ng && st == IM_OK; ++i) {
-      if (!K[i]) {
-        if (cover) cover[i] = 0;
-        continue;
-      }
+    for (uint32_t k = 0; k < nj && st == IM_OK; ++k) {
+      const uint32_t i = sel[k];
+      const unsigned char* r = rec.data() + bj[k].rec_off;
+      const uint32_t Ki = K[i];
+      uint32_t perr;
+      CelfState hs;
+      std::memcpy(&perr, r, 4);
+      std::memcpy(&hs, r + 8, sizeof(CelfState));
+      std::memcpy(seeds[i], r + 8 + sizeof(CelfState), (size_t)Ki * 4);
+      std::memcpy(marginal[i], r + 8 + sizeof(CelfState) + (((uint64_t)Ki * 4 + 7) & ~7ull), (size_t)Ki * 8);
       int64_t cv = 0;
       uint64_t ev = 0;
-      st = celf_collect(c, &cbs[i], c->stream, seeds[i], marginal[i], &cv, &ev);
+      st = celf_finish(c, &cbs[i], perr, hs, marginal[i], &cv, &ev);
       if (cover) cover[i] = cv;
       graphs[i]->last_evals = ev;
     }
   }
+  for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
+    if (!K[i] && cover) cover[i] = 0;
   if (st != IM_OK) (void)hipStreamSynchronize(c->stream);
   if (djobs) ctx_free(c, djobs);
   if (dbuild) ctx_free(c, dbuild);

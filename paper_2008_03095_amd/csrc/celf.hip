@@ -372,8 +372,8 @@ __global__ void __launch_bounds__(256) k_celf_bulk(CelfView c) {
   commit_block(c, k_sh);
 }
 
-__global__ void k_celf_init(CelfView c) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Key (initial gain, stamp 0) of vertex i; i = 0 also clears the state.
+__device__ inline void celf_init_at(const CelfView& c, uint64_t i) {
   if (i < c.m.n) {
     c.key[i] = make_key(c, (uint64_t)c.m.g0[i], (uint32_t)i);
     c.iter[i] = 0;
@@ -384,9 +384,66 @@ __global__ void k_celf_init(CelfView c) {
   }
 }
 
+__global__ void k_celf_init(CelfView c) { celf_init_at(c, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+
+// Set-up of many selections in one launch: per selection (found by binary
+// search in the prefix sums `first` of its workgroups), cov_blocks
+// workgroups clear its coverage bits, init_blocks set its keys, and one
+// clears the persistent kernel's state.
+__global__ void __launch_bounds__(256) k_celf_prepare_batch(const CelfBatchJob* jobs, const uint32_t* first,
+                                                            uint32_t njobs) {
+  uint32_t lo = 0, hi = njobs;  // the last lo with first[lo] <= blockIdx.x
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const CelfBatchJob& J = jobs[lo];
+  uint32_t local = blockIdx.x - first[lo];
+  if (local < J.cov_blocks) {
+    const uint64_t words = (uint64_t)J.v.m.n * J.v.cwords;
+    for (uint64_t i = (uint64_t)local * blockDim.x + threadIdx.x; i < words; i += (uint64_t)J.cov_blocks * blockDim.x)
+      J.v.cov[i] = 0u;
+    return;
+  }
+  local -= J.cov_blocks;
+  if (local < J.init_blocks) {
+    celf_init_at(J.v, (uint64_t)local * blockDim.x + threadIdx.x);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < J.scratch_words; i += blockDim.x) J.pscratch[i] = 0u;
+}
+
+// Packs the results of selection blockIdx.x into its record (one download
+// for all selections of a batched call).
+__global__ void __launch_bounds__(256) k_celf_collect_batch(const CelfBatchJob* jobs, unsigned char* out) {
+  const CelfBatchJob& J = jobs[blockIdx.x];
+  unsigned char* rec = out + J.rec_off;
+  const uint32_t K = J.v.K;
+  uint32_t* seeds = reinterpret_cast<uint32_t*>(rec + 8 + sizeof(CelfState));
+  int64_t* marg = reinterpret_cast<int64_t*>(rec + 8 + sizeof(CelfState) + (((uint64_t)K * 4 + 7) & ~7ull));
+  if (threadIdx.x == 0) {
+    *reinterpret_cast<uint64_t*>(rec) = *J.perr;
+    *reinterpret_cast<CelfState*>(rec + 8) = *J.v.st;
+  }
+  for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+    seeds[i] = J.v.seeds[i];
+    marg[i] = J.v.marginal[i];
+  }
+}
+
 // ---- launchers -------------------------------------------------------------
 
 uint32_t celf_topw_blocks(uint32_t n) { return (n + 4 * 64 * kTopPerLane - 1) / (4 * 64 * kTopPerLane); }
+
+void launch_celf_prepare_batch(const CelfBatchJob* jobs, const uint32_t* first, uint32_t njobs, uint32_t blocks,
+                               hipStream_t st) {
+  if (blocks) hipLaunchKernelGGL(k_celf_prepare_batch, dim3(blocks), dim3(256), 0, st, jobs, first, njobs);
+}
+
+void launch_celf_collect_batch(const CelfBatchJob* jobs, uint32_t njobs, unsigned char* out, hipStream_t st) {
+  if (njobs) hipLaunchKernelGGL(k_celf_collect_batch, dim3(njobs), dim3(256), 0, st, jobs, out);
+}
 
 void launch_celf_init(const CelfView& c, hipStream_t st) {
   hipLaunchKernelGGL(k_celf_init, dim3((c.m.n + 255) / 256), dim3(256), 0, st, c);

@@ -225,6 +225,20 @@ struct CelfView {
   CelfState* st;
 };
 
+// One selection of a batched call (im_batch_select): its set-up as
+// workgroup ranges of one launch, and where its results go in the packed
+// record array that is downloaded once.
+struct CelfBatchJob {
+  CelfView v;
+  uint32_t* pscratch;      // state of the persistent kernel, cleared
+  const uint32_t* perr;    // its error flag (inside pscratch)
+  uint32_t scratch_words;  // u32 words of pscratch
+  uint32_t cov_blocks;     // workgroups clearing the coverage bits
+  uint32_t init_blocks;    // workgroups setting keys and stamps (256 vertices each)
+  uint32_t rec_off;        // byte offset of the record: error flag (8 B), CelfState,
+                           // seeds (K x u32, padded to 8 B), marginal counts (K x i64)
+};
+
 inline uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace infuse

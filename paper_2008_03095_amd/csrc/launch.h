@@ -38,6 +38,11 @@ void launch_celf_init(const CelfView& c, hipStream_t st);
 void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 void launch_celf_topw(const CelfView& c, hipStream_t st);
 void launch_celf_eval(const CelfView& c, hipStream_t st);
+// many selections (im_batch_select): their set-up in one launch (`blocks`
+// = first[njobs]) and the packing of their results into the records at out
+void launch_celf_prepare_batch(const CelfBatchJob* jobs, const uint32_t* first, uint32_t njobs, uint32_t blocks,
+                               hipStream_t st);
+void launch_celf_collect_batch(const CelfBatchJob* jobs, uint32_t njobs, unsigned char* out, hipStream_t st);
 void launch_celf_bulk(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 
 // celf_persistent.hip

@@ -90,6 +90,10 @@ bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_
 void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st);
 im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
                        int64_t* marginal, int64_t* cover, uint64_t* evals);
+// The checks and totals of a finished selection from its downloaded error
+// flag, state and marginal counts (celf_collect, or a batched download).
+im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const CelfState& hs,
+                      const int64_t* marginal, int64_t* cover, uint64_t* evals);
 im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out);
 im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
                         void** scratch, unsigned long long** dev_out);

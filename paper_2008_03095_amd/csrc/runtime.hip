@@ -682,6 +682,12 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
     hipError_t e = hipGetLastError();
     return fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
   }
+  return celf_finish(c, cb, perr, hs, marginal, cover, evals);
+}
+
+im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const CelfState& hs,
+                      const int64_t* marginal, int64_t* cover, uint64_t* evals) {
+  const CelfView& v = cb->v;
   if (perr) return fail(IM_ERR_DEVICE, "persistent CELF kernel aborted (code %u)", perr);
   if (cb->persistent && c->profiling >= 2) {
     // phase clock of the persistent kernel: ticks of 10 ns per phase
