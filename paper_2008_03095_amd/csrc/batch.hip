@@ -7,6 +7,7 @@
 // which gives each graph its own group of workgroups, sized by the graph's
 // memo; one synchronisation at the end.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -191,17 +192,20 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     }
     const bool coop = c->tune.celf_mode == 1 && c->coop_grid;
     // workgroups of the persistent launch per selection: one each, the rest
-    // in proportion to the memo words (n * ntiles); with more selections than
+    // in proportion to the square root of the memo words (n * ntiles): the
+    // longest selection sets the launch's time, and a small graph's
+    // selection is not proportionally shorter (its evaluations are rounds
+    // of dependent loads whatever their number); with more selections than
     // workgroups, one workgroup each, taking selections in turn
     const uint32_t grid = c->coop_grid;
     std::vector<uint32_t> first(nj + 1, 0);
     const bool shaped = coop && nj <= grid;
     if (shaped) {
       double wsum = 0;
-      for (uint32_t i : sel) wsum += (double)cbs[i].v.m.n * cbs[i].v.m.ntiles;
+      for (uint32_t i : sel) wsum += std::sqrt((double)cbs[i].v.m.n * cbs[i].v.m.ntiles);
       for (uint32_t k = 0; k < nj; ++k) {
         const CelfView& v = cbs[sel[k]].v;
-        const uint32_t extra = (uint32_t)((double)(grid - nj) * ((double)v.m.n * v.m.ntiles) / wsum);
+        const uint32_t extra = (uint32_t)((double)(grid - nj) * std::sqrt((double)v.m.n * v.m.ntiles) / wsum);
         first[k + 1] = first[k] + 1 + extra;
       }
     }

@@ -90,3 +90,27 @@ def test_batch_rejects_a_repeated_graph(gpu_ctx):
         assert e.value.status == 1
     finally:
         G.free()
+
+
+def test_batch_more_selections_than_workgroups(gpu_ctx):
+    # 640 selections: more than the persistent grid's workgroups, so each
+    # workgroup runs several selections one after the other
+    from workloads import random_small_graph
+    specs = [(random_small_graph(12 + i % 20, 20 + i % 37, 500 + i), 0.3, 64, 500 + i, 1 + i % 4)
+             for i in range(640)]
+    announce(f"batch_select of {len(specs)} small graphs")
+    Gs = []
+    try:
+        for g, p, R, s, K in specs:
+            G = P.Graph.from_csr(gpu_ctx, g)
+            G.set_params(p, R, s)
+            Gs.append(G)
+        res = P.batch_select(gpu_ctx, Gs, [K for *_, K in specs])
+        for (g, p, R, s, K), (seeds, marg, cover) in zip(specs, res):
+            ref = oracle.run_memo(g, oracle.Sampler("hash", p=p, R=R, seed=s), K, threads=1)
+            assert list(seeds) == list(ref["seeds"]), (g.n, K, s)
+            assert list(marg) == list(ref["marginal"])
+            assert cover == ref["cover"]
+    finally:
+        for G in Gs:
+            G.free()
