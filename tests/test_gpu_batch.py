@@ -48,6 +48,7 @@ def _specs():
         (from_edge_list(1, [], []), 0.3, 64, 86, 1),          # one vertex, no edge
         (hub_mix_graph(89), 0.02, 1024, 89, 6),               # hub rows of 100 to 5,000 slots
         (g_hub_tri, 0.0, 300, 88, 6),                         # the same, per-edge p, ragged R
+        (chung_lu(700, 2500, 2.3, 90), 0.05, 9000, 90, 5),    # 36 tiles: two mask words per vertex
     ]
 
 

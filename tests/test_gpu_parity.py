@@ -144,6 +144,14 @@ def test_hub_rows_of_several_lengths(gpu_ctx, probs, R):
                 name=f"hub mix {probs} R={R}")
 
 
+@pytest.mark.parametrize("R", [8448, 9000, 20000])
+def test_more_than_32_tiles(gpu_ctx, R):
+    # R above 8,192 columns: more than one tile-mask word per vertex (33, 36
+    # and 79 tiles; the last two ragged)
+    g = chung_lu(800, 3000, 2.3, 55)
+    _full_check(gpu_ctx, g, 0.05, R, 55, 10, sigma_sets=[[0, 1, 2], list(range(0, 800, 7))], name=f"R={R}")
+
+
 def test_c2_full(gpu_ctx):
     w = make_config("c2")
     g = w.graphs[0]
@@ -261,6 +269,8 @@ CELF_CASES = {
     "path3000": (lambda: path_graph(3000), 0.9, 256, 9, 40),
     # ragged R (last tile partly used), zero-gain rounds towards the end
     "star500_R300": (lambda: star_graph(500), 0.3, 300, 4, 499),
+    # 36 tiles: two tile-mask words per vertex (the bulk pass's dense path)
+    "cl800_R9000": (lambda: chung_lu(800, 3000, 2.3, 56), 0.05, 9000, 56, 12),
 }
 
 
