@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -46,11 +47,19 @@ WORKLOADS = {
 }
 
 
+def code_tokens(text: str) -> str:
+    """The source text without comments and with whitespace runs folded, so
+    that an edit of a comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def roof_source_hash(sources=None) -> str:
     h = hashlib.sha256()
     for p in sources or ROOF_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -317,7 +326,7 @@ def directed_bench(args):
     # one more call, untimed, with the kernel clock and the search's work
     # counts on (both perturb the kernels a little: the level times of this
     # call are the roofline's)
-    ctx.set_profiling(1)
+    ctx.set_profiling(2)
     ctx.reset_kernel_stats()
     G.estimate_sigma_direct(S)
     torch.cuda.synchronize()
@@ -569,7 +578,10 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    ctx.set_profiling(2 if args.profile_celf else 1)
+    # the timed steps record events around the persistent CELF launch only
+    # (level 1), the roofline kernel; events around every kernel (level 2)
+    # would add a few microseconds to each of a step's launches
+    ctx.set_profiling(3 if args.profile_celf else 1)
     ctx.reset_kernel_stats()
     phases = np.zeros(4)
     torch.cuda.synchronize()
@@ -594,14 +606,24 @@ def main():
     if args.profile_celf:
         names += ["celf.barrier", "celf.eval", "celf.commit", "celf.restale", "celf.prep", "celf.post",
                   "celf.rebuild", "celf.bulk", "celf.sort", "celf.move", "celf.lookahead_commits"]
+    prof_steps = args.steps
+    if not args.profile_celf:
+        # every kernel's time from one more step, untimed, with events around
+        # each launch (level 2)
+        ctx.set_profiling(2)
+        ctx.reset_kernel_stats()
+        step()
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        prof_steps = 1
     stats = {k: ctx.kernel_stats(k) for k in names}
     evals = G.celf_evals()
     memo_stats = G.memo_stats()
 
-    # one more step, untimed, with every work count on (level 3: the
+    # one more step, untimed, with every work count on (level 4: the
     # labelling kernels' counts and the CELF kernel's listed tiles and
     # gathers; they cost atomics, so the timed steps run without them)
-    ctx.set_profiling(3)
+    ctx.set_profiling(4)
     ctx.reset_kernel_stats()
     step()
     torch.cuda.synchronize()
@@ -658,8 +680,8 @@ def main():
         "celf_evals": evals,
         "cover_count": cover,
         "kernel_avg_ms": {k: (v[1] / v[0] if v[0] else None) for k, v in stats.items()},
-        "kernel_launches_per_step": {k: v[0] / args.steps for k, v in stats.items()},
-        "kernel_total_ms_per_step": {k: v[1] / args.steps for k, v in stats.items()},
+        "kernel_launches_per_step": {k: v[0] / prof_steps for k, v in stats.items()},
+        "kernel_total_ms_per_step": {k: v[1] / prof_steps for k, v in stats.items()},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_celf_persistent",

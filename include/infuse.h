@@ -246,14 +246,19 @@ im_status im_get_tuning(const im_ctx *ctx, im_tuning *t);
  * dropped).  Errors: NULL arguments, parameters not set, K outside 1..n. */
 im_status im_autotune(im_graph *g, uint32_t K, uint32_t reps, im_tuning *best);
 
-/* Per-kernel device timing with HIP events recorded on the context stream
- * around launches (off by default).  level 0: off; 1: the kernels that run
- * once per memo construction or query (edge_hash, x_sort, hook, link,
- * flatten, count, gain0, sigma); 2: also every CELF round launch
- * (celf_topw, celf_eval, celf_bulk), whose events perturb the timing of
- * such short kernels, and the persistent CELF kernel's phase clock; 3: also
- * the work counts of memo constructions (im_memo_work).  im_kernel_stats returns the number of launches and
- * the summed milliseconds of the named kernel since the last reset. */
+/* Per-kernel device timing with HIP events recorded on the launching
+ * stream around launches (off by default).  level 0: off; 1: the long
+ * launches only, whose events cost nothing measurable: the persistent CELF
+ * kernel (celf) and the memo-free search's levels (bfs_level, with the
+ * search's work counts, im_last_search_stats); 2: also the kernels that run
+ * once per memo construction or query (edge_hash, x_sort, hook, hook_hubs,
+ * lists, link, link_hubs, flatten, count, gain0, sigma, sigma_direct, the
+ * batched construction's phases), whose events add a few microseconds
+ * each; 3: also every CELF round launch (celf_topw, celf_eval, celf_bulk)
+ * and the persistent CELF kernel's phase clock; 4: also the work counts of
+ * memo constructions (im_memo_work) and of the persistent CELF kernel.
+ * im_kernel_stats returns the number of launches and the summed
+ * milliseconds of the named kernel since the last reset. */
 im_status im_set_profiling(im_ctx *ctx, int level);
 im_status im_reset_kernel_stats(im_ctx *ctx);
 im_status im_kernel_stats(im_ctx *ctx, const char *kernel, uint64_t *launches, double *total_ms);
@@ -276,7 +281,7 @@ uint64_t im_last_celf_evals(const im_graph *g);
 im_status im_last_search_stats(const im_graph *g, uint64_t *out4);
 
 /* Work counts of the construction of the memo resident for the current
- * parameters, kept when it was built while profiling was at level 3 (they
+ * parameters, kept when it was built while profiling was at level 4 (they
  * cost atomics in every labelling kernel).  Writes out[0 .. n_out-1] (zero
  * past the last count): out[0] live (edge, simulation) pairs, out[1] union
  * attempts of the link kernels, out[2] rows rewritten by the flatten pass,

@@ -298,7 +298,7 @@ class Graph:
 
     def memo_work(self) -> dict:
         """Work counts of the resident memo's construction (built while the
-        context's profiling level was 3)."""
+        context's profiling level was 4)."""
         a = (C.c_uint64 * len(self.WORK_KEYS))()
         check(self._lib.im_memo_work(self.handle, a, len(self.WORK_KEYS)))
         return {k: int(v) for k, v in zip(self.WORK_KEYS, a)}

@@ -104,7 +104,7 @@ struct MemoView {
   uint32_t* counts;     // [2 * j] = |tlist_j|, [2 * j + 1] = |llist_j|
   uint32_t list_cap;
   // work counts of the construction (kWork* below), or nullptr when not
-  // counting (they cost atomics: only while profiling at level 3)
+  // counting (they cost atomics: only while profiling at level 4)
   unsigned long long* work;
 };
 

@@ -105,7 +105,7 @@ void* noalloc_scratch_setup(int device);
 // Records HIP events around a launch on `st` when profiling is on.
 class KTimer {
  public:
-  KTimer(im_ctx* c, const char* name, hipStream_t st, int level = 1);
+  KTimer(im_ctx* c, const char* name, hipStream_t st, int level = 2);
   ~KTimer();
 
  private:

@@ -264,9 +264,9 @@ Memo* memo_find(im_graph* g, double p, uint32_t R, uint32_t seed) {
 }
 
 // Tiles per hook_hubs wavefront from the context's cc_chunk (columns).
-// Profiling bits of a persistent CELF launch: the phase clock from level 2,
-// the work counts (listed tiles, gathers) at level 3.
-uint32_t pcelf_prof_bits(const im_ctx* c) { return (c->profiling >= 2 ? 1u : 0u) | (c->profiling >= 3 ? 2u : 0u); }
+// Profiling bits of a persistent CELF launch: the phase clock from level 3,
+// the work counts (listed tiles, gathers) at level 4.
+uint32_t pcelf_prof_bits(const im_ctx* c) { return (c->profiling >= 3 ? 1u : 0u) | (c->profiling >= 4 ? 2u : 0u); }
 
 uint32_t hub_chunk_tiles(const im_ctx* c) { return std::max(1u, std::min(32u, c->tune.cc_chunk / kTile)); }
 
@@ -342,7 +342,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   if (s != IM_OK) return s;
   im_ctx* c = g->ctx;
   MemoView mv = m->view(g);
-  m->counted = c->profiling >= 3;
+  m->counted = c->profiling >= 4;
   if (m->counted) {
     mv.work = m->work;
     launch_fill_u32(reinterpret_cast<uint32_t*>(m->work), 2 * kWorkCounts, 0u, st);
@@ -624,7 +624,7 @@ static void sweep_graph_runs(im_ctx* c, bool wait) {
 
 void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   sweep_graph_runs(c, false);
-  if (c->tune.use_graphs && c->profiling < 2) {
+  if (c->tune.use_graphs && c->profiling < 3) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -654,15 +654,15 @@ static void celf_steps_direct(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
   const uint32_t bulk_blocks = std::max(1u, std::min(2048u, v.m.n));
   for (uint32_t k = 0; k < v.K; ++k) {
     {
-      KTimer t(c, "celf_topw", st, 2);
+      KTimer t(c, "celf_topw", st, 3);
       launch_celf_topw(v, st);
     }
     {
-      KTimer t(c, "celf_eval", st, 2);
+      KTimer t(c, "celf_eval", st, 3);
       launch_celf_eval(v, st);
     }
     {
-      KTimer t(c, "celf_bulk", st, 2);
+      KTimer t(c, "celf_bulk", st, 3);
       launch_celf_bulk(v, bulk_blocks, st);
     }
   }
@@ -689,7 +689,7 @@ im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const Cel
                       const int64_t* marginal, int64_t* cover, uint64_t* evals) {
   const CelfView& v = cb->v;
   if (perr) return fail(IM_ERR_DEVICE, "persistent CELF kernel aborted (code %u)", perr);
-  if (cb->persistent && c->profiling >= 2) {
+  if (cb->persistent && c->profiling >= 3) {
     // phase clock of the persistent kernel: ticks of 10 ns per phase
     uint64_t pr[16];
     if (hipMemcpy(pr, static_cast<char*>(cb->pscratch) + pcelf_prof_offset(), sizeof(pr),
@@ -707,7 +707,7 @@ im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const Cel
       c->kstats["celf.lookahead_commits"].first += pr[15];  // steps decided without a round
     }
     uint64_t wk[2];
-    if (c->profiling >= 3 &&
+    if (c->profiling >= 4 &&
         hipMemcpy(wk, static_cast<char*>(cb->pscratch) + pcelf_work_offset(), sizeof(wk), hipMemcpyDeviceToHost) ==
             hipSuccess) {
       std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -837,7 +837,7 @@ extern "C" im_status im_get_tuning(const im_ctx* c, im_tuning* t) {
 
 extern "C" im_status im_set_profiling(im_ctx* c, int level) {
   if (!c) return fail(IM_ERR_INVALID_ARG, "NULL context");
-  if (level < 0 || level > 3) return fail(IM_ERR_INVALID_ARG, "profiling level must be 0, 1, 2 or 3");
+  if (level < 0 || level > 4) return fail(IM_ERR_INVALID_ARG, "profiling level must be 0 to 4");
   c->profiling = level;
   return IM_OK;
 }
@@ -1206,7 +1206,7 @@ static hipError_t bfs_levels(im_ctx* c, const GraphView& gv, const MemoView& mv,
       bv.cur = la;
       bv.next = lb;
       {
-        KTimer t(c, "bfs_level", st);
+        KTimer t(c, "bfs_level", st, 1);
         launch_bfs_level(gv, mv, bv, level, st);
       }
       launch_bfs_compact(bv, level, st);
@@ -1610,7 +1610,7 @@ extern "C" im_status im_memo_work(im_graph* g, uint64_t* out, uint32_t n_out) {
   if (!m) return fail(IM_ERR_INVALID_ARG, "no resident memo for the current parameters");
   if (!m->counted) {
     memo_release(g, m);
-    return fail(IM_ERR_INVALID_ARG, "the memo was built without work counting (profiling level 3)");
+    return fail(IM_ERR_INVALID_ARG, "the memo was built without work counting (profiling level 4)");
   }
   unsigned long long h[kWorkCounts];
   if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);

@@ -1,5 +1,6 @@
 """Host logic of the benchmark (CPU): the committed counter summaries are
-well formed, a changed kernel source voids a summary's traffic, the
+well formed, a changed kernel source (not a changed comment) voids a
+summary's traffic, the
 memo-free search's algorithmic bytes follow their per-unit figures, and a
 request for more than one GPU is refused before anything runs."""
 
@@ -41,6 +42,9 @@ def test_changed_source_voids_the_traffic_record(tmp_path):
            "source_hash": bench.roof_source_hash([str(src)])}
     summary = tmp_path / "k_traffic.txt"
     summary.write_text("# header\nTRAFFIC_JSON " + json.dumps(rec) + "\n")
+    assert bench.read_traffic(str(summary), [str(src)]) == rec
+    # an edited comment or re-indented line is not a change of the kernel
+    src.write_text("// a comment\nkernel   one /* an\n other */\n")
     assert bench.read_traffic(str(summary), [str(src)]) == rec
     src.write_text("kernel two\n")
     assert bench.read_traffic(str(summary), [str(src)]) is None
