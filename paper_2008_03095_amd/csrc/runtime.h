@@ -84,7 +84,6 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
 // persistent_ok allow it; it waits for and holds back every other stream of
 // the context) or the per-step kernels, which run beside other work.
 void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st, bool persistent_ok = true);
-void celf_prepare(CelfBuffers* cb, hipStream_t st);
 bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_t group_blocks,
                             const uint32_t* first, hipStream_t st);
 void celf_enqueue_steps(im_ctx* c, CelfBuffers* cb, hipStream_t st);

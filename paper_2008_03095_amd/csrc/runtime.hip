@@ -529,7 +529,7 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
 }
 
 // Clears the coverage bitmap and the state of a selection.
-void celf_prepare(CelfBuffers* cb, hipStream_t st) {
+static void celf_prepare(CelfBuffers* cb, hipStream_t st) {
   const CelfView& v = cb->v;
   launch_fill_u32(v.cov, (uint64_t)v.m.n * v.cwords, 0u, st);
   launch_celf_init(v, st);
