@@ -289,10 +289,8 @@ im_status memo_alloc(im_graph* g, double p, uint32_t R, uint32_t seed, Memo** ou
   m->tm1 = (g->per_edge || T == 0) ? 0u : (uint32_t)(T - 1);
   m->kshift = bitlen32(m->tm1);
   m->counted = false;
-  if (g->nhubs) {
-    if (hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming) != hipSuccess) m->fork_ev = nullptr;
-    if (hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming) != hipSuccess) m->join_ev = nullptr;
-  }
+  if (hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming) != hipSuccess) m->fork_ev = nullptr;
+  if (hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming) != hipSuccess) m->join_ev = nullptr;
   m->bytes = memo_bytes(g, R);
   void* base = nullptr;
   im_status s = ctx_alloc(c, m->bytes, &base);
@@ -350,17 +348,27 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
   const uint32_t chunk_tiles = hub_chunk_tiles(c);
   const bool timed = g->ev[0] != nullptr && st == c->stream;
   if (timed) (void)hipEventRecord(g->ev[0], st);
+  // the sample values are sorted on the side stream while the edges are
+  // hashed and the masks cleared (only for the context stream, as below)
+  const bool side = c->aux && m->fork_ev && m->join_ev && st == c->stream;
+  if (side) {
+    (void)hipEventRecord(m->fork_ev, st);
+    (void)hipStreamWaitEvent(c->aux, m->fork_ev, 0);
+  }
+  {
+    hipStream_t xs = side ? c->aux : st;
+    KTimer t(c, "x_sort", xs);
+    launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, xs);
+  }
+  if (side) (void)hipEventRecord(m->join_ev, c->aux);
   {
     KTimer t(c, "edge_hash", st);
     launch_edge_hash(g->view(), seed, m->edges, st);
   }
-  {
-    KTimer t(c, "x_sort", st);
-    launch_x_sort(seed, R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
-  }
   // hub vertices' mask words are or-ed into; k_lists writes every count
   launch_fill_u32(m->tmask, (uint64_t)(reinterpret_cast<char*>(m->lmask) - reinterpret_cast<char*>(m->tmask)) / 4 +
                                 (uint64_t)g->n * m->mwords, 0u, st);
+  if (side) (void)hipStreamWaitEvent(st, m->join_ev, 0);
   if (timed) (void)hipEventRecord(g->ev[1], st);
   // hub rows (few, long, latency-bound wavefronts) run on the side stream
   // next to the bandwidth-bound light rows; the two write disjoint rows
