@@ -25,6 +25,8 @@ CASES = {
     "rmat12_p01": (lambda: rmat_directed(12, 8, 0.57, 0.19, 0.19, 4), 0.01, 1024, 4, False),
     "rmat12_wc": (lambda: rmat_directed(12, 8, 0.57, 0.19, 0.19, 5), 0.0, 512, 5, True),
     "rmat14_wc_R257": (lambda: rmat_directed(14, 6, 0.57, 0.19, 0.19, 6), 0.0, 257, 6, True),
+    # more than 8,192 samples: 36 tiles per vertex
+    "rmat11_R9000": (lambda: rmat_directed(11, 4, 0.57, 0.19, 0.19, 8), 0.02, 9000, 8, False),
 }
 
 
@@ -115,6 +117,8 @@ SELECT_CASES = {
     "rmat12_p02": (lambda: rmat_directed(12, 5, 0.57, 0.19, 0.19, 7), 0.02, 128, 7, False, 8),
     # the selection of the directed benchmark line, at its size
     "rmat14_wc_K50": (lambda: rmat_directed(14, 5, 0.57, 0.19, 0.19, 4), 0.0, 1024, 4, True, 50),
+    # more than 8,192 samples
+    "drand80_R9000": (lambda: random_small_digraph(80, 400, 3), 0.05, 9000, 3, False, 5),
 }
 
 

@@ -377,6 +377,8 @@ DIRECT_CASES = {
     "p1": (lambda: chung_lu(500, 2000, 2.5, 9), 1.0, 64, 9, None),
     "hubs_uniform_w": (lambda: chung_lu(4000, 30000, 2.1, 7), 0.0, 600, 7, "uniform"),
     "trivalency": (lambda: chung_lu(3000, 15000, 2.5, 101), 0.0, 512, 101, "trivalency"),
+    # 36 tiles of samples: per-(vertex, tile) frontier items beyond one mask word
+    "wide_R9000": (lambda: chung_lu(800, 3000, 2.3, 57), 0.05, 9000, 57, None),
 }
 
 
