@@ -112,7 +112,7 @@ def cc_algorithmic_bytes(work: dict, n: int, mwords: int, light_slots: int, hub_
                           union tile, the initial gains set (8 B per vertex)
       link + link_hubs  : 1 KiB of hook parents per union tile, and per union
                           attempt the two entries read and one written (12 B)
-      flatten           : 1 KiB read per listed tile, 1 KiB per row rewritten
+      flatten           : 1 KiB read per listed tile, 4 B per entry rewritten
       count             : 1 KiB read per listed tile, 8 B per size decrement
                           made in device memory (read and write)
       gain0             : 1 KiB read per listed tile, 4 B per size gathered,
@@ -124,7 +124,7 @@ def cc_algorithmic_bytes(work: dict, n: int, mwords: int, light_slots: int, hub_
         "hook_hubs": 8 * hub_slots + 1024 * work["hub_tiles"],
         "lists": masks + 4 * (listed + link_tiles) + 8 * n,
         "link+link_hubs": link,
-        "flatten": 1024 * listed + 1024 * work["flatten_rewrites"],
+        "flatten": 1024 * listed + 4 * work["flatten_rewrites"],
         "count": 1024 * listed + 8 * work["count_atomics"],
         "gain0": 1024 * listed + 4 * work["gain_gathers"] + 8 * n,
     }
@@ -652,7 +652,7 @@ def main():
     if traffic and (traffic.get("workload") != args.workload or args.weights != "const"):
         traffic = None  # the counters were taken on another workload
     # components phase (hook ... count): the labelling kernels' algorithmic
-    # bytes over the phase's device time; beside it the survey's dense-memo
+    # bytes over the phase's device time; beside it a dense-memo
     # floor (every label written once, both endpoint labels of every live
     # edge-sample read) over the same time, as a model
     cc_ach = cc_phase_alg / (t_cc * 1e-3) / 1e9 if t_cc > 0 else None

@@ -284,7 +284,8 @@ im_status im_last_search_stats(const im_graph *g, uint64_t *out4);
  * parameters, kept when it was built while profiling was at level 4 (they
  * cost atomics in every labelling kernel).  Writes out[0 .. n_out-1] (zero
  * past the last count): out[0] live (edge, simulation) pairs, out[1] union
- * attempts of the link kernels, out[2] rows rewritten by the flatten pass,
+ * attempts of the link kernels, out[2] member entries the flatten pass
+ * re-pointed at their root (those that pointed at a non-root),
  * out[3] component-size decrements made in device memory by the count pass,
  * out[4] and out[5] (vertex, 256-column tile) rows written by the hook of
  * light vertices and of vertices with more than 64 neighbours, out[6]

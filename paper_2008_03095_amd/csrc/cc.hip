@@ -512,15 +512,15 @@ __device__ inline void flatten_body(const MemoView& m, uint32_t bid, uint32_t nb
           else act[i] = false;
         }
       }
-      bool changed = false;
+      uint32_t changed = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (q0 + i < m.R && o[i] >= 0 && c[i] != (uint32_t)o[i]) {
           o[i] = (int32_t)c[i];
-          changed = true;
+          ++changed;
         }
       if (changed) *reinterpret_cast<int4*>(row + q0) = out;
-      if (m.work) work_add(m, kWorkRewrites, (__ballot(changed) != 0 && lane == 0) ? 1u : 0u);
+      work_add(m, kWorkRewrites, changed);
     }
   }
 }

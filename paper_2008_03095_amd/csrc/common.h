@@ -112,7 +112,7 @@ struct MemoView {
 enum : uint32_t {
   kWorkLivePairs = 0,    // live (edge, column) pairs: every live edge-sample, seen from its larger end
   kWorkUnions = 1,       // union attempts of the link kernels
-  kWorkRewrites = 2,     // rows rewritten by k_flatten
+  kWorkRewrites = 2,     // member entries k_flatten re-pointed at their root
   kWorkCountAtomics = 3, // root decrements of k_count made in device memory (the others are summed in LDS)
   kWorkRowTiles = 4,     // tiles written by k_hook_rows
   kWorkHubTiles = 5,     // tiles written by k_hook_hubs

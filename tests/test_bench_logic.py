@@ -71,7 +71,7 @@ def test_cc_algorithmic_bytes():
     assert b["hook_hubs"] == 8 * 90 + 1024 * 2
     assert b["lists"] == 8 * 100 + 4 * (6 + 2) + 8 * 100
     assert b["link+link_hubs"] == 1024 * 2 + 12 * 7
-    assert b["flatten"] == 1024 * 6 + 1024 * 3
+    assert b["flatten"] == 1024 * 6 + 4 * 3
     assert b["count"] == 1024 * 6 + 8 * 11
     assert b["gain0"] == 1024 * 6 + 4 * 13 + 8 * 100
 
