@@ -568,8 +568,9 @@ def main():
     G.set_params(p, R, seed)
 
     def step():
+        # cold memo: the selection builds it (no wait between construction
+        # and selection)
         G.drop_memo()
-        G.build_memo()
         seeds, marg, cover = G.select_seeds(K)
         cnt, _ = G.estimate_sigma(seeds)
         if cnt != cover:

@@ -163,6 +163,8 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
   // downloaded with one copy; the descriptions of all launches go up in one
   // copy
   void* djobs = nullptr;
+  unsigned char* hb = nullptr;  // host side of the selections' block
+  size_t hcap = 0;              // its pinned size (0: pageable or none)
   std::vector<uint32_t> sel;
   for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
     if (K[i]) sel.push_back(i);
@@ -216,27 +218,34 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     const size_t o_pj = o_pf + align256((nj + 1) * 4);
     const size_t o_fi = o_pj + (coop ? align256(jb * nj) : 0);
     const size_t o_rec = o_fi + (coop ? align256((nj + 1) * 4) : 0);
-    std::vector<unsigned char> up, rec;
+    // host side of the block: pinned when possible (one upload of the jobs,
+    // one download of the records), else pageable
+    std::vector<unsigned char> pg;
     if (st == IM_OK) {
-      up.assign(o_rec, 0);
-      rec.resize(rec_bytes);
-      std::memcpy(up.data(), bj.data(), sizeof(CelfBatchJob) * nj);
-      std::memcpy(up.data() + o_pf, pfirst.data(), (nj + 1) * 4);
+      hb = static_cast<unsigned char*>(pinned_take(c, o_rec + rec_bytes, &hcap));
+      if (!hb) {
+        pg.resize(o_rec + rec_bytes);
+        hb = pg.data();
+      }
+      std::memset(hb, 0, o_rec);
+      unsigned char* up = hb;
+      std::memcpy(up, bj.data(), sizeof(CelfBatchJob) * nj);
+      std::memcpy(up + o_pf, pfirst.data(), (nj + 1) * 4);
       if (coop) {
         for (uint32_t k = 0; k < nj; ++k) {
           CelfBuffers& cb = cbs[sel[k]];
           const uint32_t gb = shaped ? first[k + 1] - first[k] : 1;
-          pcelf_fill_job(up.data() + o_pj + k * jb, cb.v, cb.pscratch, cb.blist, gb, c->tune.celf_round0,
+          pcelf_fill_job(up + o_pj + k * jb, cb.v, cb.pscratch, cb.blist, gb, c->tune.celf_round0,
                          pcelf_prof_bits(c));
         }
-        std::memcpy(up.data() + o_fi, first.data(), (nj + 1) * 4);
+        std::memcpy(up + o_fi, first.data(), (nj + 1) * 4);
       }
       st = ctx_alloc(c, o_rec + rec_bytes, &djobs);
     }
     if (st == IM_OK) {
       char* d = static_cast<char*>(djobs);
       const CelfBatchJob* dbj = reinterpret_cast<const CelfBatchJob*>(d);
-      if (hipMemcpyAsync(d, up.data(), o_rec, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      if (hipMemcpyAsync(d, hb, o_rec, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
         st = fail(IM_ERR_DEVICE, "batched selection: upload failed");
       } else {
         launch_celf_prepare_batch(dbj, reinterpret_cast<const uint32_t*>(d + o_pf), nj, pfirst[nj], c->stream);
@@ -251,7 +260,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
         if (!launched)
           for (uint32_t i : sel) celf_enqueue_steps(c, &cbs[i], c->stream);
         launch_celf_collect_batch(dbj, nj, reinterpret_cast<unsigned char*>(d + o_rec), c->stream);
-        if (hipMemcpyAsync(rec.data(), d + o_rec, rec_bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        if (hipMemcpyAsync(hb + o_rec, d + o_rec, rec_bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
           hipError_t e = hipGetLastError();
           st = fail(IM_ERR_DEVICE, "batched selection failed on the device: %s", hipGetErrorString(e));
@@ -260,7 +269,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
     }
     for (uint32_t k = 0; k < nj && st == IM_OK; ++k) {
       const uint32_t i = sel[k];
-      const unsigned char* r = rec.data() + bj[k].rec_off;
+      const unsigned char* r = hb + o_rec + bj[k].rec_off;
       const uint32_t Ki = K[i];
       uint32_t perr;
       CelfState hs;
@@ -278,6 +287,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
   for (uint32_t i = 0; i < ng && st == IM_OK; ++i)
     if (!K[i] && cover) cover[i] = 0;
   if (st != IM_OK) (void)hipStreamSynchronize(c->stream);
+  if (hcap) pinned_give(c, hb, hcap);
   if (djobs) ctx_free(c, djobs);
   if (dbuild) ctx_free(c, dbuild);
   for (uint32_t i = 0; i < ng; ++i) {

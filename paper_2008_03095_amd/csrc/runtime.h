@@ -65,6 +65,12 @@ struct CelfBuffers {
 };
 
 im_status fail(im_status s, const char* fmt, ...);
+// A pinned host buffer of at least `bytes` from the context's pool (its size
+// in *cap), or nullptr when no pinned memory can be had (the caller then
+// copies through pageable memory).  Give it back once the copies that use
+// it have completed; the pool is freed with the context.
+void* pinned_take(im_ctx* c, size_t bytes, size_t* cap);
+void pinned_give(im_ctx* c, void* p, size_t cap);
 im_status ctx_alloc(im_ctx* c, size_t bytes, void** out);
 void ctx_free(im_ctx* c, void* p);
 void memo_destroy(im_graph* g, Memo* m);
@@ -94,8 +100,11 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
 im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const CelfState& hs,
                       const int64_t* marginal, int64_t* cover, uint64_t* evals);
 im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out);
+// Enqueues sigma(S) into a scratch block of its own.  The seed ids are
+// uploaded from `src` (S.data() when null), which must stay valid until the
+// stream has passed the upload.
 im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
-                        void** scratch, unsigned long long** dev_out);
+                        void** scratch, unsigned long long** dev_out, const uint32_t* src = nullptr);
 
 // noalloc.hip: device address of the per-device scratch array of the
 // allocation-free sigma call (looked up once per device), or nullptr.
@@ -161,6 +170,10 @@ struct im_ctx {
   // slots): a persistent launch is fenced against every one of them
   std::vector<hipStream_t> peers;
   std::vector<hipEvent_t> fence_ev;  // one per fenced stream, reused
+  // pinned host buffers {address, bytes} for the small copies of the
+  // synchronous calls (a selection's results, a seed set and its count):
+  // copies from pageable memory are staged by the host, one at a time
+  std::vector<std::pair<void*, size_t>> pinned;
 };
 
 struct im_graph {

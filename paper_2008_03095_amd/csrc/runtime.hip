@@ -152,6 +152,33 @@ void ctx_free(im_ctx* c, void* p) {
     raw_free(c, p);
 }
 
+void* pinned_take(im_ctx* c, size_t bytes, size_t* cap) {
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    for (size_t i = 0; i < c->pinned.size(); ++i)
+      if (c->pinned[i].second >= bytes) {
+        void* p = c->pinned[i].first;
+        *cap = c->pinned[i].second;
+        c->pinned.erase(c->pinned.begin() + (ptrdiff_t)i);
+        return p;
+      }
+  }
+  const size_t want = std::max<size_t>((bytes + 4095) & ~(size_t)4095, 64 << 10);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  *cap = want;
+  return p;
+}
+
+void pinned_give(im_ctx* c, void* p, size_t cap) {
+  if (!p) return;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  c->pinned.emplace_back(p, cap);
+}
+
 // ---------------------------------------------------------------------------
 // kernel timing
 // ---------------------------------------------------------------------------
@@ -679,18 +706,40 @@ static void celf_steps_direct(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
 im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
                        int64_t* marginal, int64_t* cover, uint64_t* evals) {
   const CelfView& v = cb->v;
-  CelfState hs;
-  uint32_t perr = 0;  // error flag of the persistent kernel
-  if ((cb->persistent && hipMemcpyAsync(&perr, static_cast<char*>(cb->pscratch) + pcelf_err_offset(), sizeof(perr),
-                                        hipMemcpyDeviceToHost, st) != hipSuccess) ||
-      hipMemcpyAsync(seeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(marginal, v.marginal, (size_t)v.K * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&hs, v.st, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    hipError_t e = hipGetLastError();
-    return fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
+  // one pinned record {error flag of the persistent kernel, state, seeds,
+  // marginals}: the four copies are queued together and the call waits once
+  const size_t o_st = 256, o_seeds = o_st + align256(sizeof(CelfState)),
+               o_marg = o_seeds + align256((size_t)v.K * 4);
+  size_t cap = 0;
+  char* h = static_cast<char*>(pinned_take(c, o_marg + (size_t)v.K * 8, &cap));
+  uint32_t perr_pg = 0;
+  CelfState hs_pg;
+  uint32_t* perr = h ? reinterpret_cast<uint32_t*>(h) : &perr_pg;
+  CelfState* hs = h ? reinterpret_cast<CelfState*>(h + o_st) : &hs_pg;
+  uint32_t* hseeds = h ? reinterpret_cast<uint32_t*>(h + o_seeds) : seeds;
+  int64_t* hmarg = h ? reinterpret_cast<int64_t*>(h + o_marg) : marginal;
+  *perr = 0;
+  hipError_t e = hipSuccess;
+  if (cb->persistent)
+    e = hipMemcpyAsync(perr, static_cast<char*>(cb->pscratch) + pcelf_err_offset(), sizeof(uint32_t),
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hseeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hmarg, v.marginal, (size_t)v.K * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hs, v.st, sizeof(CelfState), hipMemcpyDeviceToHost, st);
+  const hipError_t es = hipStreamSynchronize(st);  // also when a copy failed: h is reused
+  if (e == hipSuccess) e = es;
+  im_status s;
+  if (e != hipSuccess) {
+    s = fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
+  } else {
+    if (h) {
+      std::memcpy(seeds, hseeds, (size_t)v.K * 4);
+      std::memcpy(marginal, hmarg, (size_t)v.K * 8);
+    }
+    s = celf_finish(c, cb, *perr, *hs, marginal, cover, evals);
   }
-  return celf_finish(c, cb, perr, hs, marginal, cover, evals);
+  pinned_give(c, h, cap);
+  return s;
 }
 
 im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const CelfState& hs,
@@ -801,6 +850,7 @@ extern "C" void im_ctx_destroy(im_ctx* c) {
   }
   if (c->coop_done) (void)hipEventDestroy(c->coop_done);
   for (hipEvent_t e : c->fence_ev) (void)hipEventDestroy(e);
+  for (auto& b : c->pinned) (void)hipHostFree(b.first);
   delete c;
 }
 
@@ -1129,7 +1179,7 @@ im_status infuse::normalize_set(const im_graph* g, const uint32_t* S, uint32_t l
 }
 
 im_status infuse::sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
-                        void** scratch, unsigned long long** dev_out) {
+                        void** scratch, unsigned long long** dev_out, const uint32_t* src) {
   im_ctx* c = g->ctx;
   const uint32_t len = (uint32_t)S.size();
   const bool pair = len <= sigma_pair_max();
@@ -1144,7 +1194,7 @@ im_status infuse::sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t
   auto* dS = reinterpret_cast<uint32_t*>(p8 + align256(8));
   uint32_t* bm = pair ? nullptr : reinterpret_cast<uint32_t*>(p8 + align256(8) + align256((size_t)len * 4));
   launch_fill_u32(reinterpret_cast<uint32_t*>(out), 2, 0u, st);
-  if (len) (void)hipMemcpyAsync(dS, S.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
+  if (len) (void)hipMemcpyAsync(dS, src ? src : S.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
   const MemoView mv = m->view(g);
   {
     KTimer t(c, "sigma", st);
@@ -1179,19 +1229,28 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   if (s != IM_OK) return s;
   void* scratch = nullptr;
   unsigned long long* dout = nullptr;
-  s = sigma_enqueue(g, m, set, c->stream, &scratch, &dout);
+  // pinned staging: the count at 0, the seed ids from byte 256
+  size_t cap = 0;
+  char* hp = static_cast<char*>(pinned_take(c, 256 + set.size() * 4, &cap));
+  if (hp) std::memcpy(hp + 256, set.data(), set.size() * 4);
+  s = sigma_enqueue(g, m, set, c->stream, &scratch, &dout, hp ? reinterpret_cast<const uint32_t*>(hp + 256) : nullptr);
   if (s == IM_OK) {
-    unsigned long long h = 0;
-    hipError_t e = hipMemcpyAsync(&h, dout, 8, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    unsigned long long hpg = 0;
+    unsigned long long* h = hp ? reinterpret_cast<unsigned long long*>(hp) : &hpg;
+    hipError_t e = hipMemcpyAsync(h, dout, 8, hipMemcpyDeviceToHost, c->stream);
+    const hipError_t es = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) {
       s = fail(IM_ERR_DEVICE, "sigma failed: %s", hipGetErrorString(e));
     } else {
-      if (count) *count = (int64_t)h;
-      if (sigma) *sigma = (double)h / (double)g->R;
+      if (count) *count = (int64_t)*h;
+      if (sigma) *sigma = (double)*h / (double)g->R;
     }
     ctx_free(c, scratch);
+  } else {
+    (void)hipStreamSynchronize(c->stream);  // an upload from hp may be queued
   }
+  pinned_give(c, hp, cap);
   memo_release(g, m);
   return s;
 }
