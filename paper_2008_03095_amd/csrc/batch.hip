@@ -115,10 +115,9 @@ static im_status batch_build(im_ctx* c, im_graph* const* graphs, const std::vect
     undo();
     return fail(IM_ERR_DEVICE, "batched construction failed to launch: %s", hipGetErrorString(e));
   }
+  const std::shared_ptr<ihipEvent_t> ready = record_ready(st);
   for (uint32_t k = 0; k < nj; ++k) {
-    Memo* m = memos[todo[k]];
-    if (hipEventCreateWithFlags(&m->ready_ev, hipEventDisableTiming) == hipSuccess)
-      (void)hipEventRecord(m->ready_ev, st);
+    memos[todo[k]]->ready = ready;
     graphs[todo[k]]->timed_build = false;
   }
   return IM_OK;
@@ -149,7 +148,7 @@ extern "C" im_status im_batch_select(im_ctx* c, uint32_t ng, im_graph* const* gr
       m->pins++;
       m->last_use = ++c->use_clock;
       memos[i] = m;
-      if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+      if (m->ready) (void)hipStreamWaitEvent(c->stream, m->ready_ev(), 0);
     } else {
       todo.push_back(i);
     }

@@ -119,7 +119,7 @@ extern "C" im_status im_estimate_sigma_noalloc(im_graph* g, const uint32_t* S, u
   auto* out = reinterpret_cast<unsigned long long*>(p8);
   auto* dS = reinterpret_cast<uint32_t*>(p8 + s_off);
   hipStream_t st = c->stream;
-  if (m->ready_ev) (void)hipStreamWaitEvent(st, m->ready_ev, 0);
+  if (m->ready) (void)hipStreamWaitEvent(st, m->ready_ev(), 0);
   launch_fill_u32(reinterpret_cast<uint32_t*>(out), 2, 0u, st);
   hipError_t e = hipMemcpyAsync(dS, src, (size_t)len * 4, hipMemcpyHostToDevice, st);
   const MemoView mv = m->view(g);

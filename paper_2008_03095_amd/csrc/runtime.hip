@@ -248,13 +248,20 @@ MemoView Memo::view(const im_graph* g) const {
   return v;
 }
 
+std::shared_ptr<ihipEvent_t> record_ready(hipStream_t st) {
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return {};
+  (void)hipEventRecord(e, st);
+  return std::shared_ptr<ihipEvent_t>(e, [](hipEvent_t x) { (void)hipEventDestroy(x); });
+}
+
 void memo_destroy(im_graph* g, Memo* m) {
   auto& v = g->memos;
   v.erase(std::remove(v.begin(), v.end(), m), v.end());
   // the memory may next be used from another stream: construction must be over
   // (queries using the memo hold pins, released only after they completed)
-  if (m->ready_ev) (void)hipEventSynchronize(m->ready_ev);
-  if (m->ready_ev) (void)hipEventDestroy(m->ready_ev);
+  if (m->ready) (void)hipEventSynchronize(m->ready_ev());
+  m->ready.reset();
   if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
   if (m->join_ev) (void)hipEventDestroy(m->join_ev);
   ctx_free(g->ctx, m->base);
@@ -467,8 +474,7 @@ im_status memo_build(im_graph* g, double p, uint32_t R, uint32_t seed, hipStream
     memo_destroy(g, m);
     return fail(IM_ERR_DEVICE, "memo kernels failed to launch: %s", hipGetErrorString(e));
   }
-  if (hipEventCreateWithFlags(&m->ready_ev, hipEventDisableTiming) == hipSuccess)
-    (void)hipEventRecord(m->ready_ev, st);
+  m->ready = record_ready(st);
   g->timed_build = timed;
   *out = m;
   return IM_OK;
@@ -492,7 +498,7 @@ im_status memo_acquire(im_graph* g, Memo** out) {
     if (s != IM_OK) return s;
   } else {
     g->timed_build = false;
-    if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+    if (m->ready) (void)hipStreamWaitEvent(c->stream, m->ready_ev(), 0);
   }
   *out = m;
   return IM_OK;
@@ -1680,7 +1686,7 @@ extern "C" im_status im_memo_work(im_graph* g, uint64_t* out, uint32_t n_out) {
     return fail(IM_ERR_INVALID_ARG, "the memo was built without work counting (profiling level 4)");
   }
   unsigned long long h[kWorkCounts];
-  if (m->ready_ev) (void)hipStreamWaitEvent(c->stream, m->ready_ev, 0);
+  if (m->ready) (void)hipStreamWaitEvent(c->stream, m->ready_ev(), 0);
   hipError_t e = hipMemcpyAsync(h, m->work, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   memo_release(g, m);

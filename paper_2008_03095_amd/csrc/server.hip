@@ -148,8 +148,8 @@ static bool admit(im_server* sv, Slot& s, Ticket* t) {
   if (!m) {
     st = memo_build(g, t->p, t->R, t->seed, s.stream, &m);  // returned pinned
     if (st == IM_OK) sv->builds++;
-  } else if (m->ready_ev) {
-    (void)hipStreamWaitEvent(s.stream, m->ready_ev, 0);
+  } else if (m->ready) {
+    (void)hipStreamWaitEvent(s.stream, m->ready_ev(), 0);
   }
   if (st == IM_OK) {
     if (t->kind == 0) {
