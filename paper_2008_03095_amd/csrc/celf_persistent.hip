@@ -19,8 +19,17 @@
 //     whose key exceeds max F at once (bulk), with the whole grid.
 // On commit, the rest of F is sorted and merged back into S.  All workgroups
 // decide from identical data, so only gains, coverage bits and keys cross
-// workgroups.  Evaluations also test the last committed seed's component
-// directly, so a commit needs no barrier before the next round.
+// workgroups.  Evaluations also test the components of the seeds committed
+// since the last grid barrier (up to three) directly, so a commit needs no
+// barrier before the next round.
+//
+// Look-ahead.  A round that starts with F empty (at most kAheadMax
+// candidates) also measures, per candidate u, the part of its gain that lies
+// in components of the round's lead a (the largest stale key), of the
+// second candidate b, and of both.  If a wins, the other keys for the next
+// step are gain - ov(a) (exact), and if b then wins that step too, the keys
+// for the step after are gain - ov(a) - ov(b) + ov(a, b) (inclusion and
+// exclusion over u's columns): up to two steps are decided without a round.
 //
 // Rebuild: a radix select (11-bit digits from the top bit of the largest
 // key) finds a threshold above which at most kPool keys lie, the keys above
@@ -47,6 +56,9 @@ constexpr uint32_t kBins = 1u << kDigitBits;
 constexpr uint64_t kSpinTicks = 200000000;     // 2 s of the 100 MHz clock
 constexpr uint64_t kRunTicks = 3000000000ull;  // 30 s
 
+constexpr uint32_t kOvA = kMaxCand, kOvB = 2 * kMaxCand, kOvAB = 2 * kMaxCand + kAheadMax;
+constexpr uint32_t kGainWords = 2 * kMaxCand + 2 * kAheadMax;
+
 // Device scratch of one run (zeroed by the host before the launch).
 struct PCelfScratch {
   uint32_t err;  // 1 barrier time-out, 2 inconsistent state, 4 run time-out
@@ -64,7 +76,10 @@ struct PCelfScratch {
   alignas(128) uint32_t arrive[kGroups][32];  // one 128-byte line per group
   uint32_t top[32];
   uint32_t release[kGroups][32];
-  uint64_t gains[3][2 * kMaxCand];    // per-round candidate gains, then overlaps with the lead; rotated
+  // per round: candidate gains [0, kMaxCand), overlaps with the lead
+  // [kOvA, +kMaxCand), with the second [kOvB, +kAheadMax) and with both
+  // [kOvAB, +kAheadMax); three buffers rotated
+  uint64_t gains[3][kGainWords];
   uint32_t hist[kBins];
   uint32_t pool_id[kPool];
   uint64_t pool_key[kPool];
@@ -187,7 +202,10 @@ struct PoolLds {
   uint32_t hist[kBins];
   uint32_t cg[64];               // restale of a small F: S entries above each F entry
   uint64_t fnext[kAheadMax];     // look-ahead: key of F entry i once lead is a seed
+  uint64_t fnext2[kAheadMax];    // ... once lead and second are seeds
   uint32_t lead;                 // look-ahead: leading candidate of the last round, or kInvalid
+  uint32_t second;               // its second candidate, or kInvalid
+  uint32_t lead2;                // second whose keys fnext2 holds, pending after lead's commit, or kInvalid
   uint32_t ns, head, nf, fbest;  // S size, S front, F size, index of max F
   uint64_t out_bound;
   uint64_t prefix;
@@ -273,34 +291,42 @@ __device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t
 }
 
 // This lane's share of gain(u | S) over tile t: the sizes of u's components
-// in the lane's four columns that hold no seed.  `last` is the most recent
-// seed (or kInvalid), whose coverage bits may not be visible yet: its
-// component is tested directly, and so is prev's, the seed before it, when
-// no grid barrier has passed since its commit (kInvalid otherwise).  `overlap` receives the part of the share
-// that lies in components of `lead` (the round's leading candidate): what
-// u would lose if lead became the next seed.  The rows and their tmask words are loaded
-// together; a row word of a tile without its tmask bit is stale and reads
-// as -1 (a singleton), which saves a dependent load on this latency-bound
-// path.
+// in the lane's four columns that hold no seed.  `last`, `prev` and `prev2`
+// are the seeds committed since the last grid barrier, most recent first
+// (kInvalid where there are fewer): their coverage bits may not be visible
+// yet, so their components are tested directly.  `ov_a` receives the part
+// of the share that lies in components of `lead` (the round's leading
+// candidate: what u would lose if lead became the next seed), `ov_b` the
+// part in components of `second`, `ov_ab` the part in components of both.
+// The rows and their tmask words are loaded together; a row word of a tile
+// without its tmask bit is stale and reads as -1 (a singleton), which saves
+// a dependent load on this latency-bound path.
 __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
-                                       uint32_t last, uint32_t prev, uint32_t lead, uint64_t& overlap) {
+                                       uint32_t last, uint32_t prev, uint32_t prev2, uint32_t lead,
+                                       uint32_t second, uint64_t& ov_a, uint64_t& ov_b, uint64_t& ov_ab) {
   const MemoView& m = c.m;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  const bool has_last = last != kInvalid, has_prev = prev != kInvalid;
-  const uint32_t lu = has_last ? last : u, pu = has_prev ? prev : u;
+  const bool has_last = last != kInvalid, has_prev = prev != kInvalid, has_prev2 = prev2 != kInvalid;
+  const uint32_t lu = has_last ? last : u, pu = has_prev ? prev : u, p2u = has_prev2 ? prev2 : u;
   const uint32_t ub = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
   const uint32_t lb = ldg(m.tmask + (uint64_t)lu * m.mwords + (t >> 5));
   const uint32_t pb = ldg(m.tmask + (uint64_t)pu * m.mwords + (t >> 5));
+  const uint32_t p2b = ldg(m.tmask + (uint64_t)p2u * m.mwords + (t >> 5));
   const uint32_t db = ldg(m.tmask + (uint64_t)lead * m.mwords + (t >> 5));
+  const uint32_t eb = ldg(m.tmask + (uint64_t)second * m.mwords + (t >> 5));
   const p_i4 ru = ldg4(m.M + (uint64_t)u * m.Rs + q0);
   const p_i4 rl = ldg4(m.M + (uint64_t)lu * m.Rs + q0);
   const p_i4 rp = ldg4(m.M + (uint64_t)pu * m.Rs + q0);
+  const p_i4 rp2 = ldg4(m.M + (uint64_t)p2u * m.Rs + q0);
   const p_i4 rd = ldg4(m.M + (uint64_t)lead * m.Rs + q0);
+  const p_i4 re = ldg4(m.M + (uint64_t)second * m.Rs + q0);
   const p_i4 none = p_i4{-1, -1, -1, -1};
   const p_i4 cur = ((ub >> (t & 31)) & 1u) ? ru : none;
   const p_i4 sl = ((lb >> (t & 31)) & 1u) ? rl : none;
   const p_i4 sp = ((pb >> (t & 31)) & 1u) ? rp : none;
+  const p_i4 sp2 = ((p2b >> (t & 31)) & 1u) ? rp2 : none;
   const p_i4 sd = ((db >> (t & 31)) & 1u) ? rd : none;
+  const p_i4 se = ((eb >> (t & 31)) & 1u) ? re : none;
   // every load below has a valid address, so none waits behind a branch:
   // a member reads its root's entry, a root or singleton its own
   int32_t raw[4];
@@ -312,23 +338,30 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
     raw[i] = ldg(m.M + (uint64_t)root[i] * m.Rs + q0 + i);
     word[i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
   }
-  uint64_t sum = 0, ov = 0;
+  uint64_t sum = 0, oa = 0, ob = 0, oab = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t q = q0 + i;
     const int32_t val = cur[i];
     const uint32_t lroot = sl[i] < 0 ? last : (uint32_t)sl[i];
     const uint32_t proot = sp[i] < 0 ? prev : (uint32_t)sp[i];
+    const uint32_t p2root = sp2[i] < 0 ? prev2 : (uint32_t)sp2[i];
     const uint32_t droot = sd[i] < 0 ? lead : (uint32_t)sd[i];
+    const uint32_t eroot = se[i] < 0 ? second : (uint32_t)se[i];
     const bool shared = val != -1;  // a singleton holds no seed
     const bool covered = shared && (((word[i] >> (q & 31)) & 1u) || (has_last && lroot == root[i]) ||
-                                    (has_prev && proot == root[i]));
+                                    (has_prev && proot == root[i]) || (has_prev2 && p2root == root[i]));
     const uint64_t size = (uint64_t)(uint32_t)(-(val < 0 ? val : raw[i]));
-    const bool counted = q < m.R && !covered;
-    sum += counted ? size : 0;
-    ov += (counted && shared && droot == root[i]) ? size : 0;
+    const bool counted = q < m.R && !covered && shared;
+    const bool in_a = counted && droot == root[i], in_b = counted && eroot == root[i];
+    sum += (q < m.R && !covered) ? size : 0;
+    oa += in_a ? size : 0;
+    ob += in_b ? size : 0;
+    oab += (in_a && in_b) ? size : 0;
   }
-  overlap = ov;
+  ov_a = oa;
+  ov_b = ob;
+  ov_ab = oab;
   return sum;
 }
 
@@ -902,14 +935,15 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   const uint32_t nw = G.nb * (kPBlock / 64);
   const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   const uint32_t ntiles = c.m.ntiles;
-  uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, last = kInvalid, prev = kInvalid, step_rebuilds = 0;
+  uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, step_rebuilds = 0;
+  uint32_t last = kInvalid, prev = kInvalid, prev2 = kInvalid;  // seeds committed since the last grid barrier
   bool synced = true;  // a grid barrier has passed since the last commit
   uint64_t evals = 0;
   uint64_t ptiles = 0, pcols = 0;  // profiling work counts of this wavefront
   PClock clk;
   clk.start((a.prof & 1u) != 0);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-  if (threadIdx.x == 0) L.lead = kInvalid;
+  if (threadIdx.x == 0) L.lead = L.second = L.lead2 = kInvalid;
   if (!pool_rebuild(a, G, L, s, gen, clk)) return;
   bool just_rebuilt = true;
   while (s < c.K) {
@@ -939,23 +973,31 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         st64(&c.key[id], 0ull);
       }
       // look-ahead: every F entry came from the round led by id, which
-      // measured each one's overlap with id
+      // measured each one's overlap with id (ahead), or the last commit was
+      // that round's lead and id is its second (ahead2): F holds every
+      // entry's key for the step after this one
       const bool ahead = L.lead == id;
+      const bool ahead2 = !ahead && L.lead2 == id;
+      const uint32_t second = L.second;
       clk.lap(PClock::kCommit);
       p_lds_sync();  // the marking atomics stay in flight through the pool work
       if (threadIdx.x == 0) {  // drop the seed from F
         const uint32_t b = L.fbest;
         L.fkey[b] = L.fkey[nf - 1];
         L.fid[b] = L.fid[nf - 1];
-        if (ahead) L.fnext[b] = L.fnext[nf - 1];  // nf <= kAheadMax here
+        if (ahead || ahead2) {  // nf <= kAheadMax here
+          L.fnext[b] = L.fnext[nf - 1];
+          L.fnext2[b] = L.fnext2[nf - 1];
+        }
         L.nf = nf - 1;
-        L.lead = kInvalid;
+        L.lead = L.second = kInvalid;
+        L.lead2 = ahead ? second : kInvalid;  // fnext2 stays valid for it
       }
       p_lds_sync();
-      if (ahead) {
+      if (ahead || ahead2) {
         // the keys for the next step are exact: F stays fresh, S unchanged
         for (uint32_t i = threadIdx.x; i + 1 < nf; i += kPBlock) {
-          const uint64_t k = L.fnext[i];
+          const uint64_t k = ahead ? L.fnext[i] : L.fnext2[i];
           L.fkey[i] = k;
           if (G.bi == 0) {
             st64(&c.key[L.fid[i]], k);
@@ -968,7 +1010,10 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       } else {
         pool_restale(L, clk);
       }
-      prev = synced ? kInvalid : last;  // a look-ahead commit follows the last one without a barrier
+      // up to three commits follow each other without a grid barrier (a
+      // round's lead, then its second and one more by look-ahead)
+      prev2 = synced ? kInvalid : prev;
+      prev = synced ? kInvalid : last;
       last = id;
       synced = false;
       ++s;
@@ -985,26 +1030,33 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       if (fbest) nc = min(nc, count_greater(L.skey + head, nc, fbest));
       nc = min(nc, kPool - nf);
       // look-ahead when F is empty: the round also measures each candidate's
-      // overlap with the leading (largest stale) candidate, so that if the
-      // lead wins, the others' keys for the next step are known exactly
+      // overlaps with the two largest stale candidates, so that if they win
+      // the next steps, the others' keys are known exactly
       const bool ahead = nf == 0 && nc <= kAheadMax;
+      const bool ahead2 = ahead && nc >= 2;
       const uint32_t lead = L.sid[head];
+      const uint32_t second = ahead2 ? L.sid[head + 1] : kInvalid;
       uint64_t* g = x->gains[ev_round % 3];
       if (G.bi == 0) {
         uint64_t* nxt = x->gains[(ev_round + 1) % 3];
-        for (uint32_t i = threadIdx.x; i < 2 * kMaxCand; i += kPBlock) st64(&nxt[i], 0ull);
+        for (uint32_t i = threadIdx.x; i < kGainWords; i += kPBlock) st64(&nxt[i], 0ull);
       }
       clk.lap(PClock::kPrep);
       const uint32_t items = nc * ntiles;
       for (uint32_t it = gw; it < items; it += nw) {
         const uint32_t w = it / ntiles, t = it - w * ntiles;
         const uint32_t u = L.sid[head + w];
-        uint64_t ov;
-        const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, ahead ? lead : u, ov));
+        uint64_t oa, ob, oab;
+        const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, prev2, ahead ? lead : u,
+                                                 ahead2 ? second : u, oa, ob, oab));
         if (a.prof & 2u) p_count_tile(c, u, t, lane, ptiles, pcols);
-        ov = ahead ? p_wsum(ov) : 0;
+        oa = ahead ? p_wsum(oa) : 0;
+        ob = ahead2 ? p_wsum(ob) : 0;
+        oab = ahead2 ? p_wsum(oab) : 0;
         if (lane == 0 && part) g_add64(&g[w], part);
-        if (lane == 0 && ov) g_add64(&g[kMaxCand + w], ov);
+        if (lane == 0 && oa) g_add64(&g[kOvA + w], oa);
+        if (lane == 0 && ob) g_add64(&g[kOvB + w], ob);
+        if (lane == 0 && oab) g_add64(&g[kOvAB + w], oab);
       }
       if (!grid_sync(x, G, gen, clk, PClock::kEval)) return;
       synced = true;  // every commit so far is visible in the coverage bitmap
@@ -1015,7 +1067,14 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         const uint64_t k = p_make_key(c, gain, v);
         L.fkey[nf + w] = k;
         L.fid[nf + w] = v;
-        if (ahead) L.fnext[w] = p_make_key(c, gain - ld64(&g[kMaxCand + w]), v);
+        if (ahead) {
+          const uint64_t oa = ld64(&g[kOvA + w]);
+          L.fnext[w] = p_make_key(c, gain - oa, v);
+          if (ahead2) {  // gain - ov(a) - ov(b) + ov(a, b); a and b themselves go negative, kept at 0
+            const int64_t g2 = (int64_t)(gain - oa) - (int64_t)ld64(&g[kOvB + w]) + (int64_t)ld64(&g[kOvAB + w]);
+            L.fnext2[w] = p_make_key(c, g2 > 0 ? (uint64_t)g2 : 0ull, v);
+          }
+        }
         if (G.bi == 0) {
           st64(&c.key[v], k);
           st32(&c.iter[v], s);
@@ -1026,6 +1085,8 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         L.head = head + nc;
         L.nf = nf + nc;
         L.lead = ahead ? lead : kInvalid;
+        L.second = second;
+        L.lead2 = kInvalid;  // F now holds entries without keys for two steps ahead
       }
       __syncthreads();
       f_best(L);
@@ -1046,7 +1107,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     }
     if (nf && step_rebuilds > 0)
       if (!bulk_eval(a, G, L, s, fbest, ptiles, pcols, gen, clk, evals)) return;
-    if (threadIdx.x == 0) L.lead = kInvalid;  // the rebuilt F did not come from one round
+    if (threadIdx.x == 0) L.lead = L.second = L.lead2 = kInvalid;  // the rebuilt F did not come from one round
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     synced = true;
     ++step_rebuilds;
