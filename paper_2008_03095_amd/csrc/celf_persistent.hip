@@ -20,16 +20,16 @@
 // On commit, the rest of F is sorted and merged back into S.  All workgroups
 // decide from identical data, so only gains, coverage bits and keys cross
 // workgroups.  Evaluations also test the components of the seeds committed
-// since the last grid barrier (up to three) directly, so a commit needs no
-// barrier before the next round.
+// since the last grid barrier (up to kUnsynced) directly, so a commit needs
+// no barrier before the next round.
 //
 // Look-ahead.  A round that starts with F empty (at most kAheadMax
-// candidates) also measures, per candidate u, the part of its gain that lies
-// in components of the round's lead a (the largest stale key), of the
-// second candidate b, and of both.  If a wins, the other keys for the next
-// step are gain - ov(a) (exact), and if b then wins that step too, the keys
-// for the step after are gain - ov(a) - ov(b) + ov(a, b) (inclusion and
-// exclusion over u's columns): up to two steps are decided without a round.
+// candidates) also splits each candidate u's gain by signature: for each of
+// u's columns, the subset of the round's first kAheadSet candidates (the
+// largest stale keys, the set A) whose component there is u's.  Once seeds
+// T of A are committed, u's gain is the sum of its bins whose signature
+// misses T, exactly; so while every commit comes from A the pool's keys stay
+// fresh and the steps are decided without a round.
 //
 // Rebuild: a radix select (11-bit digits from the top bit of the largest
 // key) finds a threshold above which at most kPool keys lie, the keys above
@@ -49,15 +49,17 @@ constexpr uint32_t kPool = 2048;               // pool entries per workgroup
 constexpr uint32_t kPBlock = 256;              // threads per workgroup
 constexpr uint32_t kPer = kPool / kPBlock;     // pool entries per thread
 constexpr uint32_t kMaxCand = 1024;            // evaluations per round
-constexpr uint32_t kAheadMax = 64;             // largest round that also measures overlaps with its lead
+constexpr uint32_t kAheadMax = 64;             // largest round that measures look-ahead signatures
+constexpr uint32_t kAheadSet = 3;              // candidates of such a round whose components are told apart
+constexpr uint32_t kSig = 1u << kAheadSet;     // signatures: subsets of them
+constexpr uint32_t kUnsynced = kAheadSet + 1;  // most seeds committed between two grid barriers
 constexpr uint32_t kGroups = 16;               // barrier arrival groups
 constexpr uint32_t kDigitBits = 11;
 constexpr uint32_t kBins = 1u << kDigitBits;
 constexpr uint64_t kSpinTicks = 200000000;     // 2 s of the 100 MHz clock
 constexpr uint64_t kRunTicks = 3000000000ull;  // 30 s
 
-constexpr uint32_t kOvA = kMaxCand, kOvB = 2 * kMaxCand, kOvAB = 2 * kMaxCand + kAheadMax;
-constexpr uint32_t kGainWords = 2 * kMaxCand + 2 * kAheadMax;
+constexpr uint32_t kGainWords = kMaxCand + kAheadMax * kSig;
 
 // Device scratch of one run (zeroed by the host before the launch).
 struct PCelfScratch {
@@ -76,9 +78,9 @@ struct PCelfScratch {
   alignas(128) uint32_t arrive[kGroups][32];  // one 128-byte line per group
   uint32_t top[32];
   uint32_t release[kGroups][32];
-  // per round: candidate gains [0, kMaxCand), overlaps with the lead
-  // [kOvA, +kMaxCand), with the second [kOvB, +kAheadMax) and with both
-  // [kOvAB, +kAheadMax); three buffers rotated
+  // per round: candidate gains [0, kMaxCand), then for a look-ahead round
+  // each candidate's gain by signature at kMaxCand + w * kSig + sig; three
+  // buffers rotated
   uint64_t gains[3][kGainWords];
   uint32_t hist[kBins];
   uint32_t pool_id[kPool];
@@ -201,11 +203,12 @@ struct PoolLds {
   uint64_t wmax[kPBlock / 64];
   uint32_t hist[kBins];
   uint32_t cg[64];               // restale of a small F: S entries above each F entry
-  uint64_t fnext[kAheadMax];     // look-ahead: key of F entry i once lead is a seed
-  uint64_t fnext2[kAheadMax];    // ... once lead and second are seeds
-  uint32_t lead;                 // look-ahead: leading candidate of the last round, or kInvalid
-  uint32_t second;               // its second candidate, or kInvalid
-  uint32_t lead2;                // second whose keys fnext2 holds, pending after lead's commit, or kInvalid
+  uint64_t fbin[kAheadMax][kSig];  // look-ahead: gain of F entry i by signature
+  uint32_t aset[kAheadSet];        // look-ahead: the set A of the round F came from
+  uint32_t na;                     // |A| (0: F's bins are not valid)
+  uint32_t amask;                  // members of A committed since
+  uint32_t uns[kUnsynced];         // seeds committed since the last grid barrier, most recent first
+  uint32_t nuns;                   // their number (valid until the next barrier)
   uint32_t ns, head, nf, fbest;  // S size, S front, F size, index of max F
   uint64_t out_bound;
   uint64_t prefix;
@@ -291,42 +294,44 @@ __device__ inline uint64_t p_make_key(const CelfView& c, uint64_t gain, uint32_t
 }
 
 // This lane's share of gain(u | S) over tile t: the sizes of u's components
-// in the lane's four columns that hold no seed.  `last`, `prev` and `prev2`
-// are the seeds committed since the last grid barrier, most recent first
-// (kInvalid where there are fewer): their coverage bits may not be visible
-// yet, so their components are tested directly.  `ov_a` receives the part
-// of the share that lies in components of `lead` (the round's leading
-// candidate: what u would lose if lead became the next seed), `ov_b` the
-// part in components of `second`, `ov_ab` the part in components of both.
-// The rows and their tmask words are loaded together; a row word of a tile
-// without its tmask bit is stale and reads as -1 (a singleton), which saves
-// a dependent load on this latency-bound path.
+// in the lane's four columns that hold no seed.  uns[0 .. nuns) (LDS) are
+// the seeds committed since the last grid barrier: their coverage bits may
+// not be visible yet, so their components are tested directly.  With na > 0,
+// bins[sig] receives the part of the share in components shared with
+// exactly the candidates {aset[j] : bit j of sig} (j < na, LDS); a lane's bin is
+// at most four component sizes of at most 2^24 vertices.  The rows and their
+// tmask words are loaded together; a row word of a tile without its tmask
+// bit is stale and reads as -1 (a singleton), which saves a dependent load
+// on this latency-bound path.
 __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t, uint32_t lane,
-                                       uint32_t last, uint32_t prev, uint32_t prev2, uint32_t lead,
-                                       uint32_t second, uint64_t& ov_a, uint64_t& ov_b, uint64_t& ov_ab) {
+                                       const uint32_t* uns, uint32_t nuns, const uint32_t* aset, uint32_t na,
+                                       uint32_t (&bins)[kSig]) {
   const MemoView& m = c.m;
   const uint32_t q0 = t * kTile + lane * kPerLane;
-  const bool has_last = last != kInvalid, has_prev = prev != kInvalid, has_prev2 = prev2 != kInvalid;
-  const uint32_t lu = has_last ? last : u, pu = has_prev ? prev : u, p2u = has_prev2 ? prev2 : u;
-  const uint32_t ub = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
-  const uint32_t lb = ldg(m.tmask + (uint64_t)lu * m.mwords + (t >> 5));
-  const uint32_t pb = ldg(m.tmask + (uint64_t)pu * m.mwords + (t >> 5));
-  const uint32_t p2b = ldg(m.tmask + (uint64_t)p2u * m.mwords + (t >> 5));
-  const uint32_t db = ldg(m.tmask + (uint64_t)lead * m.mwords + (t >> 5));
-  const uint32_t eb = ldg(m.tmask + (uint64_t)second * m.mwords + (t >> 5));
-  const p_i4 ru = ldg4(m.M + (uint64_t)u * m.Rs + q0);
-  const p_i4 rl = ldg4(m.M + (uint64_t)lu * m.Rs + q0);
-  const p_i4 rp = ldg4(m.M + (uint64_t)pu * m.Rs + q0);
-  const p_i4 rp2 = ldg4(m.M + (uint64_t)p2u * m.Rs + q0);
-  const p_i4 rd = ldg4(m.M + (uint64_t)lead * m.Rs + q0);
-  const p_i4 re = ldg4(m.M + (uint64_t)second * m.Rs + q0);
+  const uint32_t bit = t & 31;
   const p_i4 none = p_i4{-1, -1, -1, -1};
-  const p_i4 cur = ((ub >> (t & 31)) & 1u) ? ru : none;
-  const p_i4 sl = ((lb >> (t & 31)) & 1u) ? rl : none;
-  const p_i4 sp = ((pb >> (t & 31)) & 1u) ? rp : none;
-  const p_i4 sp2 = ((p2b >> (t & 31)) & 1u) ? rp2 : none;
-  const p_i4 sd = ((db >> (t & 31)) & 1u) ? rd : none;
-  const p_i4 se = ((eb >> (t & 31)) & 1u) ? re : none;
+  const uint32_t ub = ldg(m.tmask + (uint64_t)u * m.mwords + (t >> 5));
+  const p_i4 ru = ldg4(m.M + (uint64_t)u * m.Rs + q0);
+  // unused slots read u's own row: every load has a valid address
+  uint32_t sid[kUnsynced], sb[kUnsynced];
+  p_i4 sr[kUnsynced];
+#pragma unroll
+  for (uint32_t j = 0; j < kUnsynced; ++j) {
+    sid[j] = j < nuns ? uns[j] : u;
+    sb[j] = ldg(m.tmask + (uint64_t)sid[j] * m.mwords + (t >> 5));
+    sr[j] = ldg4(m.M + (uint64_t)sid[j] * m.Rs + q0);
+  }
+  uint32_t aid[kAheadSet], ab[kAheadSet];
+  p_i4 ar[kAheadSet];
+  if (na) {
+#pragma unroll
+    for (uint32_t j = 0; j < kAheadSet; ++j) {
+      aid[j] = j < na ? aset[j] : u;
+      ab[j] = ldg(m.tmask + (uint64_t)aid[j] * m.mwords + (t >> 5));
+      ar[j] = ldg4(m.M + (uint64_t)aid[j] * m.Rs + q0);
+    }
+  }
+  const p_i4 cur = ((ub >> bit) & 1u) ? ru : none;
   // every load below has a valid address, so none waits behind a branch:
   // a member reads its root's entry, a root or singleton its own
   int32_t raw[4];
@@ -338,31 +343,60 @@ __device__ inline uint64_t p_eval_tile(const CelfView& c, uint32_t u, uint32_t t
     raw[i] = ldg(m.M + (uint64_t)root[i] * m.Rs + q0 + i);
     word[i] = ld32(&c.cov[(uint64_t)root[i] * c.cwords + (q0 >> 5)]);
   }
-  uint64_t sum = 0, oa = 0, ob = 0, oab = 0;
+#pragma unroll
+  for (uint32_t b = 0; b < kSig; ++b) bins[b] = 0;
+  uint64_t sum = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const uint32_t q = q0 + i;
     const int32_t val = cur[i];
-    const uint32_t lroot = sl[i] < 0 ? last : (uint32_t)sl[i];
-    const uint32_t proot = sp[i] < 0 ? prev : (uint32_t)sp[i];
-    const uint32_t p2root = sp2[i] < 0 ? prev2 : (uint32_t)sp2[i];
-    const uint32_t droot = sd[i] < 0 ? lead : (uint32_t)sd[i];
-    const uint32_t eroot = se[i] < 0 ? second : (uint32_t)se[i];
     const bool shared = val != -1;  // a singleton holds no seed
-    const bool covered = shared && (((word[i] >> (q & 31)) & 1u) || (has_last && lroot == root[i]) ||
-                                    (has_prev && proot == root[i]) || (has_prev2 && p2root == root[i]));
-    const uint64_t size = (uint64_t)(uint32_t)(-(val < 0 ? val : raw[i]));
-    const bool counted = q < m.R && !covered && shared;
-    const bool in_a = counted && droot == root[i], in_b = counted && eroot == root[i];
-    sum += (q < m.R && !covered) ? size : 0;
-    oa += in_a ? size : 0;
-    ob += in_b ? size : 0;
-    oab += (in_a && in_b) ? size : 0;
+    bool seeded = (word[i] >> (q & 31)) & 1u;
+#pragma unroll
+    for (uint32_t j = 0; j < kUnsynced; ++j) {
+      const int32_t sv = ((sb[j] >> bit) & 1u) ? sr[j][i] : -1;
+      seeded = seeded || (j < nuns && (sv < 0 ? sid[j] : (uint32_t)sv) == root[i]);
+    }
+    const bool counted = q < m.R && !(shared && seeded);
+    const uint32_t size = (uint32_t)(-(val < 0 ? val : raw[i]));
+    sum += counted ? size : 0u;
+    if (na) {
+      uint32_t sig = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < kAheadSet; ++j) {
+        const int32_t av = ((ab[j] >> bit) & 1u) ? ar[j][i] : -1;
+        sig |= (j < na && shared && (av < 0 ? aid[j] : (uint32_t)av) == root[i]) ? 1u << j : 0u;
+      }
+#pragma unroll
+      for (uint32_t b = 0; b < kSig; ++b) bins[b] += (counted && sig == b) ? size : 0u;
+    }
   }
-  ov_a = oa;
-  ov_b = ob;
-  ov_ab = oab;
   return sum;
+}
+
+// Sums the lanes' signature bins over the wavefront: each butterfly step
+// halves the bins a lane holds (a lane keeps the upper half when its lane
+// bit is set and adds its partner's), then the groups of lanes that hold the
+// same bin are summed.  Returns the wavefront's total of bin
+// (lane >> (6 - kAheadSet)) & (kSig - 1), the same in every lane of the
+// group.  The halving steps sum at most 16 lanes (2^30 fits 32 bits); the
+// rest is summed in 64 bits.
+__device__ inline uint64_t p_bins_reduce(uint32_t (&v)[kSig], uint32_t lane) {
+#pragma unroll
+  for (uint32_t k = 0; k < kAheadSet; ++k) {
+    const uint32_t o = 32u >> k, h = kSig >> (k + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (uint32_t i = 0; i < h; ++i) {
+      const uint32_t keep = up ? v[i + h] : v[i];
+      const uint32_t give = up ? v[i] : v[i + h];
+      v[i] = keep + (uint32_t)__shfl_xor((int)give, (int)o);
+    }
+  }
+  uint64_t x = v[0];
+#pragma unroll
+  for (uint32_t o = 32u >> kAheadSet; o >= 1; o >>= 1) x += __shfl_xor(x, (int)o);
+  return x;
 }
 
 // The bulk pass visits a candidate's tiles in batches of kBulkB.  With one
@@ -936,14 +970,14 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
   const uint32_t gw = G.bi * (kPBlock / 64) + (threadIdx.x >> 6);
   const uint32_t ntiles = c.m.ntiles;
   uint32_t gen = 0, s = 0, rounds = 0, ev_round = 0, step_rebuilds = 0;
-  uint32_t last = kInvalid, prev = kInvalid, prev2 = kInvalid;  // seeds committed since the last grid barrier
+
   bool synced = true;  // a grid barrier has passed since the last commit
   uint64_t evals = 0;
   uint64_t ptiles = 0, pcols = 0;  // profiling work counts of this wavefront
   PClock clk;
   clk.start((a.prof & 1u) != 0);
   const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-  if (threadIdx.x == 0) L.lead = L.second = L.lead2 = kInvalid;
+  if (threadIdx.x == 0) L.na = L.nuns = 0;
   if (!pool_rebuild(a, G, L, s, gen, clk)) return;
   bool just_rebuilt = true;
   while (s < c.K) {
@@ -972,32 +1006,49 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         *gp(c.marginal + s) = (int64_t)(fbest >> c.B);
         st64(&c.key[id], 0ull);
       }
-      // look-ahead: every F entry came from the round led by id, which
-      // measured each one's overlap with id (ahead), or the last commit was
-      // that round's lead and id is its second (ahead2): F holds every
-      // entry's key for the step after this one
-      const bool ahead = L.lead == id;
-      const bool ahead2 = !ahead && L.lead2 == id;
-      const uint32_t second = L.second;
+      // look-ahead: F came from a round that measured every entry's gain by
+      // signature over A, and every seed since is in A; if id is in A too,
+      // F holds every entry's key for the step after this one
+      const uint32_t na = L.na;
+      uint32_t jm = kAheadSet;
+#pragma unroll
+      for (uint32_t j = 0; j < kAheadSet; ++j)
+        if (j < na && L.aset[j] == id) jm = j;
+      const bool ahead = jm < kAheadSet;
+      // A's members and one more seed can follow each other without a grid
+      // barrier: at most kUnsynced
+      const uint32_t nu = synced ? 0u : L.nuns;
+      if (nu == kUnsynced) {  // cannot happen; every workgroup decides the same
+        if (G.bi == 0 && threadIdx.x == 0) g_or(&x->err, 2u);
+        return;
+      }
       clk.lap(PClock::kCommit);
       p_lds_sync();  // the marking atomics stay in flight through the pool work
       if (threadIdx.x == 0) {  // drop the seed from F
         const uint32_t b = L.fbest;
         L.fkey[b] = L.fkey[nf - 1];
         L.fid[b] = L.fid[nf - 1];
-        if (ahead || ahead2) {  // nf <= kAheadMax here
-          L.fnext[b] = L.fnext[nf - 1];
-          L.fnext2[b] = L.fnext2[nf - 1];
+        if (ahead) {  // nf <= kAheadMax here
+#pragma unroll
+          for (uint32_t g = 0; g < kSig; ++g) L.fbin[b][g] = L.fbin[nf - 1][g];
+          L.amask |= 1u << jm;
+        } else {
+          L.na = 0;
         }
         L.nf = nf - 1;
-        L.lead = L.second = kInvalid;
-        L.lead2 = ahead ? second : kInvalid;  // fnext2 stays valid for it
+        for (uint32_t j = kUnsynced - 1; j > 0; --j) L.uns[j] = L.uns[j - 1];
+        L.uns[0] = id;
+        L.nuns = nu + 1;
       }
       p_lds_sync();
-      if (ahead || ahead2) {
+      if (ahead) {
         // the keys for the next step are exact: F stays fresh, S unchanged
+        const uint32_t mask = L.amask;
         for (uint32_t i = threadIdx.x; i + 1 < nf; i += kPBlock) {
-          const uint64_t k = ahead ? L.fnext[i] : L.fnext2[i];
+          uint64_t gain = 0;
+#pragma unroll 4
+          for (uint32_t g = 0; g < kSig; ++g) gain += (g & mask) ? 0ull : L.fbin[i][g];
+          const uint64_t k = p_make_key(c, gain, L.fid[i]);
           L.fkey[i] = k;
           if (G.bi == 0) {
             st64(&c.key[L.fid[i]], k);
@@ -1010,11 +1061,6 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       } else {
         pool_restale(L, clk);
       }
-      // up to three commits follow each other without a grid barrier (a
-      // round's lead, then its second and one more by look-ahead)
-      prev2 = synced ? kInvalid : prev;
-      prev = synced ? kInvalid : last;
-      last = id;
       synced = false;
       ++s;
       rounds = 0;
@@ -1029,13 +1075,11 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       uint32_t nc = min(want, ns - head);
       if (fbest) nc = min(nc, count_greater(L.skey + head, nc, fbest));
       nc = min(nc, kPool - nf);
-      // look-ahead when F is empty: the round also measures each candidate's
-      // overlaps with the two largest stale candidates, so that if they win
-      // the next steps, the others' keys are known exactly
+      // look-ahead when F is empty: the round also splits each candidate's
+      // gain by signature over its first kAheadSet candidates (the set A)
       const bool ahead = nf == 0 && nc <= kAheadMax;
-      const bool ahead2 = ahead && nc >= 2;
-      const uint32_t lead = L.sid[head];
-      const uint32_t second = ahead2 ? L.sid[head + 1] : kInvalid;
+      const uint32_t na = ahead ? min(nc, kAheadSet) : 0u;
+      const uint32_t nuns = L.nuns;
       uint64_t* g = x->gains[ev_round % 3];
       if (G.bi == 0) {
         uint64_t* nxt = x->gains[(ev_round + 1) % 3];
@@ -1046,17 +1090,15 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
       for (uint32_t it = gw; it < items; it += nw) {
         const uint32_t w = it / ntiles, t = it - w * ntiles;
         const uint32_t u = L.sid[head + w];
-        uint64_t oa, ob, oab;
-        const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, last, prev, prev2, ahead ? lead : u,
-                                                 ahead2 ? second : u, oa, ob, oab));
+        uint32_t bins[kSig];
+        const uint64_t part = p_wsum(p_eval_tile(c, u, t, lane, L.uns, nuns, L.sid + head, na, bins));
         if (a.prof & 2u) p_count_tile(c, u, t, lane, ptiles, pcols);
-        oa = ahead ? p_wsum(oa) : 0;
-        ob = ahead2 ? p_wsum(ob) : 0;
-        oab = ahead2 ? p_wsum(oab) : 0;
         if (lane == 0 && part) g_add64(&g[w], part);
-        if (lane == 0 && oa) g_add64(&g[kOvA + w], oa);
-        if (lane == 0 && ob) g_add64(&g[kOvB + w], ob);
-        if (lane == 0 && oab) g_add64(&g[kOvAB + w], oab);
+        if (na) {
+          const uint64_t tot = p_bins_reduce(bins, lane);
+          if ((lane & ((64u >> kAheadSet) - 1)) == 0 && tot)
+            g_add64(&g[kMaxCand + w * kSig + ((lane >> (6 - kAheadSet)) & (kSig - 1))], tot);
+        }
       }
       if (!grid_sync(x, G, gen, clk, PClock::kEval)) return;
       synced = true;  // every commit so far is visible in the coverage bitmap
@@ -1067,26 +1109,23 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
         const uint64_t k = p_make_key(c, gain, v);
         L.fkey[nf + w] = k;
         L.fid[nf + w] = v;
-        if (ahead) {
-          const uint64_t oa = ld64(&g[kOvA + w]);
-          L.fnext[w] = p_make_key(c, gain - oa, v);
-          if (ahead2) {  // gain - ov(a) - ov(b) + ov(a, b); a and b themselves go negative, kept at 0
-            const int64_t g2 = (int64_t)(gain - oa) - (int64_t)ld64(&g[kOvB + w]) + (int64_t)ld64(&g[kOvAB + w]);
-            L.fnext2[w] = p_make_key(c, g2 > 0 ? (uint64_t)g2 : 0ull, v);
-          }
-        }
         if (G.bi == 0) {
           st64(&c.key[v], k);
           st32(&c.iter[v], s);
         }
       }
+      // a look-ahead round's bins (F was empty: entry w is candidate w)
+      if (na)
+        for (uint32_t i = threadIdx.x; i < nc * kSig; i += kPBlock) L.fbin[i / kSig][i % kSig] = ld64(&g[kMaxCand + i]);
       __syncthreads();
       if (threadIdx.x == 0) {
         L.head = head + nc;
         L.nf = nf + nc;
-        L.lead = ahead ? lead : kInvalid;
-        L.second = second;
-        L.lead2 = kInvalid;  // F now holds entries without keys for two steps ahead
+        // F's bins are valid only when F is this round's candidates alone
+        L.na = na;
+        L.amask = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kAheadSet; ++j) L.aset[j] = j < na ? L.sid[head + j] : kInvalid;
       }
       __syncthreads();
       f_best(L);
@@ -1107,7 +1146,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
     }
     if (nf && step_rebuilds > 0)
       if (!bulk_eval(a, G, L, s, fbest, ptiles, pcols, gen, clk, evals)) return;
-    if (threadIdx.x == 0) L.lead = L.second = L.lead2 = kInvalid;  // the rebuilt F did not come from one round
+    if (threadIdx.x == 0) L.na = 0;  // the rebuilt F did not come from one round
     if (!pool_rebuild(a, G, L, s, gen, clk)) return;
     synced = true;
     ++step_rebuilds;
@@ -1140,7 +1179,7 @@ __device__ void run_celf(const PCelfJob& a, const Grp& G, PoolLds& L) {
 // group_blocks workgroups (trailing workgroups that make no whole group
 // return at once) and group g runs the selections g, g + groups, ... one
 // after the other.
-__global__ void __launch_bounds__(kPBlock) k_celf_persistent(const PCelfJob* __restrict__ jobs, uint32_t njobs,
+__global__ void __launch_bounds__(kPBlock, 2) k_celf_persistent(const PCelfJob* __restrict__ jobs, uint32_t njobs,
                                                             uint32_t group_blocks,
                                                             const uint32_t* __restrict__ first) {
   __shared__ PoolLds L;
