@@ -44,6 +44,18 @@ def test_c4_large_graph(gpu_ctx):
         assert [int(x) for x in seeds] == gold["seeds"]
         assert [int(x) for x in marg] == gold["marginal"]
         assert cover == gold["cover"]
+        # the same selection again with the persistent kernel's phase clock:
+        # most steps are decided by look-ahead (keys kept exact across the
+        # commits of one round's leading candidates), with the same seeds
+        gpu_ctx.set_profiling(3)
+        try:
+            gpu_ctx.reset_kernel_stats()
+            s2, m2, c2 = G.select_seeds(w.K)
+            ahead = gpu_ctx.kernel_stats("celf.lookahead_commits")[0]
+        finally:
+            gpu_ctx.set_profiling(0)
+        assert ([int(x) for x in s2], [int(x) for x in m2], c2) == (gold["seeds"], gold["marginal"], gold["cover"])
+        assert ahead >= 60, ahead
         g0 = G.gains0()
         assert int(g0.sum()) == gold["g0_sum"]
         assert gains_checksum(g0) == gold["g0_check"]
