@@ -473,8 +473,10 @@ __device__ inline void link_hubs_body(const GraphView& g, const MemoView& m, uin
 
 // k_flatten: every non-root entry of a listed tile is replaced by its root
 // (plain loads and stores only; a stale value read during the walk is an
-// older ancestor, so every walk still ends at the root).  The four columns
-// of a lane walk together, one load each per step.
+// older ancestor, so every walk still ends at the root).  A wavefront takes
+// two list entries at a time, the rows of the next two requested first; the
+// eight columns of a lane (four per entry) walk together, one load each per
+// step.
 __device__ inline void flatten_body(const MemoView& m, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
@@ -482,45 +484,57 @@ __device__ inline void flatten_body(const MemoView& m, uint32_t bid, uint32_t nb
   for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
     uint32_t cnt;
     const uint32_t ent = list_chunk(it, k0, lane, cnt);
-    // the next entry's row is requested before the current one is walked
-    uint32_t e = uni(__builtin_amdgcn_readfirstlane(ent));
-    int4 nrow = list_row(m, e, lane);
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const uint32_t ec = e;
-      const int4 cur = nrow;
-      e = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(j + 1, cnt - 1));
-      nrow = list_row(m, e, lane);
-      const uint32_t v = ec / m.ntiles, t = ec % m.ntiles;
-      int32_t* row = m.M + (uint64_t)v * m.Rs;
-      const uint32_t q0 = t * kTile + lane * kPerLane;
-      int4 out = cur;
-      int32_t* o = &out.x;
-      uint32_t c[4];
-      bool act[4];
+    uint32_t ea = uni(__builtin_amdgcn_readfirstlane(ent));
+    uint32_t eb = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(1u, cnt - 1));
+    int4 na = list_row(m, ea, lane), nb = list_row(m, eb, lane);
+    for (uint32_t j = 0; j < cnt; j += 2) {
+      const uint32_t ec[2] = {ea, eb};
+      int4 out[2] = {na, nb};
+      const bool hasb = j + 1 < cnt;
+      ea = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(j + 2, cnt - 1));
+      eb = (uint32_t)__builtin_amdgcn_readlane(ent, (int)min(j + 3, cnt - 1));
+      na = list_row(m, ea, lane);
+      nb = list_row(m, eb, lane);
+      uint32_t c[8], q0[2];
+      bool act[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        act[i] = q0 + i < m.R && o[i] >= 0;
-        c[i] = act[i] ? (uint32_t)o[i] : 0u;
-      }
-      while (act[0] || act[1] || act[2] || act[3]) {
-        int32_t p[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) p[i] = act[i] ? m.M[(uint64_t)c[i] * m.Rs + q0 + i] : -1;
+      for (int x = 0; x < 2; ++x) {
+        q0[x] = (ec[x] % m.ntiles) * kTile + lane * kPerLane;
+        const int32_t* o = &out[x].x;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          if (act[i] && p[i] >= 0) c[i] = (uint32_t)p[i];
-          else act[i] = false;
+          act[4 * x + i] = (x == 0 || hasb) && q0[x] + i < m.R && o[i] >= 0;
+          c[4 * x + i] = act[4 * x + i] ? (uint32_t)o[i] : 0u;
         }
       }
-      uint32_t changed = 0;
+      bool any = true;
+      while (any) {
+        int32_t p[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (q0 + i < m.R && o[i] >= 0 && c[i] != (uint32_t)o[i]) {
-          o[i] = (int32_t)c[i];
-          ++changed;
+        for (int k = 0; k < 8; ++k) p[k] = act[k] ? m.M[(uint64_t)c[k] * m.Rs + q0[k >> 2] + (k & 3)] : -1;
+        any = false;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (act[k] && p[k] >= 0) c[k] = (uint32_t)p[k];
+          else act[k] = false;
+          any = any || act[k];
         }
-      if (changed) *reinterpret_cast<int4*>(row + q0) = out;
-      work_add(m, kWorkRewrites, changed);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        if (x == 1 && !hasb) break;
+        const uint32_t v = ec[x] / m.ntiles;
+        int32_t* o = &out[x].x;
+        uint32_t changed = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (q0[x] + i < m.R && o[i] >= 0 && c[4 * x + i] != (uint32_t)o[i]) {
+            o[i] = (int32_t)c[4 * x + i];
+            ++changed;
+          }
+        if (changed) *reinterpret_cast<int4*>(m.M + (uint64_t)v * m.Rs + q0[x]) = out[x];
+        work_add(m, kWorkRewrites, changed);
+      }
     }
   }
 }
