@@ -660,6 +660,28 @@ __device__ inline void gain0_body(const MemoView& m, uint32_t bid, uint32_t nblk
   }
 }
 
+// Clears the coverage words a selection can read: those of the listed
+// (vertex, tile) pairs, the tile's 256 columns in 8 words.  A coverage word
+// is read only for a column whose component is not a singleton, and that
+// component's root has a candidate edge in the tile, so its pair is listed;
+// the words of unlisted pairs are never read and may hold anything.
+__device__ inline void cov_clear_body(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t bid,
+                                      uint32_t nblk) {
+  const uint32_t lane = threadIdx.x & 63;
+  __shared__ uint32_t pre[kSubLists + 1];
+  const ListIter it = list_iter(m, m.tlist, 0, pre, bid, nblk);
+  for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
+    uint32_t cnt;
+    const uint32_t ent = list_chunk(it, k0, lane, cnt);
+    if (lane < cnt) {
+      const uint32_t v = ent / m.ntiles, t = ent % m.ntiles;
+      uint4* w = reinterpret_cast<uint4*>(cov + (uint64_t)v * cwords + t * (kTile / 32));
+      w[0] = make_uint4(0u, 0u, 0u, 0u);
+      w[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+}
+
 // ---- kernels: one graph per launch, or many graphs per launch (batching) ----
 
 template <bool PER_EDGE>
@@ -684,6 +706,9 @@ __global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts)
   count_body(m, block_verts, blockIdx.x);
 }
 __global__ void __launch_bounds__(256) k_gain0(MemoView m) { gain0_body(m, blockIdx.x, gridDim.x); }
+__global__ void __launch_bounds__(256) k_cov_clear(MemoView m, uint32_t* cov, uint32_t cwords) {
+  cov_clear_body(m, cov, cwords, blockIdx.x, gridDim.x);
+}
 
 // Batched: workgroup blockIdx.x of the phase belongs to the graph found in
 // the phase's prefix sums; per-slot and uniform probabilities are chosen per
@@ -813,6 +838,10 @@ void launch_count(const MemoView& m, hipStream_t st) {
   const uint32_t bv = count_block_verts(m);
   const uint32_t vblocks = (m.n + bv - 1) / bv;
   hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m, bv);
+}
+
+void launch_cov_clear(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_cov_clear, dim3(blocks), dim3(256), 0, st, m, cov, cwords);
 }
 
 void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st) {

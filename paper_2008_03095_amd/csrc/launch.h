@@ -25,6 +25,8 @@ void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st);
 void launch_flatten(const MemoView& m, uint32_t blocks, hipStream_t st);
 void launch_count(const MemoView& m, hipStream_t st);
 void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st);
+// zeroes the coverage words of the memo's listed (vertex, tile) pairs
+void launch_cov_clear(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t blocks, hipStream_t st);
 // batched labelling: the shape of one graph's job (hook_hubs and count
 // parameters; workgroups per phase into blocks[kBatchPhases], prep excluded)
 // and one phase's launch over all jobs of b (`blocks` = the phase's total)
