@@ -71,7 +71,7 @@ static im_status batch_build(im_ctx* c, im_graph* const* graphs, const std::vect
     // X of a large R is sorted by the single-graph kernels beforehand
     J.sort_blocks = m->R <= x_sort_single_max() ? 1u : 0u;
     if (!J.sort_blocks) launch_x_sort(m->seed, m->R, m->Rs, m->scratch, m->xs, m->inv, m->pos, st);
-    J.hash_blocks = std::max(1u, std::min(65536u, (g->n + 3) / 4));
+    J.hash_blocks = std::max(1u, std::min(65536u, (g->nnz + 255) / 256));
     J.fill_words = (uint32_t)((reinterpret_cast<char*>(m->lmask) - reinterpret_cast<char*>(m->tmask)) / 4 +
                               (uint64_t)g->n * m->mwords);
     const uint32_t fill_blocks = std::min(4096u, (J.fill_words + 2047) / 2048);

@@ -66,6 +66,7 @@ struct GraphView {
   uint32_t nnz;
   const uint32_t* row_ptr;  // [n+1]
   const uint32_t* col;      // [nnz] ascending per row
+  const uint32_t* src;      // [nnz] the row of each slot
   const uint32_t* split;    // [n]  first slot of row v whose neighbour is > v
   const uint32_t* tm1;      // [nnz] per-slot T-1, or nullptr (uniform p)
   const uint32_t* hubs;     // [nhubs] vertices with more than kWave device neighbours

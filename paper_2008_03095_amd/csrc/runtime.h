@@ -195,6 +195,7 @@ struct im_graph {
   void* gbuf = nullptr;
   uint32_t* row_ptr = nullptr;
   uint32_t* col = nullptr;
+  uint32_t* src = nullptr;  // row of each slot (the edge hashes take one thread per slot)
   uint32_t* split = nullptr;
   uint32_t* tm1 = nullptr;
   uint32_t* hubs = nullptr;  // vertices with more than kWave device neighbours

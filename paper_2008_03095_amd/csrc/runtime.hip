@@ -23,6 +23,7 @@ infuse::GraphView im_graph::view() const {
   v.nnz = nnz;
   v.row_ptr = row_ptr;
   v.col = col;
+  v.src = src;
   v.split = split;
   v.tm1 = per_edge ? tm1 : nullptr;
   v.hubs = hubs;
@@ -985,6 +986,9 @@ static im_status load_graph(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t*
     split[u] = (uint32_t)(std::lower_bound(col.begin() + rp[u], col.end(), u) - col.begin());
   }
   rp[n] = (uint32_t)col.size();
+  std::vector<uint32_t> src(col.size());
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint32_t j = rp[u]; j < rp[u + 1]; ++j) src[j] = u;
   std::vector<uint32_t> hubs;
   std::vector<uint2> hub_piece;
   for (uint32_t u = 0; u < n; ++u)
@@ -1007,7 +1011,7 @@ static im_status load_graph(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t*
   g->hub_pieces = (uint32_t)hub_piece.size();
   for (uint32_t u = 0; u < n; ++u) g->nlong += rp[u + 1] - rp[u] > kSplitArcs;
   void* base = nullptr;
-  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff, &base);
+  s = ctx_alloc(c, b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff + b_col, &base);
   if (s != IM_OK) {
     delete g;
     return s;
@@ -1020,9 +1024,12 @@ static im_status load_graph(im_ctx* c, uint32_t n, uint64_t nnz, const uint64_t*
   g->tm1 = p_slot ? reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split) : nullptr;
   g->hubs = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1);
   g->hub_piece = reinterpret_cast<uint2*>(p8 + b_rp + b_col + b_split + b_tm1 + b_hubs);
+  g->src = reinterpret_cast<uint32_t*>(p8 + b_rp + b_col + b_split + b_tm1 + b_hubs + b_poff);
   hipError_t e = hipMemcpyAsync(g->row_ptr, rp.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && g->nnz)
     e = hipMemcpyAsync(g->col, col.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && g->nnz)
+    e = hipMemcpyAsync(g->src, src.data(), (size_t)g->nnz * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(g->split, split.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && p_slot && g->nnz)

@@ -13,17 +13,13 @@
 
 namespace infuse {
 
-// One wavefront per vertex row, strided over the `nblk` workgroups.
+// One thread per CSR slot (its row from g.src), strided over the `nblk`
+// workgroups: consecutive threads read and write consecutive slots.
 __device__ inline void edge_hash_body(const GraphView& g, uint32_t seed, uint2* edges, uint32_t bid, uint32_t nblk) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = (bid * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwaves = (nblk * blockDim.x) >> 6;
-  for (uint32_t u = wave; u < g.n; u += nwaves) {
-    const uint32_t beg = g.row_ptr[u], end = g.row_ptr[u + 1];
-    for (uint32_t j = beg + lane; j < end; j += kWave) {
-      const uint32_t v = g.col[j];
-      edges[j] = make_uint2(v, fmix32(seed ^ (g.directed ? arc_key32(u, v, g.n) : edge_key32(u, v, g.n))));
-    }
+  const uint32_t stride = nblk * blockDim.x;
+  for (uint32_t j = bid * blockDim.x + threadIdx.x; j < g.nnz; j += stride) {
+    const uint32_t u = g.src[j], v = g.col[j];
+    edges[j] = make_uint2(v, fmix32(seed ^ (g.directed ? arc_key32(u, v, g.n) : edge_key32(u, v, g.n))));
   }
 }
 
@@ -110,6 +106,76 @@ __global__ void __launch_bounds__(1024) k_x_sort_single(uint32_t seed, uint32_t 
   x_sort_single_body(seed, R, Rs, xs, inv, pos);
 }
 
+// R <= kCountSortMax: one workgroup of 1024 threads sorts by counting.  The
+// X values are distinct and spread evenly, so their top kCountBits bits
+// split them into buckets of about one value: count per bucket (LDS
+// atomics), scan the counts into offsets, place each simulation at its
+// bucket's next slot, then order the few values of each bucket by X.  The
+// X of a simulation is recomputed where needed instead of stored.
+constexpr uint32_t kCountBits = 13;
+constexpr uint32_t kCountSortMax = 1u << kCountBits;
+__global__ void __launch_bounds__(1024) k_x_sort_count(uint32_t seed, uint32_t R, uint32_t Rs, uint32_t* xs,
+                                                       uint32_t* inv, uint32_t* pos) {
+  constexpr uint32_t NB = kCountSortMax, kPerT = NB / 1024;
+  __shared__ uint32_t cnt[NB];   // counts, then running slots, then bucket ends
+  __shared__ uint32_t slot[NB];  // simulations in sorted order
+  __shared__ uint32_t part[1024 / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (uint32_t i = tid; i < NB; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  for (uint32_t r = tid; r < R; r += 1024) atomicAdd(&cnt[fmix32(seed + r) >> (32 - kCountBits)], 1u);
+  __syncthreads();
+  // exclusive scan: each thread its kPerT consecutive buckets, then the
+  // workgroup over the threads' sums
+  uint32_t loc[kPerT], sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPerT; ++k) {
+    loc[k] = sum;
+    sum += cnt[tid * kPerT + k];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) part[wv] = incl;
+  __syncthreads();
+  uint32_t base = 0;
+  for (uint32_t w = 0; w < wv; ++w) base += part[w];
+  base += incl - sum;
+#pragma unroll
+  for (uint32_t k = 0; k < kPerT; ++k) cnt[tid * kPerT + k] = base + loc[k];
+  __syncthreads();
+  for (uint32_t r = tid; r < R; r += 1024) slot[atomicAdd(&cnt[fmix32(seed + r) >> (32 - kCountBits)], 1u)] = r;
+  __syncthreads();
+  // cnt[b] is now the end of bucket b; insertion sort of each bucket by X
+  for (uint32_t b = tid; b < NB; b += 1024) {
+    const uint32_t beg = b ? cnt[b - 1] : 0u, end = cnt[b];
+    for (uint32_t i = beg + 1; i < end; ++i) {
+      const uint32_t r = slot[i], x = fmix32(seed + r);
+      uint32_t j = i;
+      while (j > beg && fmix32(seed + slot[j - 1]) > x) {
+        slot[j] = slot[j - 1];
+        --j;
+      }
+      slot[j] = r;
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < Rs; q += 1024) {
+    if (q < R) {
+      const uint32_t r = slot[q];
+      xs[q] = fmix32(seed + r);
+      inv[q] = r;
+      if (r < R) pos[r] = q;  // always: every simulation holds one slot
+    } else {
+      xs[q] = kInvalid;
+      inv[q] = kInvalid;
+    }
+  }
+}
+
 // Batched set-up of many memos: per graph, one workgroup sorts X (when
 // R <= kSortChunk; larger R is sorted by the single-graph kernels first),
 // the next ones hash the edges and the rest clear the mask arrays.
@@ -172,7 +238,7 @@ __global__ void k_x_pad(uint32_t R, uint32_t Rs, uint32_t* xs, uint32_t* inv) {
 }
 
 void launch_edge_hash(const GraphView& g, uint32_t seed, uint2* edges, hipStream_t st) {
-  uint32_t blocks = (g.n + 3) / 4;
+  uint32_t blocks = (g.nnz + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_edge_hash, dim3(blocks), dim3(256), 0, st, g, seed, edges);
@@ -190,6 +256,10 @@ uint32_t x_sort_scratch_elems(uint32_t R) {
 
 void launch_x_sort(uint32_t seed, uint32_t R, uint32_t Rs, uint64_t* scratch, uint32_t* xs,
                    uint32_t* inv, uint32_t* pos, hipStream_t st) {
+  if (R <= kCountSortMax) {
+    hipLaunchKernelGGL(k_x_sort_count, dim3(1), dim3(1024), 0, st, seed, R, Rs, xs, inv, pos);
+    return;
+  }
   const uint32_t nchunks = (R + kSortChunk - 1) / kSortChunk;
   if (nchunks == 1) {
     hipLaunchKernelGGL(k_x_sort_single, dim3(1), dim3(1024), 0, st, seed, R, Rs, xs, inv, pos);
