@@ -109,11 +109,13 @@ im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* see
 im_status celf_finish(im_ctx* c, const CelfBuffers* cb, uint32_t perr, const CelfState& hs,
                       const int64_t* marginal, int64_t* cover, uint64_t* evals);
 im_status normalize_set(const im_graph* g, const uint32_t* S, uint32_t len, std::vector<uint32_t>* out);
-// Enqueues sigma(S) into a scratch block of its own.  The seed ids are
-// uploaded from `src` (S.data() when null), which must stay valid until the
-// stream has passed the upload.
+// Enqueues sigma(S) into a scratch block of its own (the count at byte 0,
+// the seed ids from byte 256).  With `staged` (pinned host memory laid out
+// the same way, the count zeroed), one upload sets both; otherwise the count
+// is cleared and S.data() uploaded.  The host memory must stay valid until
+// the stream has passed the upload.
 im_status sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
-                        void** scratch, unsigned long long** dev_out, const uint32_t* src = nullptr);
+                        void** scratch, unsigned long long** dev_out, const void* staged = nullptr);
 
 // noalloc.hip: device address of the per-device scratch array of the
 // allocation-free sigma call (looked up once per device), or nullptr.

@@ -1194,7 +1194,7 @@ im_status infuse::normalize_set(const im_graph* g, const uint32_t* S, uint32_t l
 }
 
 im_status infuse::sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t>& S, hipStream_t st,
-                        void** scratch, unsigned long long** dev_out, const uint32_t* src) {
+                        void** scratch, unsigned long long** dev_out, const void* staged) {
   im_ctx* c = g->ctx;
   const uint32_t len = (uint32_t)S.size();
   const bool pair = len <= sigma_pair_max();
@@ -1208,8 +1208,12 @@ im_status infuse::sigma_enqueue(im_graph* g, Memo* m, const std::vector<uint32_t
   auto* out = reinterpret_cast<unsigned long long*>(p8);
   auto* dS = reinterpret_cast<uint32_t*>(p8 + align256(8));
   uint32_t* bm = pair ? nullptr : reinterpret_cast<uint32_t*>(p8 + align256(8) + align256((size_t)len * 4));
-  launch_fill_u32(reinterpret_cast<uint32_t*>(out), 2, 0u, st);
-  if (len) (void)hipMemcpyAsync(dS, src ? src : S.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
+  if (staged) {
+    (void)hipMemcpyAsync(base, staged, align256(8) + (size_t)len * 4, hipMemcpyHostToDevice, st);
+  } else {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(out), 2, 0u, st);
+    if (len) (void)hipMemcpyAsync(dS, S.data(), (size_t)len * 4, hipMemcpyHostToDevice, st);
+  }
   const MemoView mv = m->view(g);
   {
     KTimer t(c, "sigma", st);
@@ -1244,11 +1248,15 @@ extern "C" im_status im_estimate_sigma(im_graph* g, const uint32_t* S, uint32_t 
   if (s != IM_OK) return s;
   void* scratch = nullptr;
   unsigned long long* dout = nullptr;
-  // pinned staging: the count at 0, the seed ids from byte 256
+  // pinned staging laid out as the device block: the count (zero) at 0, the
+  // seed ids from byte 256
   size_t cap = 0;
   char* hp = static_cast<char*>(pinned_take(c, 256 + set.size() * 4, &cap));
-  if (hp) std::memcpy(hp + 256, set.data(), set.size() * 4);
-  s = sigma_enqueue(g, m, set, c->stream, &scratch, &dout, hp ? reinterpret_cast<const uint32_t*>(hp + 256) : nullptr);
+  if (hp) {
+    std::memset(hp, 0, 256);
+    std::memcpy(hp + 256, set.data(), set.size() * 4);
+  }
+  s = sigma_enqueue(g, m, set, c->stream, &scratch, &dout, hp);
   if (s == IM_OK) {
     unsigned long long hpg = 0;
     unsigned long long* h = hp ? reinterpret_cast<unsigned long long*>(hp) : &hpg;
