@@ -18,7 +18,9 @@
 //              merged by lock-free union: the larger root is linked under the
 //              smaller with compare-and-swap, so every root stays the minimum
 //              of its tree in any interleaving.  The hook parent stored in the
-//              memo stands for v, so no second scan for it is needed.
+//              memo stands for v, so no second scan for it is needed.  A
+//              wavefront queues its live (edge, column) pairs and joins them
+//              64 at a time, one per lane.
 //   k_flatten  every non-root entry is replaced by its root;
 //   k_count    each member decrements its root's -1 once: afterwards roots
 //              hold -|component| (the size memo) and members hold the label.
@@ -376,10 +378,71 @@ __device__ inline int4 list_row(const MemoView& m, uint32_t e, uint32_t lane) {
   return *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + t * kTile + lane * kPerLane);
 }
 
+// Live (candidate, column) pairs of a wavefront queued in LDS (a ring of
+// kQueue entries) and joined 64 at a time, one union per lane: a
+// candidate's live columns are a contiguous run (columns are sorted by X),
+// so unions taken per lane would leave most lanes idle while a few walk four
+// columns each.  root[c] is a vertex of the tree being joined in column c
+// (its root when last seen), shared by the lanes that join in that column.
+constexpr uint32_t kQueue = 512;
+struct PairQueue {
+  uint32_t u[kQueue];    // candidate
+  uint8_t c[kQueue];     // column within the tile
+  uint32_t root[kTile];
+};
+__device__ inline void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Columns (bits 0-3) of this lane where candidate u is live and still has to
+// be joined: v has a hook parent there (mn >= 0) and it is not u.
+__device__ inline uint32_t join_mask(const TileCtx& tc, const int32_t (&mn)[4], uint32_t u, uint32_t h, uint32_t tt) {
+  uint32_t m4 = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    m4 |= (tc.valid[i] && (h ^ tc.x[i]) <= tt && mn[i] >= 0 && (int32_t)u != mn[i]) ? 1u << i : 0u;
+  return m4;
+}
+
+// Appends the lanes' pairs of candidate u at tail (lane order); returns how
+// many the wavefront added.  Wave-uniform call.
+__device__ inline uint32_t pq_push(PairQueue& Q, uint32_t tail, uint32_t u, uint32_t m4, uint32_t lane) {
+  const uint32_t cnt = (uint32_t)__builtin_popcount(m4);
+  uint32_t incl = cnt;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+    if (lane >= off) incl += y;
+  }
+  uint32_t k = tail + incl - cnt;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if ((m4 >> i) & 1u) {
+      Q.u[k & (kQueue - 1)] = u;
+      Q.c[k & (kQueue - 1)] = (uint8_t)(lane * kPerLane + i);
+      ++k;
+    }
+  lds_wave_sync();
+  return (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+}
+
+// Joins the cnt (<= 64) pairs from head, one per lane, in tile t.
+// Wave-uniform call.
+__device__ inline void pq_run(const MemoView& m, PairQueue& Q, uint32_t head, uint32_t cnt, uint32_t t,
+                              uint32_t lane) {
+  if (lane < cnt) {
+    const uint32_t slot = (head + lane) & (kQueue - 1);
+    const uint32_t u = Q.u[slot], ci = Q.c[slot], q = t * kTile + ci;
+    const uint32_t a = find_root_halving(m.M, m.Rs, Q.root[ci], q);
+    Q.root[ci] = unite_root(m.M, m.Rs, a, u, q);
+  }
+  lds_wave_sync();
+}
+
 template <bool PER_EDGE>
 __device__ inline void link_body(const GraphView& g, const MemoView& m, uint32_t bid, uint32_t nblk) {
   const uint32_t lane = threadIdx.x & 63;
   __shared__ uint32_t pre[kSubLists + 1];
+  __shared__ PairQueue pq[4];
+  PairQueue& Q = pq[threadIdx.x >> 6];
   const ListIter it = list_iter(m, m.llist, 1, pre, bid, nblk);
   for (uint32_t idx = it.first; idx < it.total; idx += it.stride) {
     const uint32_t e = uni(it.at(idx));
@@ -400,24 +463,17 @@ __device__ inline void link_body(const GraphView& g, const MemoView& m, uint32_t
     // means v has no live smaller neighbour in that column.
     const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
     const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
-    // root of v's tree per column, looked up when the first further live
-    // smaller neighbour needs joining
-    uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
-    uint32_t tries = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Q.root[lane * kPerLane + i] = (uint32_t)mn[i];  // read only where mn >= 0
+    lds_wave_sync();
+    uint32_t head = 0, tail = 0;
     for_candidates<PER_EDGE, true>(g, m, v, beg, end, split, lane, true, rcol, rh, rtm1, tc,
                                    [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
-#pragma unroll
-                                     for (int i = 0; i < 4; ++i) {
-                                       const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
-                                       if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
-                                         ++tries;
-                                         if (rv[i] == kInvalid)
-                                           rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
-                                         rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
-                                       }
-                                     }
+                                     tail += pq_push(Q, tail, u, join_mask(tc, mn, u, h, tt), lane);
+                                     for (; tail - head >= 64; head += 64) pq_run(m, Q, head, 64, t, lane);
                                    });
-    work_add(m, kWorkUnions, tries);
+    for (; tail != head; head += min(64u, tail - head)) pq_run(m, Q, head, min(64u, tail - head), t, lane);
+    work_add(m, kWorkUnions, lane == 0 ? tail : 0u);
   }
 }
 
@@ -427,6 +483,7 @@ __device__ inline void link_body(const GraphView& g, const MemoView& m, uint32_t
 // first slot.
 template <bool PER_EDGE>
 __device__ inline void link_hubs_body(const GraphView& g, const MemoView& m, uint32_t bid) {
+  __shared__ PairQueue pq[4];
   const uint64_t wid = (uint64_t)bid * 4 + (threadIdx.x >> 6);
   const uint32_t pg = uni((uint32_t)(wid / m.ntiles)), t = uni((uint32_t)(wid % m.ntiles));
   if (pg >= g.hub_pieces) return;
@@ -434,39 +491,35 @@ __device__ inline void link_hubs_body(const GraphView& g, const MemoView& m, uin
   const uint32_t v = uni(pc.x);
   if (!((m.lmask[(uint64_t)v * m.mwords + (t >> 5)] >> (t & 31)) & 1u)) return;
   const uint32_t lane = threadIdx.x & 63;
+  PairQueue& Q = pq[threadIdx.x >> 6];
   const uint32_t pbeg = uni(pc.y);
   const uint32_t pend = min(pbeg + kHubPiece, uni(g.split[v]));  // smaller neighbours only
   TileCtx tc;
   tile_from_x(m, t, lane, load_tile_x(m, t, lane), m.kshift, tc, PER_EDGE);
   const int4 hp = *reinterpret_cast<const int4*>(m.M + (uint64_t)v * m.Rs + tc.q0);
   const int32_t mn[4] = {hp.x, hp.y, hp.z, hp.w};
-  uint32_t rv[4] = {kInvalid, kInvalid, kInvalid, kInvalid};
-  uint32_t tries = 0;
-  for (uint32_t beg = pbeg; beg < pend; beg += kWave) {
-  const uint32_t end = min(beg + (uint32_t)kWave, pend);
-  uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
-  if (beg + lane < end) {
-    const uint2 ed = m.edges[beg + lane];
-    rcol = ed.x;
-    rh = ed.y;
-    if (PER_EDGE) rtm1 = g.tm1[beg + lane];
-  }
-  for_candidates<PER_EDGE, true>(g, m, v, beg, end, end, lane, true, rcol, rh, rtm1, tc,
-                                 [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
 #pragma unroll
-                                   for (int i = 0; i < 4; ++i) {
-                                     const bool live = tc.valid[i] && (h ^ tc.x[i]) <= tt;
-                                     if (live && mn[i] >= 0 && (int32_t)u != mn[i]) {
-                                       ++tries;
-                                       if (rv[i] == kInvalid)
-                                         rv[i] = find_root_halving(m.M, m.Rs, (uint32_t)mn[i], tc.q0 + i);
-                                       rv[i] = unite_root(m.M, m.Rs, rv[i], u, tc.q0 + i);
-                                     }
-                                   }
-                                 });
+  for (int i = 0; i < 4; ++i) Q.root[lane * kPerLane + i] = (uint32_t)mn[i];  // read only where mn >= 0
+  lds_wave_sync();
+  uint32_t head = 0, tail = 0;
+  for (uint32_t beg = pbeg; beg < pend; beg += kWave) {
+    const uint32_t end = min(beg + (uint32_t)kWave, pend);
+    uint32_t rcol = kInvalid, rh = 0, rtm1 = 0;
+    if (beg + lane < end) {
+      const uint2 ed = m.edges[beg + lane];
+      rcol = ed.x;
+      rh = ed.y;
+      if (PER_EDGE) rtm1 = g.tm1[beg + lane];
+    }
+    for_candidates<PER_EDGE, true>(g, m, v, beg, end, end, lane, true, rcol, rh, rtm1, tc,
+                                   [&](uint32_t u, uint32_t h, uint32_t tt, bool) {
+                                     tail += pq_push(Q, tail, u, join_mask(tc, mn, u, h, tt), lane);
+                                     for (; tail - head >= 64; head += 64) pq_run(m, Q, head, 64, t, lane);
+                                   });
   }
+  for (; tail != head; head += min(64u, tail - head)) pq_run(m, Q, head, min(64u, tail - head), t, lane);
   if (m.work) {
-    work_add(m, kWorkUnions, tries);
+    work_add(m, kWorkUnions, lane == 0 ? tail : 0u);
     work_add(m, kWorkHubLinkWaves, lane == 0 ? 1u : 0u);
   }
 }
