@@ -313,15 +313,24 @@ def batch_select(ctx: Context, graphs: Sequence[Graph], Ks: Sequence[int]):
     """im_batch_select: every graph's memo and selection in batched launches."""
     lib = ctx._lib
     ng = len(graphs)
-    seeds = [np.zeros(max(int(k), 1), dtype=np.uint32) for k in Ks]
-    margs = [np.zeros(max(int(k), 1), dtype=np.int64) for k in Ks]
-    hv = (C.c_void_p * ng)(*[g.handle.value for g in graphs])
-    kv = (C.c_uint32 * ng)(*[int(k) for k in Ks])
-    sp = (C.POINTER(C.c_uint32) * ng)(*[s.ctypes.data_as(C.POINTER(C.c_uint32)) for s in seeds])
-    mp = (C.POINTER(C.c_int64) * ng)(*[m.ctypes.data_as(C.POINTER(C.c_int64)) for m in margs])
-    cov = (C.c_int64 * ng)()
-    check(lib.im_batch_select(ctx.handle, ng, hv, kv, sp, mp, cov))
-    return [(seeds[i][:Ks[i]], margs[i][:Ks[i]], int(cov[i])) for i in range(ng)]
+    kv = np.ascontiguousarray(np.asarray(Ks, dtype=np.uint32).reshape(-1))
+    kmax = max(1, int(kv.max())) if ng else 1
+    # one block per output kind, row i for graph i; the pointer tables are
+    # built with numpy (a ctypes object per graph would cost more than the
+    # call's device work for many small graphs)
+    seeds = np.zeros((ng, kmax), dtype=np.uint32)
+    margs = np.zeros((ng, kmax), dtype=np.int64)
+    rows = np.arange(ng, dtype=np.uint64)
+    sp = np.uint64(seeds.ctypes.data) + rows * np.uint64(seeds.strides[0])
+    mp = np.uint64(margs.ctypes.data) + rows * np.uint64(margs.strides[0])
+    hv = np.array([g.handle.value for g in graphs], dtype=np.uint64)
+    cov = np.zeros(ng, dtype=np.int64)
+    check(lib.im_batch_select(ctx.handle, ng, hv.ctypes.data_as(C.POINTER(C.c_void_p)),
+                              kv.ctypes.data_as(C.POINTER(C.c_uint32)),
+                              sp.ctypes.data_as(C.POINTER(C.POINTER(C.c_uint32))),
+                              mp.ctypes.data_as(C.POINTER(C.POINTER(C.c_int64))),
+                              cov.ctypes.data_as(C.POINTER(C.c_int64))))
+    return [(seeds[i, :kv[i]], margs[i, :kv[i]], int(cov[i])) for i in range(ng)]
 
 
 class Server:
