@@ -33,7 +33,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "celf_persistent_c4_traffic.txt")
 ROOF_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("celf_persistent.hip", "common.h")]
 # the labelling kernels of the memo construction (components phase)
 CC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cc_kernels_c4_traffic.txt")
-CC_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("cc.hip", "tile.h", "common.h")]
+CC_SOURCES = [os.path.join(ROOT, "paper_2008_03095_amd", "csrc", f) for f in ("cc.hip", "lists.h", "tile.h", "common.h")]
 CC_KERNELS = ("hook", "hook_hubs", "lists", "link", "link_hubs", "flatten", "count")
 # the memo-free search (directed workload): level kernel and its sources
 BFS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bfs_level_d1_traffic.txt")

@@ -38,6 +38,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "lists.h"
 #include "tile.h"
 
 namespace infuse {
@@ -315,61 +316,6 @@ __device__ inline uint32_t unite_root(int32_t* M, uint32_t Rs, uint32_t a, uint3
     b = find_root_halving(M, Rs, b, q, a);
   }
   return a;
-}
-
-// Wavefront iteration over the concatenation of the kSubLists sub-lists of a
-// work list: every wavefront of the grid strides over all entries (so the
-// heavy tiles of hub vertices spread over the whole grid).  The sub-list
-// sizes are prefix-summed in LDS by each workgroup (blockDim.x == 256 ==
-// kSubLists) and an entry's sub-list found by binary search.
-struct ListIter {
-  const uint32_t* list;
-  const uint32_t* pre;  // LDS, kSubLists + 1 prefix sums
-  uint32_t cap, total, first, stride;
-  __device__ uint32_t at(uint32_t idx) const {
-    uint32_t lo = 0, hi = kSubLists;  // pre[lo] <= idx < pre[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (pre[mid] <= idx) lo = mid; else hi = mid;
-    }
-    return list[(uint64_t)lo * cap + (idx - pre[lo])];
-  }
-};
-__device__ inline ListIter list_iter(const MemoView& m, const uint32_t* base, int which, uint32_t* pre,
-                                     uint32_t bid, uint32_t nblk) {
-  static_assert(kSubLists == 256, "one prefix element per thread of a 256-thread workgroup");
-  const uint32_t tid = threadIdx.x;
-  uint32_t x = m.counts[2 * tid + which];
-  pre[tid + 1] = x;
-  if (tid == 0) pre[0] = 0;
-  __syncthreads();
-  for (uint32_t off = 1; off < kSubLists; off <<= 1) {
-    const uint32_t y = tid + 1 > off ? pre[tid + 1 - off] : 0u;
-    __syncthreads();
-    x += y;
-    pre[tid + 1] = x;
-    __syncthreads();
-  }
-  ListIter it;
-  it.list = base;
-  it.pre = pre;
-  it.cap = m.list_cap;
-  it.total = uni(pre[kSubLists]);
-  it.first = uni(bid * (blockDim.x >> 6) + (threadIdx.x >> 6));
-  it.stride = nblk * (blockDim.x >> 6);
-  return it;
-}
-
-// A wavefront's entries of a work list, 64 at a time: the entries of the
-// wavefront are first + k * stride (k = 0, 1, ...); lane l resolves entry
-// k0 + l of them.  `count` receives how many of the 64 exist (a prefix of
-// the lanes).  One load brings 64 entries, so the per-entry work that
-// follows does not wait for the list.
-__device__ inline uint32_t list_chunk(const ListIter& it, uint32_t k0, uint32_t lane, uint32_t& count) {
-  const uint64_t idx = (uint64_t)it.first + (uint64_t)(k0 + lane) * it.stride;
-  const bool ok = idx < it.total;
-  count = (uint32_t)__popcll(__ballot(ok));
-  return ok ? it.at((uint32_t)idx) : 0u;
 }
 
 // Row words of entry e (vertex e / ntiles, tile e % ntiles) for this lane.
@@ -713,28 +659,6 @@ __device__ inline void gain0_body(const MemoView& m, uint32_t bid, uint32_t nblk
   }
 }
 
-// Clears the coverage words a selection can read: those of the listed
-// (vertex, tile) pairs, the tile's 256 columns in 8 words.  A coverage word
-// is read only for a column whose component is not a singleton, and that
-// component's root has a candidate edge in the tile, so its pair is listed;
-// the words of unlisted pairs are never read and may hold anything.
-__device__ inline void cov_clear_body(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t bid,
-                                      uint32_t nblk) {
-  const uint32_t lane = threadIdx.x & 63;
-  __shared__ uint32_t pre[kSubLists + 1];
-  const ListIter it = list_iter(m, m.tlist, 0, pre, bid, nblk);
-  for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
-    uint32_t cnt;
-    const uint32_t ent = list_chunk(it, k0, lane, cnt);
-    if (lane < cnt) {
-      const uint32_t v = ent / m.ntiles, t = ent % m.ntiles;
-      uint4* w = reinterpret_cast<uint4*>(cov + (uint64_t)v * cwords + t * (kTile / 32));
-      w[0] = make_uint4(0u, 0u, 0u, 0u);
-      w[1] = make_uint4(0u, 0u, 0u, 0u);
-    }
-  }
-}
-
 // ---- kernels: one graph per launch, or many graphs per launch (batching) ----
 
 template <bool PER_EDGE>
@@ -759,9 +683,6 @@ __global__ void __launch_bounds__(256) k_count(MemoView m, uint32_t block_verts)
   count_body(m, block_verts, blockIdx.x);
 }
 __global__ void __launch_bounds__(256) k_gain0(MemoView m) { gain0_body(m, blockIdx.x, gridDim.x); }
-__global__ void __launch_bounds__(256) k_cov_clear(MemoView m, uint32_t* cov, uint32_t cwords) {
-  cov_clear_body(m, cov, cwords, blockIdx.x, gridDim.x);
-}
 
 // Batched: workgroup blockIdx.x of the phase belongs to the graph found in
 // the phase's prefix sums; per-slot and uniform probabilities are chosen per
@@ -891,10 +812,6 @@ void launch_count(const MemoView& m, hipStream_t st) {
   const uint32_t bv = count_block_verts(m);
   const uint32_t vblocks = (m.n + bv - 1) / bv;
   hipLaunchKernelGGL(k_count, dim3(vblocks * m.ntiles), dim3(256), 0, st, m, bv);
-}
-
-void launch_cov_clear(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_cov_clear, dim3(blocks), dim3(256), 0, st, m, cov, cwords);
 }
 
 void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st) {

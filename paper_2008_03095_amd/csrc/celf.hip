@@ -19,11 +19,14 @@
 // fresh and larger than every stale key, hence it is the lowest-id maximiser
 // of the exact gains, the same vertex plain greedy and the sequential CELF
 // queue pick.
+#include <cstring>
+
 #include "common.h"
+#include "launch.h"
+#include "lists.h"
 
 namespace infuse {
 
-__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Cross-block hand-off inside a kernel.  Data another block reads later in
 // the same kernel is written with atomics or write-through (agent-scope)
@@ -384,7 +387,48 @@ __device__ inline void celf_init_at(const CelfView& c, uint64_t i) {
   }
 }
 
-__global__ void k_celf_init(CelfView c) { celf_init_at(c, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+// Clears the coverage words a selection can read: those of the listed
+// (vertex, tile) pairs, the tile's 256 columns in 8 words.  A coverage word
+// is read only for a column whose component is not a singleton, and that
+// component's root has a candidate edge in the tile, so its pair is listed;
+// the words of unlisted pairs are never read and may hold anything.
+__device__ inline void cov_clear_body(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t bid,
+                                      uint32_t nblk) {
+  const uint32_t lane = threadIdx.x & 63;
+  __shared__ uint32_t pre[kSubLists + 1];
+  const ListIter it = list_iter(m, m.tlist, 0, pre, bid, nblk);
+  for (uint32_t k0 = 0; (uint64_t)it.first + (uint64_t)k0 * it.stride < it.total; k0 += 64) {
+    uint32_t cnt;
+    const uint32_t ent = list_chunk(it, k0, lane, cnt);
+    if (lane < cnt) {
+      const uint32_t v = ent / m.ntiles, t = ent % m.ntiles;
+      uint4* w = reinterpret_cast<uint4*>(cov + (uint64_t)v * cwords + t * (kTile / 32));
+      w[0] = make_uint4(0u, 0u, 0u, 0u);
+      w[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+}
+
+// Set-up of one selection in one launch: cov_blocks workgroups clear the
+// coverage words of the listed tiles, init_blocks set the keys, and the last
+// one clears the persistent kernel's state and writes its job description
+// (passed by value, so no separate upload), or nothing when pjob is null.
+__global__ void __launch_bounds__(256) k_celf_setup(CelfView c, uint32_t cov_blocks, uint32_t init_blocks,
+                                                    uint32_t* pscratch, uint32_t scratch_words, JobWords job,
+                                                    uint32_t* pjob) {
+  if (blockIdx.x < cov_blocks) {
+    cov_clear_body(c.m, c.cov, c.cwords, blockIdx.x, cov_blocks);
+    return;
+  }
+  const uint32_t b = blockIdx.x - cov_blocks;
+  if (b < init_blocks) {
+    celf_init_at(c, (uint64_t)b * blockDim.x + threadIdx.x);
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < scratch_words; i += blockDim.x) pscratch[i] = 0u;
+  if (pjob)
+    for (uint32_t i = threadIdx.x; i < kJobWords; i += blockDim.x) pjob[i] = job.w[i];
+}
 
 // Set-up of many selections in one launch: per selection (found by binary
 // search in the prefix sums `first` of its workgroups), cov_blocks
@@ -445,8 +489,14 @@ void launch_celf_collect_batch(const CelfBatchJob* jobs, uint32_t njobs, unsigne
   if (njobs) hipLaunchKernelGGL(k_celf_collect_batch, dim3(njobs), dim3(256), 0, st, jobs, out);
 }
 
-void launch_celf_init(const CelfView& c, hipStream_t st) {
-  hipLaunchKernelGGL(k_celf_init, dim3((c.m.n + 255) / 256), dim3(256), 0, st, c);
+void launch_celf_setup(const CelfView& c, uint32_t* pscratch, uint32_t scratch_words, const void* job,
+                       void* pjob, hipStream_t st) {
+  constexpr uint32_t cov_blocks = 1024;  // list walkers: light work per entry
+  const uint32_t init_blocks = (c.m.n + 255) / 256;
+  JobWords jw = {};
+  if (job) std::memcpy(jw.w, job, sizeof(jw.w));
+  hipLaunchKernelGGL(k_celf_setup, dim3(cov_blocks + init_blocks + 1), dim3(256), 0, st, c, cov_blocks,
+                     init_blocks, pscratch, scratch_words, jw, job ? static_cast<uint32_t*>(pjob) : nullptr);
 }
 
 void launch_celf_topw(const CelfView& c, hipStream_t st) {

@@ -25,8 +25,7 @@ void launch_link_hubs(const GraphView& g, const MemoView& m, hipStream_t st);
 void launch_flatten(const MemoView& m, uint32_t blocks, hipStream_t st);
 void launch_count(const MemoView& m, hipStream_t st);
 void launch_gain0(const MemoView& m, uint32_t blocks, hipStream_t st);
-// zeroes the coverage words of the memo's listed (vertex, tile) pairs
-void launch_cov_clear(const MemoView& m, uint32_t* cov, uint32_t cwords, uint32_t blocks, hipStream_t st);
+
 // batched labelling: the shape of one graph's job (hook_hubs and count
 // parameters; workgroups per phase into blocks[kBatchPhases], prep excluded)
 // and one phase's launch over all jobs of b (`blocks` = the phase's total)
@@ -36,7 +35,17 @@ void launch_build_batch(const BuildBatch& b, uint32_t phase, uint32_t blocks, hi
 
 // celf.hip
 uint32_t celf_topw_blocks(uint32_t n);
-void launch_celf_init(const CelfView& c, hipStream_t st);
+// A persistent job description as kernel-argument words (at most 512 bytes).
+constexpr uint32_t kJobWords = 128;
+struct JobWords {
+  uint32_t w[kJobWords];
+};
+// Set-up of one selection in one launch: coverage words of the listed tiles
+// cleared, keys from the initial gains, the persistent kernel's state
+// cleared and, with `job` (host memory of kJobWords words), its description
+// written to `pjob`.
+void launch_celf_setup(const CelfView& c, uint32_t* pscratch, uint32_t scratch_words, const void* job,
+                       void* pjob, hipStream_t st);
 void launch_celf_step(const CelfView& c, uint32_t bulk_blocks, hipStream_t st);
 void launch_celf_topw(const CelfView& c, hipStream_t st);
 void launch_celf_eval(const CelfView& c, hipStream_t st);

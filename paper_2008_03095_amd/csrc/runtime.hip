@@ -571,13 +571,11 @@ im_status celf_alloc(im_graph* g, const Memo* m, uint32_t K, uint32_t W, CelfBuf
 }
 
 // Clears the coverage bitmap (the words of listed tiles: the others are
-// never read; 1,024 workgroups walk the tile list, which is light work per
-// entry) and the state of a selection.
-static void celf_prepare(CelfBuffers* cb, hipStream_t st) {
-  const CelfView& v = cb->v;
-  launch_cov_clear(v.m, v.cov, v.cwords, 1024, st);
-  launch_celf_init(v, st);
-  launch_fill_u32(static_cast<uint32_t*>(cb->pscratch), pcelf_scratch_bytes() / 4, 0u, st);
+// never read) and the state of a selection, and with `job` writes the
+// persistent kernel's description, in one launch.
+static void celf_prepare(CelfBuffers* cb, const void* job, hipStream_t st) {
+  launch_celf_setup(cb->v, static_cast<uint32_t*>(cb->pscratch), (uint32_t)(pcelf_scratch_bytes() / 4), job,
+                    cb->pjob, st);
 }
 
 // One persistent launch over `njobs` selections (device descriptions).
@@ -628,12 +626,13 @@ bool celf_launch_persistent(im_ctx* c, const void* jobs, uint32_t njobs, uint32_
 }
 
 void celf_enqueue(im_ctx* c, CelfBuffers* cb, hipStream_t st, bool persistent_ok) {
-  celf_prepare(cb, st);
-  if (persistent_ok && c->tune.celf_mode == 1 && c->coop_grid) {
+  const bool persistent = persistent_ok && c->tune.celf_mode == 1 && c->coop_grid;
+  if (persistent)
     pcelf_fill_job(cb->hjob, cb->v, cb->pscratch, cb->blist, c->coop_grid, c->tune.celf_round0,
                    pcelf_prof_bits(c));
-    if (hipMemcpyAsync(cb->pjob, cb->hjob, pcelf_job_bytes(), hipMemcpyHostToDevice, st) == hipSuccess &&
-        celf_launch_persistent(c, cb->pjob, 1, c->coop_grid, nullptr, st)) {
+  celf_prepare(cb, persistent ? cb->hjob : nullptr, st);
+  if (persistent) {
+    if (celf_launch_persistent(c, cb->pjob, 1, c->coop_grid, nullptr, st)) {
       cb->persistent = true;
       return;
     }
