@@ -714,39 +714,37 @@ static void celf_steps_direct(im_ctx* c, CelfBuffers* cb, hipStream_t st) {
 im_status celf_collect(im_ctx* c, CelfBuffers* cb, hipStream_t st, uint32_t* seeds,
                        int64_t* marginal, int64_t* cover, uint64_t* evals) {
   const CelfView& v = cb->v;
-  // one pinned record {error flag of the persistent kernel, state, seeds,
-  // marginals}: the four copies are queued together and the call waits once
-  const size_t o_st = 256, o_seeds = o_st + align256(sizeof(CelfState)),
-               o_marg = o_seeds + align256((size_t)v.K * 4);
+  // seeds, marginals, the state and the persistent kernel's scratch (its
+  // error word first; cleared at set-up, so 0 for the per-step kernels) lie
+  // in this order in one allocation: one copy into a pinned record, one wait
+  const char* d0 = reinterpret_cast<const char*>(v.seeds);
+  const size_t o_marg = reinterpret_cast<const char*>(v.marginal) - d0,
+               o_st = reinterpret_cast<const char*>(v.st) - d0,
+               o_err = static_cast<const char*>(cb->pscratch) + pcelf_err_offset() - d0,
+               span = o_err + sizeof(uint32_t);
   size_t cap = 0;
-  char* h = static_cast<char*>(pinned_take(c, o_marg + (size_t)v.K * 8, &cap));
-  uint32_t perr_pg = 0;
-  CelfState hs_pg;
-  uint32_t* perr = h ? reinterpret_cast<uint32_t*>(h) : &perr_pg;
-  CelfState* hs = h ? reinterpret_cast<CelfState*>(h + o_st) : &hs_pg;
-  uint32_t* hseeds = h ? reinterpret_cast<uint32_t*>(h + o_seeds) : seeds;
-  int64_t* hmarg = h ? reinterpret_cast<int64_t*>(h + o_marg) : marginal;
-  *perr = 0;
-  hipError_t e = hipSuccess;
-  if (cb->persistent)
-    e = hipMemcpyAsync(perr, static_cast<char*>(cb->pscratch) + pcelf_err_offset(), sizeof(uint32_t),
-                       hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hseeds, v.seeds, (size_t)v.K * 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hmarg, v.marginal, (size_t)v.K * 8, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hs, v.st, sizeof(CelfState), hipMemcpyDeviceToHost, st);
-  const hipError_t es = hipStreamSynchronize(st);  // also when a copy failed: h is reused
+  char* h = static_cast<char*>(pinned_take(c, span, &cap));
+  std::vector<char> pageable;
+  if (!h) {
+    pageable.resize(span);
+    h = pageable.data();
+  }
+  hipError_t e = hipMemcpyAsync(h, d0, span, hipMemcpyDeviceToHost, st);
+  const hipError_t es = hipStreamSynchronize(st);  // also when the copy failed: h is reused
   if (e == hipSuccess) e = es;
   im_status s;
   if (e != hipSuccess) {
     s = fail(IM_ERR_DEVICE, "CELF failed on the device: %s", hipGetErrorString(e));
   } else {
-    if (h) {
-      std::memcpy(seeds, hseeds, (size_t)v.K * 4);
-      std::memcpy(marginal, hmarg, (size_t)v.K * 8);
-    }
-    s = celf_finish(c, cb, *perr, *hs, marginal, cover, evals);
+    uint32_t perr;
+    CelfState hs;
+    std::memcpy(&perr, h + o_err, sizeof(perr));
+    std::memcpy(&hs, h + o_st, sizeof(hs));
+    std::memcpy(seeds, h, (size_t)v.K * 4);
+    std::memcpy(marginal, h + o_marg, (size_t)v.K * 8);
+    s = celf_finish(c, cb, perr, hs, marginal, cover, evals);
   }
-  pinned_give(c, h, cap);
+  if (pageable.empty()) pinned_give(c, h, cap);
   return s;
 }
 
