@@ -15,30 +15,32 @@ __device__ inline uint64_t wave_sum_u64q(uint64_t x) {
   return x;
 }
 
-// A workgroup per 64 columns; its four wavefronts split the seeds.  First
-// each (seed, column) gets its label and component size, the loads of a
-// wavefront's seeds issued together; then a seed's component counts unless
-// an earlier seed of the list has the same label in that column.  S holds
-// distinct ids (the callers deduplicate it), so a singleton seed shares its
-// component with no other seed; a shared label is usually met early, since
-// the seeds of one large component share its root.
-constexpr int kSigmaBatch = 8;
+// A workgroup per 16 columns: lane l of the workgroup takes column l % 16
+// and the seeds j = l / 16 + 16 k, so the loads of all its (at most 128)
+// seeds are issued in one batch per lane (8 seeds) and a launch has R / 16
+// workgroups.  Each (seed, column) gets its label and component size; then a
+// seed's component counts unless an earlier seed of the list has the same
+// label in that column.  S holds distinct ids (the callers deduplicate it),
+// so a singleton seed shares its component with no other seed.
+constexpr int kSigmaCols = 16;
+constexpr int kSigmaBatch = kSigmaPairMax / (256 / kSigmaCols);
 __global__ void __launch_bounds__(256) k_sigma_pair(MemoView m, const uint32_t* S, uint32_t len,
                                                     unsigned long long* out) {
-  __shared__ uint32_t roots[kSigmaPairMax][64];
-  __shared__ int32_t sizes[kSigmaPairMax][64];
+  __shared__ uint32_t roots[kSigmaPairMax][kSigmaCols];
+  __shared__ int32_t sizes[kSigmaPairMax][kSigmaCols];
   __shared__ unsigned long long part[4];
-  const uint32_t c = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t q = blockIdx.x * 64 + c;
+  constexpr uint32_t kSlots = 256 / kSigmaCols;
+  const uint32_t c = threadIdx.x % kSigmaCols, sl = threadIdx.x / kSigmaCols, w = threadIdx.x >> 6;
+  const uint32_t q = blockIdx.x * kSigmaCols + c;
   const uint32_t qq = q < m.R ? q : m.R - 1;  // in range; the count skips q >= R
   const uint32_t t = qq / kTile;
-  for (uint32_t j0 = w * kSigmaBatch; j0 < len; j0 += 4 * kSigmaBatch) {
+  if (sl < len) {  // len <= kSigmaPairMax = kSlots * kSigmaBatch: one batch
     uint32_t s[kSigmaBatch];
     int32_t raw[kSigmaBatch];
     uint32_t tw[kSigmaBatch];
 #pragma unroll
     for (int k = 0; k < kSigmaBatch; ++k) {
-      s[k] = S[min(j0 + k, len - 1)];
+      s[k] = S[min(sl + kSlots * k, len - 1)];
       raw[k] = m.M[(uint64_t)s[k] * m.Rs + qq];
       tw[k] = m.tmask[(uint64_t)s[k] * m.mwords + (t >> 5)];
     }
@@ -50,7 +52,7 @@ __global__ void __launch_bounds__(256) k_sigma_pair(MemoView m, const uint32_t* 
     }
 #pragma unroll
     for (int k = 0; k < kSigmaBatch; ++k) {
-      const uint32_t j = j0 + k;
+      const uint32_t j = sl + kSlots * k;
       if (j < len) {
         roots[j][c] = val[k] < 0 ? s[k] : (uint32_t)val[k];
         sizes[j][c] = val[k] == -1 ? 0 : (val[k] < 0 ? -val[k] : -gsz[k]);  // 0 marks a singleton
@@ -60,7 +62,7 @@ __global__ void __launch_bounds__(256) k_sigma_pair(MemoView m, const uint32_t* 
   __syncthreads();
   uint64_t cnt = 0;
   if (q < m.R) {
-    for (uint32_t j = w; j < len; j += 4) {
+    for (uint32_t j = sl; j < len; j += kSlots) {
       const int32_t sz = sizes[j][c];
       if (sz == 0) {  // a singleton seed: its own component, of size 1
         cnt += 1;
@@ -77,7 +79,7 @@ __global__ void __launch_bounds__(256) k_sigma_pair(MemoView m, const uint32_t* 
     }
   }
   cnt = wave_sum_u64q(cnt);
-  if (c == 0) part[w] = cnt;
+  if ((threadIdx.x & 63) == 0) part[w] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
@@ -129,7 +131,7 @@ uint32_t sigma_pair_max() { return kSigmaPairMax; }
 
 void launch_sigma_pair(const MemoView& m, const uint32_t* S, uint32_t len, unsigned long long* out,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_sigma_pair, dim3((m.R + 63) / 64), dim3(256), 0, st, m, S, len, out);
+  hipLaunchKernelGGL(k_sigma_pair, dim3((m.R + kSigmaCols - 1) / kSigmaCols), dim3(256), 0, st, m, S, len, out);
 }
 
 void launch_sigma_bitmap(const MemoView& m, const uint32_t* S, uint32_t len, uint32_t* bm,
